@@ -1,0 +1,310 @@
+"""Checks that pin the FP64 oracle to what the mathematics fixes.
+
+Each function takes a loaded oracle library (so that the mutation test can
+run the same checks against deliberately broken copies) and returns
+``(ok, detail)``.  None of them re-types the oracle's formulas: they test
+invariants (anti-Hermiticity, gauge covariance, parity structure), closed
+forms (free-field plane waves), library routines (dense LAPACK solves) and
+hand-derived storage-format vectors.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2302_09224_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+C1, C3 = 1.0, -1.0 / 24.0
+
+
+# ---------------------------------------------------------------------------
+# small helpers (geometry only)
+# ---------------------------------------------------------------------------
+
+def links(dims, kind="haar", seed=inputs.GAUGE_SEED):
+    f, l = inputs.make_links(dims, kind, seed)
+    return f.numpy(), l.numpy()
+
+
+def spinor(V, seed):
+    return inputs.gaussian_spinor(V, seed).numpy()
+
+
+def coords(dims):
+    return [c.numpy() for c in inputs.coords(dims)]
+
+
+def shifted_site(dims, mu, hop):
+    """lexicographic index of x + hop*mu for every site x (periodic)"""
+    c = coords(dims)
+    c[mu] = (c[mu] + hop) % dims[mu]
+    X, Y, Z, T = dims
+    return ((c[3] * Z + c[2]) * Y + c[1]) * X + c[0]
+
+
+def plane_wave(dims, n, v):
+    """e^{i p.x} v with p_mu = 2 pi n_mu / L_mu (t: 2 pi (n_t + 1/2) / L_t)"""
+    c = coords(dims)
+    p = [2 * np.pi * n[m] / dims[m] for m in range(3)] + [2 * np.pi * (n[3] + 0.5) / dims[3]]
+    phase = np.exp(1j * sum(p[m] * c[m] for m in range(4)))
+    return phase[:, None] * np.asarray(v)[None, :], p
+
+
+def staggered_eta(dims):
+    x, y, z, t = coords(dims)
+    return [np.ones_like(x), (-1.0) ** x, (-1.0) ** (x + y), (-1.0) ** (x + y + z)]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(np.ravel(b))
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / (nb if nb > 0 else 1.0)
+
+
+def dense_normal(fat, lng, dims, mass, shift=0.0, parity=0, lib=None):
+    """dense matrix of A = 4m^2 + shift - D_pq D_qp on the sites of parity p,
+    assembled column by column from oracle applications"""
+    sites = oracle.parity_sites(dims, parity)
+    n = 3 * sites.size
+    A = np.zeros((n, n), dtype=np.complex128)
+    V = oracle.volume(dims)
+    for j in range(n):
+        e = np.zeros((V, 3), dtype=np.complex128)
+        e[sites[j // 3], j % 3] = 1.0
+        A[:, j] = oracle.normal_op(fat, lng, e, dims, mass, shift, parity, lib=lib)[sites].ravel()
+    return A
+
+
+# ---------------------------------------------------------------------------
+# operator pins
+# ---------------------------------------------------------------------------
+
+def check_antihermitian(lib, dims=(4, 6, 4, 8), kind="haar", tol=1e-13):
+    """<x, D y> = -<D x, y> for random fields (D is anti-Hermitian)"""
+    fat, lng = links(dims, kind)
+    V = oracle.volume(dims)
+    x, y = spinor(V, 11), spinor(V, 12)
+    dx = oracle.dslash(fat, lng, x, dims, lib=lib)
+    dy = oracle.dslash(fat, lng, y, dims, lib=lib)
+    lhs, rhs = np.vdot(x, dy), -np.vdot(dx, y)
+    err = abs(lhs - rhs) / max(abs(lhs), 1e-300)
+    return err < tol, f"anti-Hermiticity rel err {err:.2e} (|<x,Dy>| = {abs(lhs):.3e})"
+
+
+def check_parity_structure(lib, dims=(4, 4, 6, 4)):
+    """D maps a field on one parity to a field on the other parity only"""
+    fat, lng = links(dims, "haar")
+    V = oracle.volume(dims)
+    par = oracle.site_parities(dims)
+    x = spinor(V, 13) * (par == 0)[:, None]
+    dx = oracle.dslash(fat, lng, x, dims, lib=lib)
+    leak = np.abs(dx[par == 0]).max()
+    cover = np.abs(dx[par == 1]).min()
+    return leak == 0.0 and cover > 0.0, f"even->even leak {leak:.2e}, min odd {cover:.2e}"
+
+
+def check_gauge_covariance(lib, dims=(4, 4, 4, 6), kind="near_unit", tol=1e-13):
+    """D[F', L'](G psi) = G D[F, L] psi, F'_mu(x) = G(x) F_mu(x) G(x+mu)^dag,
+    L'_mu(x) = G(x) L_mu(x) G(x+3mu)^dag, G a random SU(3) field"""
+    fat, lng = links(dims, kind)
+    V = oracle.volume(dims)
+    G = inputs.random_su3_field(V, 777).numpy()
+    Gd = np.conj(np.transpose(G, (0, 2, 1)))
+    fat2, lng2 = np.empty_like(fat), np.empty_like(lng)
+    for mu in range(4):
+        s1, s3 = shifted_site(dims, mu, 1), shifted_site(dims, mu, 3)
+        fat2[mu] = G @ fat[mu] @ Gd[s1]
+        lng2[mu] = G @ lng[mu] @ Gd[s3]
+    psi = spinor(V, 14)
+    lhs = oracle.dslash(fat2, lng2, np.einsum("sab,sb->sa", G, psi), dims, lib=lib)
+    rhs = np.einsum("sab,sb->sa", G, oracle.dslash(fat, lng, psi, dims, lib=lib))
+    err = rel(lhs, rhs)
+    return err < tol, f"gauge covariance rel err {err:.2e}"
+
+
+def check_free_field_dslash(lib, dims=(4, 6, 8, 4), tol=1e-13):
+    """unit links: D(e^{ipx} v) = sum_mu eta_mu(x) 2i (c1 sin p_mu + c3 sin 3p_mu) e^{ipx} v"""
+    fat, lng = [a.numpy() for a in inputs.unit_links(dims, c1=C1, c3=C3)]
+    eta = staggered_eta(dims)
+    worst = 0.0
+    for n in [(0, 0, 0, 0), (1, 2, 3, 1), (3, 5, 7, 2), (2, 1, 0, 3)]:
+        psi, p = plane_wave(dims, n, [1.0, 0.5 - 0.25j, -0.3j])
+        expect = sum(eta[m][:, None] * 2j * (C1 * np.sin(p[m]) + C3 * np.sin(3 * p[m])) for m in range(4)) * psi
+        got = oracle.dslash(fat, lng, psi, dims, lib=lib)
+        worst = max(worst, rel(got, expect))
+    return worst < tol, f"free-field D rel err {worst:.2e}"
+
+
+def check_free_field_normal(lib, dims=(4, 6, 8, 4), mass=0.1, tol=1e-13):
+    """unit links: A = 4m^2 - D_eo D_oe has the plane waves (on even sites) as
+    eigenvectors with eigenvalue 4m^2 + 4 sum_mu (c1 sin p_mu + c3 sin 3p_mu)^2"""
+    fat, lng = [a.numpy() for a in inputs.unit_links(dims, c1=C1, c3=C3)]
+    par = oracle.site_parities(dims)
+    worst = 0.0
+    for n in [(0, 0, 0, 0), (1, 2, 3, 1), (3, 5, 7, 2), (1, 1, 1, 3)]:
+        psi, p = plane_wave(dims, n, [0.2, 1.0j, -0.7])
+        psi = psi * (par == 0)[:, None]
+        lam = 4 * mass ** 2 + 4 * sum((C1 * np.sin(q) + C3 * np.sin(3 * q)) ** 2 for q in p)
+        got = oracle.normal_op(fat, lng, psi, dims, mass, lib=lib)
+        worst = max(worst, rel(got, lam * psi))
+    return worst < tol, f"free-field A eigen rel err {worst:.2e}"
+
+
+def check_normal_hpd(lib, dims=(4, 4, 4, 4), mass=0.1):
+    """A is Hermitian positive definite with spectrum >= 4m^2 (4^4, rough links)"""
+    fat, lng = links(dims, "haar")
+    A = dense_normal(fat, lng, dims, mass, lib=lib)
+    herm = np.abs(A - A.conj().T).max() / np.abs(A).max()
+    try:
+        np.linalg.cholesky(A)
+        chol = True
+    except np.linalg.LinAlgError:
+        chol = False
+    lmin = np.linalg.eigvalsh(0.5 * (A + A.conj().T)).min()
+    ok = herm < 1e-14 and chol and lmin >= 4 * mass ** 2 * (1 - 1e-12)
+    return ok, f"hermiticity {herm:.2e}, cholesky {chol}, lambda_min {lmin:.6f} vs 4m^2 {4*mass**2}"
+
+
+# ---------------------------------------------------------------------------
+# solver pins
+# ---------------------------------------------------------------------------
+
+def check_cg_dense(lib, dims=(4, 4, 4, 4), mass=0.1, shift=0.0, tol=1e-10):
+    """plain FP64 CG against a dense LAPACK solve on 4^4 rough links"""
+    fat, lng = links(dims, "haar")
+    sites = oracle.parity_sites(dims, 0)
+    V = oracle.volume(dims)
+    b = np.zeros((V, 3), dtype=np.complex128)
+    b[sites] = inputs.gaussian_spinor(sites.size, inputs.SOURCE_SEED).numpy()
+    A = dense_normal(fat, lng, dims, mass, shift, lib=lib)
+    xd = np.linalg.solve(A, b[sites].ravel())
+    x, it, res, st = oracle.cg(fat, lng, b, dims, mass, shift, tol=tol, maxiter=2000, lib=lib)
+    err = rel(x[sites].ravel(), xd)
+    ok = st == 0 and res <= tol and err < 1e-8 and np.abs(x[oracle.parity_sites(dims, 1)]).max() == 0
+    return ok, f"CG iters {it}, true resid {res:.2e}, |x-x_dense|/|x| {err:.2e}"
+
+
+def check_multishift_dense(lib, dims=(4, 4, 4, 4), mass=0.1, shifts=(1e-3, 0.01, 0.1, 1.0, 10.0), tol=1e-11):
+    """every multi-shift solution against the dense solve of its own system"""
+    fat, lng = links(dims, "haar")
+    sites = oracle.parity_sites(dims, 0)
+    V = oracle.volume(dims)
+    b = np.zeros((V, 3), dtype=np.complex128)
+    b[sites] = inputs.gaussian_spinor(sites.size, inputs.SOURCE_SEED + 1).numpy()
+    A0 = dense_normal(fat, lng, dims, mass, 0.0, lib=lib)
+    out = oracle.multishift_cg(fat, lng, b, dims, mass, shifts, tol, maxiter=2000, lib=lib)
+    worst = 0.0
+    for i, s in enumerate(shifts):
+        xd = np.linalg.solve(A0 + s * np.eye(A0.shape[0]), b[sites].ravel())
+        worst = max(worst, rel(out["x"][i][sites].ravel(), xd))
+    ok = worst < 1e-9 and out["status"] == 0
+    return ok, f"multi-shift worst |x-x_dense|/|x| {worst:.2e}, iters {list(out['iters'])}"
+
+
+def check_multishift_single_is_cg(lib, dims=(4, 4, 4, 6), mass=0.05):
+    """one shift: the multi-shift recurrences collapse to plain CG (zeta = 1)"""
+    fat, lng = links(dims, "near_unit")
+    sites = oracle.parity_sites(dims, 0)
+    V = oracle.volume(dims)
+    b = np.zeros((V, 3), dtype=np.complex128)
+    b[sites] = inputs.gaussian_spinor(sites.size, 5).numpy()
+    x, it, res, st = oracle.cg(fat, lng, b, dims, mass, 0.02, tol=1e-10, maxiter=3000, lib=lib)
+    out = oracle.multishift_cg(fat, lng, b, dims, mass, [0.02], 1e-10, maxiter=3000, lib=lib)
+    err = rel(out["x"][0], x)
+    ok = err < 1e-12 and abs(int(out["iters"][0]) - it) == 0 and out["zeta"][0] == 1.0
+    return ok, f"single-shift vs CG rel {err:.2e}, iters {out['iters'][0]} vs {it}"
+
+
+def check_multishift_colinear(lib, dims=(4, 4, 6, 4), mass=0.05, shifts=(0.0, 0.05, 0.5, 3.0), k=15):
+    """after k steps, b - (A + s_i) x_i = zeta_i r for every shift (Sec. 3.2:
+    the shifted residuals are co-linear with the base residual)"""
+    fat, lng = links(dims, "haar")
+    sites = oracle.parity_sites(dims, 0)
+    V = oracle.volume(dims)
+    b = np.zeros((V, 3), dtype=np.complex128)
+    b[sites] = inputs.gaussian_spinor(sites.size, 6).numpy()
+    out = oracle.multishift_cg(fat, lng, b, dims, mass, shifts, 0.0, maxiter=k, lib=lib)
+    worst = 0.0
+    for i, s in enumerate(shifts):
+        ri = b - oracle.normal_op(fat, lng, out["x"][i], dims, mass, s, lib=lib)
+        worst = max(worst, np.linalg.norm(ri - out["zeta"][i] * out["r"]) / np.linalg.norm(b))
+    zs = out["zeta"]
+    ok = worst < 1e-11 and zs[0] == 1.0 and all(0 < zs[i + 1] < zs[i] for i in range(len(shifts) - 1))
+    return ok, f"co-linearity defect {worst:.2e}, zeta {zs}"
+
+
+# ---------------------------------------------------------------------------
+# codec pins (hand-derived vectors)
+# ---------------------------------------------------------------------------
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            rows.append([part.split() for part in line.split("|")])
+    return rows
+
+
+def check_int20_golden(lib):
+    bad = []
+    for vin, wout in _read_golden("int20_appendix_a.txt"):
+        v = np.array([float(s) for s in vin], dtype=np.float32)[None, :]
+        w = oracle.int20_encode(v, lib=lib)[0]
+        want = np.array([int(s, 16) for s in wout], dtype=np.uint32)
+        if not np.array_equal(w, want):
+            bad.append((vin, [hex(int(a)) for a in w]))
+        # decode: within half a quantum 2^(E-128) of v, and a fixed point of encode
+        back = oracle.int20_decode(want[None, :], lib=lib)[0]
+        half_q = 2.0 ** (int(want[3] >> 24) - 128)
+        if (np.abs(back.astype(np.float64) - v[0]).max() > half_q
+                or not np.array_equal(oracle.int20_encode(back[None, :], lib=lib)[0], want)):
+            bad.append(("decode", vin, back))
+    return not bad, f"int20 golden mismatches: {bad}"
+
+
+def check_int30_golden(lib):
+    bad = []
+    for vin, wout in _read_golden("int30_listing3.txt"):
+        v = np.array([float(s) for s in vin], dtype=np.float64)[None, :]
+        w = oracle.int30_encode(v, lib=lib)[0]
+        want = np.array([int(s, 16) for s in wout], dtype=np.uint32)
+        if not np.array_equal(w, want):
+            bad.append((vin, [hex(int(a)) for a in w]))
+        back = oracle.int30_decode(want[None, :], lib=lib)[0]
+        if not np.array_equal(back, v[0]):          # every int30 row is on its grid
+            bad.append(("decode", vin, back))
+    return not bad, f"int30 golden mismatches: {bad}"
+
+
+def check_half16_golden(lib):
+    bad = []
+    for vin, nin, qout in _read_golden("half16_listing1.txt"):
+        v = np.array([float(s) for s in vin], dtype=np.float32)[None, :]
+        q, nm = oracle.half16_encode(v, lib=lib)
+        if not (np.array_equal(q[0], np.array([int(s) for s in qout], dtype=np.int16))
+                and nm[0] == np.float32(float(nin[0]))):
+            bad.append((vin, list(q[0]), float(nm[0])))
+    return not bad, f"half16 golden mismatches: {bad}"
+
+
+def check_fixed_golden(lib):
+    bad = []
+    for (bits, absmax, u), (qs,) in _read_golden("fixed_gauge.txt"):
+        q, _ = oracle.fix_encode(np.array([complex(float(u), 0.0)]), int(bits), absmax=float(absmax), lib=lib)
+        if int(q[0]) != int(qs) or int(q[1]) != 0:
+            bad.append((bits, absmax, u, int(q[0])))
+    return not bad, f"fixed-point golden mismatches: {bad}"
+
+
+ALL_OPERATOR = [check_antihermitian, check_parity_structure, check_gauge_covariance,
+                check_free_field_dslash, check_free_field_normal, check_normal_hpd]
+ALL_SOLVER = [check_cg_dense, check_multishift_dense, check_multishift_single_is_cg,
+              check_multishift_colinear]
+ALL_CODEC = [check_int20_golden, check_int30_golden, check_half16_golden, check_fixed_golden]
+ALL = ALL_OPERATOR + ALL_SOLVER + ALL_CODEC

@@ -1,0 +1,260 @@
+/*
+ * hisq.h -- C ABI of libhisq: the even-odd HISQ staggered Dslash in low-bit
+ * storage formats and the stabilised mixed-precision CG / multi-shift CG
+ * solvers built on it, for AMD Instinct MI355X (gfx950).
+ *
+ * Paper: M. A. Clark, D. Howarth, J. Tu, M. Wagner, E. Weinberg,
+ * "Maximizing the Bang Per Bit", arXiv:2302.09224 (Lattice 2022).
+ *
+ * Conventions for every call
+ *  - Pointers marked (device) are HIP device pointers owned by the caller; the
+ *    library never frees or reallocates them.  Pointers marked (host) are
+ *    ordinary host memory.  Device pointers must be 16-byte aligned
+ *    (HISQ_EALIGN otherwise).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it.  Calls that must return a host value
+ *    (gauge packing, solvers) synchronise that stream before returning.
+ *  - Errors are returned as hisq_status; no C++ exception crosses the ABI.
+ *    hisq_last_error() gives a message for the calling thread's last error.
+ *  - Lattice: dims = {X, Y, Z, T}, each even and >= 4; site index
+ *    i = ((t*Z + z)*Y + y)*X + x; parity (x+y+z+t) & 1; the checkerboard
+ *    index of a site within its parity is i >> 1; V = X*Y*Z*T, Vh = V/2.
+ *  - Canonical FP64 fields (the interchange format at the ABI):
+ *      links:   complex128 [4][V][3][3]  (direction mu = x,y,z,t; site; row; col)
+ *      spinor:  complex128 [Vh][3]       (one parity, checkerboard order)
+ *    complex128 = two doubles (re, im).  The staggered phases and the
+ *    boundary signs are expected to be folded into the links already.
+ *  - Packed fields (the formats the kernels stream) have a library-defined
+ *    layout; create them only with hisq_gauge_pack / hisq_spinor_pack and read
+ *    them back with hisq_spinor_unpack.  Their sizes are given by
+ *    hisq_gauge_bytes / hisq_spinor_bytes.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HISQ_OK = 0,
+    HISQ_EINVAL = -1,      /* bad argument (dims, format, sizes, null pointer) */
+    HISQ_EALIGN = -2,      /* a device pointer is not 16-byte aligned */
+    HISQ_EHIP = -3,        /* a HIP runtime call failed */
+    HISQ_ENOCONV = -4,     /* solver hit maxiter; stats are filled, x is the best iterate */
+    HISQ_EBREAKDOWN = -5,  /* solver breakdown: <p,Ap> <= 0 or a non-finite residual */
+    HISQ_EWORKSPACE = -6,  /* workspace too small (see the *_workspace_bytes queries) */
+    HISQ_ERANGE = -7       /* a value exceeds what the storage format can hold */
+} hisq_status;
+
+/* Spinor (fermion) storage formats. */
+enum {
+    HISQ_SPINOR_F64 = 0,     /* IEEE FP64, 48 B/site */
+    HISQ_SPINOR_F32 = 1,     /* IEEE FP32, 24 B/site */
+    HISQ_SPINOR_HALF16 = 2,  /* QUDA half: 6 x int16 + FP32 site max, 16 B/site (Sec. 2, Listing 1) */
+    HISQ_SPINOR_INT20 = 3,   /* 6 x 20-bit + 8-bit shared exponent, 16 B/site (Sec. 4, Listing 2, App. A) */
+    HISQ_SPINOR_INT30 = 4    /* 6 x 30-bit + 8-bit shared exponent, 24 B/site (Sec. 4, Listing 3) */
+};
+
+/* Gauge (link) storage formats. */
+enum {
+    HISQ_GAUGE_F64 = 0,      /* IEEE FP64, 144 B/matrix */
+    HISQ_GAUGE_F32 = 1,      /* IEEE FP32, 72 B/matrix */
+    HISQ_GAUGE_FIX16 = 2,    /* 16-bit fixed point, global scale, 36 B/matrix (Sec. 2 footnote, Sec. 4) */
+    HISQ_GAUGE_FIX32 = 3     /* 32-bit fixed point, global scale, 72 B/matrix (Sec. 4) */
+};
+
+/* Precision triplet gauge / fermion / compute of one stencil application
+ * (Sec. 4).  compute is 32 (FP32) or 64 (FP64).  Supported triplets:
+ *   F64/F64/64, F32/F32/32, FIX16/HALF16/32, FIX16/INT20/32,
+ *   FIX32/INT30/64, FIX32/INT30/32. */
+typedef struct {
+    int gauge;
+    int spinor;
+    int compute;
+} hisq_fmt;
+
+/* A packed pair of link fields, filled by hisq_gauge_pack. */
+typedef struct {
+    int dims[4];
+    int fmt;              /* HISQ_GAUGE_* */
+    const void *fat;      /* (device) packed one-link (fat) field */
+    const void *lng;      /* (device) packed three-link (Naik) field */
+    double fat_max;       /* global max |real component| of the fat field (fixed-point scale) */
+    double long_max;      /* same for the long field */
+} hisq_gauge;
+
+/* Bytes of ONE packed link field (fat or long): 4*V matrices. */
+size_t hisq_gauge_bytes(const int dims[4], int gauge_fmt);
+
+/* Bytes of one packed single-parity spinor of `nsites` sites (Vh for a field). */
+size_t hisq_spinor_bytes(long nsites, int spinor_fmt);
+
+/* Pack canonical FP64 links into `gauge_fmt` and fill *g.
+ * fat_src, long_src: (device) canonical complex128 [4][V][3][3].
+ * fat_dst, long_dst: (device) hisq_gauge_bytes(dims, gauge_fmt) bytes each.
+ * Fixed-point formats scale each field by its own global max real component
+ * (Sec. 2 footnote); q = round-half-even(u * Q / max), Q = 2^15-1 or 2^31-1.
+ * FP32 rounds to nearest.  Synchronises `stream` (the scales are returned in *g).
+ * Errors: EINVAL (dims/format/null), EALIGN, ERANGE (non-finite link), EHIP. */
+hisq_status hisq_gauge_pack(hisq_gauge *g, void *fat_dst, void *long_dst,
+                            const double *fat_src, const double *long_src,
+                            const int dims[4], int gauge_fmt, void *stream);
+
+/* Pack `nsites` canonical FP64 colour vectors (device complex128 [nsites][3])
+ * into `spinor_fmt` at dst (device, hisq_spinor_bytes bytes).
+ * HALF16 and INT20 first round the values to FP32 (their compute precision),
+ * INT30 works in FP64.  HALF16: per-site max M, q = rint(v * (32767/M)).
+ * INT20/INT30: shared exponent E = (FP exponent of M/(2^(B-1)-1)) + 1,
+ * q = rint(v * 2^(127-E)) (the packing of Appendix A; INT30 per Sec. 4). */
+hisq_status hisq_spinor_pack(void *dst, const double *src, long nsites, int spinor_fmt, void *stream);
+
+/* Inverse of hisq_spinor_pack: decode to device complex128 [nsites][3]. */
+hisq_status hisq_spinor_unpack(double *dst, const void *src, long nsites, int spinor_fmt, void *stream);
+
+/* The even-odd HISQ Dslash (the stencil of Secs. 1 and 5; Figs. 2-3):
+ *   out(x) = sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^dag in(x-mu)
+ *                   + L_mu(x) in(x+3mu) - L_mu(x-3mu)^dag in(x-3mu) ]
+ * for every site x of parity `parity`; `in` holds the sites of parity
+ * 1-parity.  in/out: (device) packed spinors in fmt.spinor (Vh sites each;
+ * must not alias).  g: packed links, g->fmt == fmt.gauge.  The arithmetic is
+ * done in fmt.compute after unpacking in registers; the result is packed
+ * again into fmt.spinor.  Errors: EINVAL, EALIGN, EHIP. */
+hisq_status hisq_dslash(void *out, const void *in, const hisq_gauge *g, int parity,
+                        hisq_fmt fmt, void *stream);
+
+/* out = a * x + b * Dslash(in), x (device, packed, parity `parity`) may be
+ * NULL (then out = b * Dslash(in)).  Same rules as hisq_dslash. */
+hisq_status hisq_dslash_xpay(void *out, const void *in, const hisq_gauge *g, int parity,
+                             hisq_fmt fmt, double a, const void *x, double b, void *stream);
+
+/* The even-site normal operator of the solvers (Sec. 3):
+ *   out = (4 m^2 + shift) in - D_eo D_oe in
+ * in/out: (device) packed even-parity spinors; tmp: (device) packed odd-parity
+ * spinor of the same format (overwritten). */
+hisq_status hisq_normal_op(void *out, const void *in, void *tmp, const hisq_gauge *g,
+                           double mass, double shift, hisq_fmt fmt, void *stream);
+
+/* Batched Dslash (block of right-hand sides, Sec. 1 "Block solvers"): nrhs
+ * consecutive packed fields in `in` and `out` (each hisq_spinor_bytes(Vh))
+ * share one pass over the links.  1 <= nrhs <= 16. */
+hisq_status hisq_dslash_batched(void *out, const void *in, const hisq_gauge *g, int parity,
+                                hisq_fmt fmt, int nrhs, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Solvers (Sec. 3)                                                          */
+/* ------------------------------------------------------------------------ */
+
+#define HISQ_MAX_SHIFTS 32
+#define HISQ_MAX_GRAD_BUFFER 16
+
+typedef struct {
+    double delta;        /* reliable update when |r| < delta * max|r| since the last one (Sec. 3 footnote: 0.1);
+                            <= 0 disables reliable updates (the residual is only checked at the end) */
+    int maxiter;         /* iteration cap per solve (per phase for multi-shift) */
+    int grad_buffer;     /* gradient vectors buffered before the FP64 solution update (Sec. 3.1 item 1), 1..16 */
+    int pr_beta;         /* 1: Polak-Ribiere beta (Sec. 3.1 item 3); 0: Fletcher-Reeves */
+    int reproject;       /* 1: re-project the gradient vector at each reliable update (Sec. 3.1 item 2) */
+    int poll_every;      /* iterations enqueued between host polls of the device state (rounded up to a
+                            multiple of grad_buffer); 0 = default */
+    int use_graph;       /* 1: replay each block of iterations as a captured hipGraph */
+    double shift_floor;  /* multi-shift: a shifted system stops updating once its iterated residual is below
+                            max(tol_i, shift_floor) (Sec. 3.2: "reach the limit of the sloppy precision");
+                            <= 0 selects the sloppy format's epsilon */
+} hisq_solver_params;
+
+typedef struct {
+    int status;                 /* hisq_status of the solve */
+    int iters;                  /* sloppy iterations (multi-shift: multi-shift phase) */
+    int reliable_updates;
+    int dslash_sloppy;          /* sloppy Dslash applications */
+    int dslash_f64;             /* FP64 Dslash applications */
+    double true_resid;          /* final |b - A x| / |b| (multi-shift: max over shifts of resid/tol_i * tol_0) */
+    double seconds;             /* wall-clock of the solve */
+    double alg_bytes;           /* algorithmic HBM bytes of all kernels of the solve */
+    int nshift;
+    int shift_iters[HISQ_MAX_SHIFTS];        /* multi-shift phase iteration at which shift i stopped */
+    double shift_resid_ms[HISQ_MAX_SHIFTS];  /* true residual of shift i after the multi-shift phase */
+    int refine_iters[HISQ_MAX_SHIFTS];       /* refinement CG iterations of shift i */
+    double shift_resid[HISQ_MAX_SHIFTS];     /* final true residual of shift i */
+} hisq_solver_stats;
+
+/* Default parameters: delta 0.1, maxiter 100000, grad_buffer 4, PR beta,
+ * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto). */
+void hisq_solver_params_default(hisq_solver_params *p);
+
+/* Workspace bytes for hisq_cg_solve on `dims` with sloppy format `sloppy`. */
+size_t hisq_cg_workspace_bytes(const int dims[4], hisq_fmt sloppy, const hisq_solver_params *p);
+
+/* Mixed-precision CG (Sec. 3.1) for (4m^2 + shift - D_eo D_oe) x = b on the
+ * even sites:  the iterated residual and gradient vectors live in
+ * sloppy.spinor, the Dslash runs in the sloppy triplet; the solution is
+ * accumulated in FP64 from buffered gradient vectors; reliable updates
+ * recompute the true residual with the FP64 operator (g64, F64/F64/64) and
+ * re-project the gradient vector; beta is Polak-Ribiere.  Stops when the
+ * true relative residual |b - A x|/|b| <= tol.
+ * x: (device) canonical complex128 [Vh][3], initial guess in, solution out.
+ * b: (device) canonical complex128 [Vh][3].
+ * g64: links packed as HISQ_GAUGE_F64; gs: links packed as sloppy.gauge.
+ * ws: (device) workspace of at least hisq_cg_workspace_bytes bytes.
+ * stats: (host) filled on return, may be NULL.
+ * Errors: EINVAL, EALIGN, EWORKSPACE, ENOCONV, EBREAKDOWN, EHIP. */
+hisq_status hisq_cg_solve(double *x, const double *b, const hisq_gauge *g64, const hisq_gauge *gs,
+                          double mass, double shift, double tol, hisq_fmt sloppy,
+                          const hisq_solver_params *p, void *ws, size_t ws_bytes,
+                          hisq_solver_stats *stats, void *stream);
+
+/* Workspace bytes for hisq_multishift_cg_solve. */
+size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift, hisq_fmt ms_fmt,
+                                       hisq_fmt refine_fmt, const hisq_solver_params *p);
+
+/* Mixed-precision multi-shift CG with post-solve refinement (Sec. 3.2):
+ * x_i = (4m^2 + shift_i - D_eo D_oe)^-1 b for i = 0..nshift-1.  One Krylov
+ * space of the base system (shift_0, the smallest) built in the ms_fmt
+ * triplet with reliable updates on the base only; all shifted solutions
+ * (FP64) and gradient vectors are updated in one fused launch per iteration;
+ * shift i stops updating when its iterated residual reaches
+ * max(tol_i, shift_floor); the phase ends when every shift i >= 1 has
+ * stopped.  Then CG refinement in the refine_fmt triplet: the base first,
+ * keeping its gradient vector, then every shift in ascending order from a
+ * clean restart, each to its own tol_i (true residual).
+ * x: (host) array of nshift (device) canonical complex128 [Vh][3] outputs.
+ * shifts, tol: (host) arrays of nshift doubles, shifts strictly ascending,
+ * shifts[0] >= 0 and 1 <= nshift <= HISQ_MAX_SHIFTS.
+ * g64: F64 links; g_ms: links in ms_fmt.gauge; g_ref: links in refine_fmt.gauge.
+ * Errors as hisq_cg_solve. */
+hisq_status hisq_multishift_cg_solve(double *const *x, const double *b, const double *shifts,
+                                     int nshift, const double *tol, const hisq_gauge *g64,
+                                     const hisq_gauge *g_ms, const hisq_gauge *g_ref, double mass,
+                                     hisq_fmt ms_fmt, hisq_fmt refine_fmt,
+                                     const hisq_solver_params *p, void *ws, size_t ws_bytes,
+                                     hisq_solver_stats *stats, void *stream);
+
+/* Workspace bytes for hisq_cg_solve_batched. */
+size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt sloppy,
+                                       const hisq_solver_params *p);
+
+/* nrhs independent mixed-precision CG solves (same operator, different right-hand
+ * sides) that share every Dslash launch, so each link is loaded once per
+ * application for the whole block (Sec. 1 "Block solvers").  x, b: (device)
+ * nrhs consecutive canonical complex128 [Vh][3] fields.  Each right-hand side
+ * converges to tol on its own; stats describe the slowest one.  1 <= nrhs <= 16. */
+hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hisq_gauge *g64,
+                                  const hisq_gauge *gs, double mass, double shift, double tol,
+                                  hisq_fmt sloppy, const hisq_solver_params *p, void *ws,
+                                  size_t ws_bytes, hisq_solver_stats *stats, void *stream);
+
+/* Thread-local message of the calling thread's last non-OK status. */
+const char *hisq_last_error(void);
+
+/* Library version string. */
+const char *hisq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

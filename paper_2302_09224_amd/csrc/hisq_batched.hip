@@ -1,0 +1,513 @@
+// hisq_batched.hip -- a block of independent mixed-precision CG solves that
+// share every Dslash launch (Sec. 1, "Block solvers": the link traffic of the
+// stencil is amortised over the right-hand sides).
+//
+// Each right-hand side j keeps its own scalars (rho_j, alpha_j, beta_j, ...)
+// in the control block; the Dslash applies one load of each link matrix to all
+// nrhs spinors.  The iteration is the single-system one of hisq_solver.hip
+// (buffered FP64 solution, Polak-Ribiere beta, reliable updates with
+// re-projection) done for every j at once; a reliable update requested by any
+// right-hand side is performed for all of them (it is never harmful), and a
+// right-hand side whose true residual meets tol stops updating.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "hisq_internal.h"
+
+namespace hisq {
+
+namespace {
+
+constexpr int FIN_THREADS = 256;
+
+// sum over blocks b of partial[(b*nrhs + j)*NV + k], k < NV; valid in thread 0
+template <int NV>
+__device__ __forceinline__ void bsum(const double *partial, int nb, int nrhs, int j, double (&v)[NV], double *lds) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) v[k] += partial[((size_t)b * nrhs + j) * NV + k];
+    }
+    block_sum<NV>(v, lds);
+    __syncthreads();
+}
+
+__global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, int nb, int nrhs, int jb, Guard gd) {
+    __shared__ double lds[16];
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        double v[1];
+        bsum<1>(partial, nb, nrhs, j, v, lds);
+        if (threadIdx.x) continue;
+        const double pi = v[0];
+        c->bpi[j] = pi;
+        if (!c->bactive[j]) {
+            c->balpha[j] = 0.0;
+            c->balpha_buf[jb][j] = 0.0;
+            continue;
+        }
+        if (!(pi > 0.0) || !__builtin_isfinite(pi)) {
+            c->stop = gd.j - 1;
+            c->reason = STOP_BREAKDOWN;
+            c->breakdown = 1;
+            c->balpha[j] = 0.0;
+            c->balpha_buf[jb][j] = 0.0;
+            continue;
+        }
+        const double a = c->brho[j] / pi;
+        c->balpha[j] = a;
+        c->balpha_buf[jb][j] = a;
+    }
+}
+
+__global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nrhs, Guard gd) {
+    __shared__ double lds[32];
+    if (!gd.pass()) return;
+    int reason = STOP_NONE;
+    for (int j = 0; j < nrhs; j++) {
+        double v[2];
+        bsum<2>(partial, nb, nrhs, j, v, lds);
+        if (threadIdx.x || !c->bactive[j]) continue;
+        const double rn = v[0], g = v[1];
+        c->bk[j] += 1;
+        if (!__builtin_isfinite(rn) || !__builtin_isfinite(g)) {
+            reason = STOP_BREAKDOWN;
+            c->breakdown = 1;
+            continue;
+        }
+        const double rho = c->brho[j];
+        const double beta = c->pr ? (rn - g) / rho : rn / rho;
+        c->bbeta[j] = beta;
+        c->bpa_re[j] = 1.0;
+        c->bpa_im[j] = 0.0;
+        c->bpb[j] = beta;
+        c->brmax2[j] = fmax(c->brmax2[j], rn);
+        if (c->delta2 > 0.0 && rn < c->delta2 * c->brmax2[j]) reason = reason ? reason : STOP_RU;
+        if (rn <= c->tol2 * c->bb2[j]) reason = reason ? reason : STOP_CONV;
+        c->brho_prev[j] = rho;
+        c->brho[j] = rn;
+    }
+    if (threadIdx.x) return;
+    const int k = c->k + 1;
+    c->k = k;
+    if (reason == STOP_NONE && k >= c->maxiter) reason = STOP_MAXITER;
+    if (reason != STOP_NONE) {
+        c->reason = reason;
+        c->stop = gd.j;
+    }
+}
+
+__global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, int nb, int nrhs) {
+    __shared__ double lds[16];
+    int all = 1;
+    for (int j = 0; j < nrhs; j++) {
+        double v[1];
+        bsum<1>(partial, nb, nrhs, j, v, lds);
+        if (threadIdx.x) continue;
+        const double r2 = v[0];
+        c->br2_true[j] = r2;
+        if (!__builtin_isfinite(r2)) c->breakdown = 1;
+        if (c->bactive[j] && r2 <= c->tol2 * c->bb2[j]) {
+            c->bactive[j] = 0;
+            c->bdone[j] = 1;
+        }
+        all &= !c->bactive[j];
+    }
+    if (threadIdx.x) return;
+    c->done = all;
+    c->stop = (all || c->breakdown) ? -1 : STOP_NEVER;
+}
+
+__global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, int nrhs, int mode, Guard gd) {
+    __shared__ double lds[64];
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        double v[4];
+        bsum<4>(partial, nb, nrhs, j, v, lds);
+        if (threadIdx.x || !c->bactive[j]) continue;
+        const double rho = v[0];
+        double beta = 0.0, cr = 0.0, ci = 0.0;
+        if (mode != 1) {
+            if (c->reproject && rho > 0.0) {
+                cr = v[1] / rho;
+                ci = v[2] / rho;
+            }
+            beta = c->pr ? (rho - v[3]) / c->brho_prev[j] : rho / c->brho_prev[j];
+        }
+        c->bpa_re[j] = 1.0 - beta * cr;
+        c->bpa_im[j] = -beta * ci;
+        c->bpb[j] = beta;
+        c->bbeta[j] = beta;
+        c->brho[j] = rho;
+        c->brmax2[j] = rho;
+    }
+    if (threadIdx.x) return;
+    c->reason = STOP_NONE;
+    c->stop = STOP_NEVER;
+}
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct BBuf {
+    SolverCtrl *ctrl;
+    double *partial;
+    char *x64, *b64, *r64, *t64;
+    char *rs, *aps, *ts;
+    char *p[HISQ_MAX_GRAD_BUFFER];
+};
+
+size_t partial_len(const Geom &g, int nrhs) {
+    const size_t a = (size_t)dslash_blocks(g.vh, 64) * nrhs;
+    const size_t b = (size_t)4096 * 4 * nrhs;
+    return std::max(a, b);
+}
+
+size_t carve(BBuf *B, char *base, const Geom &g, int nrhs, int bs, int nb) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    BBuf tmp;
+    BBuf &b = B ? *B : tmp;
+    const size_t vh = g.vh;
+    b.ctrl = (SolverCtrl *)take(sizeof(SolverCtrl));
+    b.partial = (double *)take(partial_len(g, nrhs) * sizeof(double));
+    b.x64 = take(48 * vh * nrhs);
+    b.b64 = take(48 * vh * nrhs);
+    b.r64 = take(48 * vh * nrhs);
+    b.t64 = take(48 * vh * nrhs);
+    b.rs = take((size_t)bs * vh * nrhs);
+    b.aps = take((size_t)bs * vh * nrhs);
+    b.ts = take((size_t)bs * vh * nrhs);
+    for (int i = 0; i < HISQ_MAX_GRAD_BUFFER; i++) b.p[i] = i < nb ? take((size_t)bs * vh * nrhs) : nullptr;
+    return off;
+}
+
+struct BRun {
+    Geom g;
+    size_t vh;
+    int nrhs;
+    hisq_fmt fmt;
+    const hisq_gauge *g64, *gs;
+    double c_;
+    int nb, chunk;
+    bool graph;
+    BBuf *B;
+    hipStream_t st;
+    size_t fs, fs64;
+    long iters = 0, rus = 0, dsl = 0, d64 = 0;
+    double alg = 0.0;
+    hipGraphExec_t exec = nullptr;
+
+    ~BRun() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+
+    DslashArgs dargs(const hisq_gauge *gg, const hisq_fmt &f, char *out, const char *in, int parity) const {
+        DslashArgs a;
+        memset(&a, 0, sizeof(a));
+        a.out = out;
+        a.in = in;
+        a.fat = (const char *)gg->fat;
+        a.lng = (const char *)gg->lng;
+        a.b = 1.0;
+        a.g = g;
+        a.parity = parity;
+        a.red = RED_NONE;
+        a.nrhs = nrhs;
+        a.field_stride = spinor_field_bytes(vh, f.spinor);
+        const double q = gg->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
+        a.gfat = gg->fat_max / q;
+        a.glong = gg->long_max / q;
+        return a;
+    }
+
+    hisq_status enq_iteration(int j) {
+        const int jb = j % nb, jn = (j + 1) % nb;
+        SolverCtrl *c = B->ctrl;
+        const Guard gns{&c->stop, j, 0}, gsn{&c->stop, j, 1};
+        DslashArgs A = dargs(gs, fmt, B->ts, B->p[jb], 1);
+        A.guard = gns;
+        HISQ_TRY_HIP(launch_dslash_batched(A, fmt, 256, st));
+        DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
+        Bk.b = -1.0;
+        Bk.x = B->p[jb];
+        Bk.a = c_;
+        Bk.red = RED_DOT_X;
+        Bk.partial = B->partial;
+        Bk.guard = gns;
+        HISQ_TRY_HIP(launch_dslash_batched(Bk, fmt, 256, st));
+        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, dslash_blocks(g.vh, 256),
+                           nrhs, jb, gns);
+        HISQ_TRY_HIP(hipGetLastError());
+        HISQ_TRY_HIP(launch_bcg_axpy(B->rs, B->aps, c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, gns, st));
+        hipLaunchKernelGGL(k_bfin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs, gns);
+        HISQ_TRY_HIP(hipGetLastError());
+        if (jb == nb - 1) {
+            SpinorList pl;
+            for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;
+            HISQ_TRY_HIP(launch_bflush_x(B->x64, fs64, pl, nb, c, vh, fs, nrhs, fmt.spinor, fmt.compute, gsn, st));
+        }
+        HISQ_TRY_HIP(launch_bcg_pupdate(B->p[jn], B->rs, B->p[jb], c, vh, fs, nrhs, fmt.spinor, fmt.compute, gsn, st));
+        return HISQ_OK;
+    }
+
+    hisq_status enq_reliable(int mode, int count, const char *p_src) {
+        SolverCtrl *c = B->ctrl;
+        const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
+        if (count > 0) {
+            SpinorList pl;
+            for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;
+            HISQ_TRY_HIP(launch_bflush_x(B->x64, fs64, pl, count, c, vh, fs, nrhs, fmt.spinor, fmt.compute,
+                                         Guard{nullptr, 0, 0}, st));
+        }
+        DslashArgs A = dargs(g64, f64, B->t64, B->x64, 1);
+        HISQ_TRY_HIP(launch_dslash_batched(A, f64, 256, st));
+        DslashArgs Bk = dargs(g64, f64, B->r64, B->t64, 0);
+        Bk.x = B->x64;
+        Bk.a = -c_;
+        Bk.y = B->b64;
+        Bk.c = 1.0;
+        Bk.red = RED_NORM;
+        Bk.partial = B->partial;
+        HISQ_TRY_HIP(launch_dslash_batched(Bk, f64, 256, st));
+        hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, dslash_blocks(g.vh, 256), nrhs);
+        HISQ_TRY_HIP(hipGetLastError());
+        d64 += 2;
+        alg += 2.0 * vh * (16.0 * 144 + nrhs * 2.0 * 48) + 2.0 * vh * nrhs * 48;
+        const Guard g0{&c->stop, 0, 0};
+        HISQ_TRY_HIP(launch_bru_convert(B->rs, B->r64, fs64, mode == 1 ? nullptr : p_src, mode == 0 ? B->aps : nullptr,
+                                        c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, g0, st));
+        hipLaunchKernelGGL(k_bfin_ru_finish, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs,
+                           mode, g0);
+        HISQ_TRY_HIP(hipGetLastError());
+        HISQ_TRY_HIP(launch_bcg_pupdate(B->p[0], B->rs, mode == 1 ? B->rs : p_src, c, vh, fs, nrhs, fmt.spinor,
+                                        fmt.compute, g0, st));
+        return HISQ_OK;
+    }
+
+    hisq_status read_ctrl(SolverCtrl *h) {
+        HISQ_TRY_HIP(hipMemcpyAsync(h, B->ctrl, sizeof(SolverCtrl), hipMemcpyDeviceToHost, st));
+        HISQ_TRY_HIP(hipStreamSynchronize(st));
+        return HISQ_OK;
+    }
+
+    hisq_status enq_chunk() {
+        if (graph) {
+            if (!exec) {
+                hipGraph_t gr = nullptr;
+                HISQ_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                hisq_status s = HISQ_OK;
+                for (int j = 0; j < chunk && s == HISQ_OK; j++) s = enq_iteration(j);
+                hipError_t e = hipStreamEndCapture(st, &gr);
+                if (s != HISQ_OK) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return s;
+                }
+                HISQ_TRY_HIP(e);
+                e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                HISQ_TRY_HIP(e);
+            }
+            HISQ_TRY_HIP(hipGraphLaunch(exec, st));
+            return HISQ_OK;
+        }
+        for (int j = 0; j < chunk; j++) HISQ_TRY(enq_iteration(j));
+        return HISQ_OK;
+    }
+};
+
+struct BDev {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    SolverCtrl *host = nullptr;
+    std::mutex mu;
+};
+BDev g_bdev[64];
+
+}  // namespace
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt sloppy,
+                                                  const hisq_solver_params *p) {
+    if (!dims || !dims_ok(dims) || !triplet_ok(sloppy) || nrhs < 1 || nrhs > 16) return 0;
+    hisq_solver_params q;
+    hisq_solver_params_default(&q);
+    if (p) q = *p;
+    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return 0;
+    return carve(nullptr, nullptr, make_geom(dims), nrhs, spinor_site_bytes(sloppy.spinor), q.grad_buffer);
+}
+
+extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hisq_gauge *g64,
+                                             const hisq_gauge *gs, double mass, double shift, double tol,
+                                             hisq_fmt sloppy, const hisq_solver_params *p, void *ws, size_t ws_bytes,
+                                             hisq_solver_stats *stats, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    hisq_solver_stats tmp;
+    hisq_solver_stats *st = stats ? stats : &tmp;
+    memset(st, 0, sizeof(*st));
+    st->status = HISQ_EINVAL;
+    if (!x || !b || !g64 || !gs || !ws) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: null argument");
+    if (nrhs < 1 || nrhs > 16) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: nrhs must be in [1,16]");
+    if (!aligned16(x) || !aligned16(b) || !aligned16(ws)) return set_error(HISQ_EALIGN, "unaligned pointer");
+    if (!triplet_ok(sloppy) || (sloppy.gauge == HISQ_GAUGE_FIX32 && sloppy.compute == 32))
+        return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: unsupported sloppy triplet");
+    if (!(tol > 0.0)) return set_error(HISQ_EINVAL, "tol must be > 0");
+    const int *dims = g64->dims;
+    if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
+    if (!gs->fat || !gs->lng || gs->fmt != sloppy.gauge || g64->fmt != HISQ_GAUGE_F64 || !g64->fat || !g64->lng)
+        return set_error(HISQ_EINVAL, "gauge format mismatch or null gauge");
+    for (int k = 0; k < 4; k++)
+        if (gs->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "gauge dims differ");
+    hisq_solver_params q;
+    hisq_solver_params_default(&q);
+    if (p) q = *p;
+    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return set_error(HISQ_EINVAL, "bad grad_buffer");
+    if (q.maxiter <= 0) q.maxiter = 100000;
+    if (q.poll_every <= 0) q.poll_every = 32;
+    const Geom g = make_geom(dims);
+    BBuf B;
+    const size_t need = carve(&B, (char *)ws, g, nrhs, spinor_site_bytes(sloppy.spinor), q.grad_buffer);
+    if (ws_bytes < need) return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+
+    int d = 0;
+    HISQ_TRY_HIP(hipGetDevice(&d));
+    BDev &dv = g_bdev[d & 63];
+    std::unique_lock<std::mutex> lk(dv.mu);
+    if (!dv.stream) {
+        HISQ_TRY_HIP(hipStreamCreateWithFlags(&dv.stream, hipStreamNonBlocking));
+        HISQ_TRY_HIP(hipEventCreateWithFlags(&dv.ev, hipEventDisableTiming));
+        HISQ_TRY_HIP(hipHostMalloc((void **)&dv.host, sizeof(SolverCtrl), hipHostMallocDefault));
+    }
+    HISQ_TRY_HIP(hipEventRecord(dv.ev, (hipStream_t)stream));
+    HISQ_TRY_HIP(hipStreamWaitEvent(dv.stream, dv.ev, 0));
+    hipStream_t s_ = dv.stream;
+
+    BRun R;
+    R.g = g;
+    R.vh = g.vh;
+    R.nrhs = nrhs;
+    R.fmt = sloppy;
+    R.g64 = g64;
+    R.gs = gs;
+    R.c_ = 4.0 * mass * mass + shift;
+    R.nb = q.grad_buffer;
+    R.chunk = ((q.poll_every + q.grad_buffer - 1) / q.grad_buffer) * q.grad_buffer;
+    R.graph = q.use_graph != 0;
+    R.B = &B;
+    R.st = s_;
+    R.fs = spinor_field_bytes(g.vh, sloppy.spinor);
+    R.fs64 = spinor_field_bytes(g.vh, SF_F64);
+
+    for (int j = 0; j < nrhs; j++) {
+        HISQ_TRY_HIP(launch_spinor_pack(B.x64 + j * R.fs64, x + 6 * (size_t)g.vh * j, g.vh, SF_F64, s_));
+        HISQ_TRY_HIP(launch_spinor_pack(B.b64 + j * R.fs64, b + 6 * (size_t)g.vh * j, g.vh, SF_F64, s_));
+    }
+    SolverCtrl *h = dv.host;
+    memset(h, 0, sizeof(*h));
+    h->stop = STOP_NEVER;
+    h->pr = q.pr_beta;
+    h->reproject = q.reproject;
+    h->maxiter = q.maxiter;
+    h->tol2 = tol * tol;
+    h->delta2 = q.delta > 0 ? q.delta * q.delta : 0.0;
+    for (int j = 0; j < nrhs; j++) h->bactive[j] = 1;
+    HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
+    // |b_j|^2: the F64 norm kernel per right-hand side, each into its own partial column
+    for (int j = 0; j < nrhs; j++) {
+        int nbk = 0;
+        HISQ_TRY_HIP(launch_norm2_f64(B.b64 + j * R.fs64, g.vh, B.partial + (size_t)j * 4096, &nbk, s_));
+    }
+    // gather b2 on the host (once per solve) and store it in the control block
+    {
+        const int nbk = blas_blocks(g.vh);
+        std::vector<double> part((size_t)nrhs * 4096);
+        HISQ_TRY_HIP(hipMemcpyAsync(part.data(), B.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
+        HISQ_TRY_HIP(hipStreamSynchronize(s_));
+        for (int j = 0; j < nrhs; j++) {
+            double acc = 0.0;
+            for (int k = 0; k < nbk; k++) acc += part[(size_t)j * 4096 + k];
+            h->bb2[j] = acc;
+            if (acc == 0.0) {
+                h->bactive[j] = 0;
+                h->bdone[j] = 1;
+            }
+        }
+        HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
+    }
+    hisq_status status = R.enq_reliable(1, 0, nullptr);
+    if (status == HISQ_OK) status = R.read_ctrl(h);
+    long k0 = 0;
+    while (status == HISQ_OK && !h->done) {
+        if (h->breakdown) {
+            status = set_error(HISQ_EBREAKDOWN, "batched CG breakdown");
+            break;
+        }
+        status = R.enq_chunk();
+        if (status != HISQ_OK) break;
+        status = R.read_ctrl(h);
+        if (status != HISQ_OK) break;
+        const long dk = h->k - k0;
+        k0 = h->k;
+        R.iters += dk;
+        R.dsl += 2 * dk;
+        {
+            const double bs = spinor_site_bytes(sloppy.spinor), bg = gauge_matrix_bytes(sloppy.gauge);
+            R.alg += dk * (double)g.vh * (2.0 * (16.0 * bg + nrhs * 2.0 * bs) + nrhs * (bs + 6.0 * bs + (R.nb * bs + 96.0) / R.nb));
+        }
+        if (h->stop == STOP_NEVER) continue;
+        if (h->breakdown) {
+            status = set_error(HISQ_EBREAKDOWN, "batched CG breakdown after %d iterations", h->k);
+            break;
+        }
+        if (h->stop < 0 || h->stop >= R.chunk) {
+            status = set_error(HISQ_EBREAKDOWN, "inconsistent batched solver state (stop %d)", h->stop);
+            break;
+        }
+        const int jb = h->stop % R.nb;
+        const int reason = h->reason;
+        status = R.enq_reliable(0, jb + 1, B.p[jb]);
+        if (status != HISQ_OK) break;
+        R.rus++;
+        status = R.read_ctrl(h);
+        if (status != HISQ_OK) break;
+        if (h->done) break;
+        if (reason == STOP_MAXITER || h->k >= q.maxiter) {
+            status = set_error(HISQ_ENOCONV, "batched CG: no convergence in %d iterations", h->k);
+            break;
+        }
+    }
+    for (int j = 0; j < nrhs; j++) {
+        hipError_t e = launch_spinor_unpack(x + 6 * (size_t)g.vh * j, B.x64 + j * R.fs64, g.vh, SF_F64, s_);
+        if (e != hipSuccess && status == HISQ_OK) status = set_error(HISQ_EHIP, "unpack: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(s_);
+    if (e != hipSuccess && status == HISQ_OK) status = set_error(HISQ_EHIP, "sync: %s", hipGetErrorString(e));
+    st->iters = (int)R.iters;
+    st->reliable_updates = (int)R.rus;
+    st->dslash_sloppy = (int)R.dsl;
+    st->dslash_f64 = (int)R.d64;
+    st->alg_bytes = R.alg;
+    st->nshift = nrhs;
+    double worst = 0.0;
+    for (int j = 0; j < nrhs; j++) {
+        st->shift_resid[j] = h->bb2[j] > 0 ? std::sqrt(h->br2_true[j] / h->bb2[j]) : 0.0;
+        st->refine_iters[j] = h->bk[j];
+        worst = std::max(worst, st->shift_resid[j]);
+    }
+    st->true_resid = worst;
+    st->status = status;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}

@@ -1,0 +1,613 @@
+// hisq_blas.hip -- streaming kernels of libhisq: storage packing/unpacking,
+// gauge-field packing, and the fused vector updates of the solvers.
+//
+// All of these are HBM-bound sweeps over one or a few fields; each is written
+// as a grid-stride loop with a capped grid so that its reductions produce a
+// fixed, small number of per-block partials (summed later in a fixed order:
+// the reductions are bitwise reproducible).  Reductions accumulate in FP64
+// and are taken on the values as stored (after packing), which is what the
+// next iteration will read.
+#include "hisq_internal.h"
+
+namespace hisq {
+
+int blas_blocks(size_t n) {
+    size_t nb = (n + BLAS_BLOCK - 1) / BLAS_BLOCK;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+namespace {
+
+// natural arithmetic precision of a spinor format
+template <int SF> struct Natural { typedef float T; };
+template <> struct Natural<SF_F64> { typedef double T; };
+template <> struct Natural<SF_INT30> { typedef double T; };
+
+__device__ __forceinline__ size_t gtid() { return (size_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ size_t gstride() { return (size_t)gridDim.x * blockDim.x; }
+
+// canonical complex128 [n][3] (device) <-> register vector
+template <class R> __device__ __forceinline__ CVec<R> load_canon(const double *src, size_t s) {
+    const f64x2 *p = reinterpret_cast<const f64x2 *>(src + 6 * s);
+    CVec<R> v;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        f64x2 w = p[c];
+        v.re[c] = (R)w.x;
+        v.im[c] = (R)w.y;
+    }
+    return v;
+}
+
+template <class R> __device__ __forceinline__ void store_canon(double *dst, size_t s, const CVec<R> &v) {
+    f64x2 *p = reinterpret_cast<f64x2 *>(dst + 6 * s);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        f64x2 w;
+        w.x = (double)v.re[c];
+        w.y = (double)v.im[c];
+        p[c] = w;
+    }
+}
+
+template <int SF> __global__ void k_spinor_pack(char *dst, const double *src, size_t n) {
+    typedef typename Natural<SF>::T T;
+    for (size_t s = gtid(); s < n; s += gstride()) SpinorIO<SF, T>::store(dst, n, s, load_canon<T>(src, s));
+}
+
+template <int SF> __global__ void k_spinor_unpack(double *dst, const char *src, size_t n) {
+    typedef typename Natural<SF>::T T;
+    for (size_t s = gtid(); s < n; s += gstride()) store_canon<T>(dst, s, SpinorIO<SF, T>::load(src, n, s));
+}
+
+template <int SFD, int SFS> __global__ void k_spinor_convert(char *dst, const char *src, size_t n) {
+    for (size_t s = gtid(); s < n; s += gstride())
+        SpinorIO<SFD, double>::store(dst, n, s, SpinorIO<SFS, double>::load(src, n, s));
+}
+
+__global__ void k_absmax(const double *src, size_t n, double *partial) {
+    __shared__ double lds[16];
+    double m = 0.0;
+    int bad = 0;
+    for (size_t i = gtid(); i < n; i += gstride()) {
+        double v = src[i];
+        bad |= !__builtin_isfinite(v);
+        m = fmax(m, fabs(v));
+    }
+    if (bad) m = __builtin_inf();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, lds[w]);
+        partial[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_reduce_max(const double *partial, int n, double *out) {
+    __shared__ double lds[16];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, partial[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, lds[w]);
+        *out = m;
+    }
+}
+
+// canonical FP64 links [4][V][3][3] -> packed sub-fields (mu, parity)
+template <int GF> __global__ void k_gauge_pack(char *dst, const double *src, Geom g, const double *absmax) {
+    const size_t V = 2 * (size_t)g.vh;
+    const size_t vh = g.vh;
+    const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
+    const double m = *absmax;
+    const double c = GF == GF_FIX16 ? (m > 0.0 ? 32767.0 / m : 0.0) : (m > 0.0 ? 2147483647.0 / m : 0.0);
+    for (size_t idx = gtid(); idx < 4 * V; idx += gstride()) {
+        const int mu = (int)(idx / V);
+        const size_t site = idx - (size_t)mu * V;
+        size_t r = site;
+        const int x = (int)(r % g.X); r /= g.X;
+        const int y = (int)(r % g.Y); r /= g.Y;
+        const int z = (int)(r % g.Z);
+        const int t = (int)(r / g.Z);
+        const int par = (x + y + z + t) & 1;
+        const size_t s = site >> 1;
+        char *base = dst + (size_t)(2 * mu + par) * sub;
+        const double *u = src + idx * 18;
+        if (GF == GF_F64) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                f64x2 w;
+                w.x = u[2 * k];
+                w.y = u[2 * k + 1];
+                st<f64x2>(base + k * 16 * vh + 16 * s, w);
+            }
+        } else if (GF == GF_F32) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                f32x4 w;
+                w.x = (float)u[4 * k]; w.y = (float)u[4 * k + 1]; w.z = (float)u[4 * k + 2]; w.w = (float)u[4 * k + 3];
+                st<f32x4>(base + k * 16 * vh + 16 * s, w);
+            }
+            f32x2 t2;
+            t2.x = (float)u[16];
+            t2.y = (float)u[17];
+            st<f32x2>(base + 64 * vh + 8 * s, t2);
+        } else if (GF == GF_FIX16) {
+            unsigned q[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++) q[k] = (unsigned)(int)__builtin_rint(u[k] * c) & 0xffffu;
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                u32x4 w;
+                w.x = q[8 * k + 0] | (q[8 * k + 1] << 16);
+                w.y = q[8 * k + 2] | (q[8 * k + 3] << 16);
+                w.z = q[8 * k + 4] | (q[8 * k + 5] << 16);
+                w.w = q[8 * k + 6] | (q[8 * k + 7] << 16);
+                st<u32x4>(base + k * 16 * vh + 16 * s, w);
+            }
+            st<unsigned>(base + 32 * vh + 4 * s, q[16] | (q[17] << 16));
+        } else {  // GF_FIX32
+            unsigned q[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++) q[k] = (unsigned)(int)__builtin_rint(u[k] * c);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                u32x4 w;
+                w.x = q[4 * k]; w.y = q[4 * k + 1]; w.z = q[4 * k + 2]; w.w = q[4 * k + 3];
+                st<u32x4>(base + k * 16 * vh + 16 * s, w);
+            }
+            u32x2 t2;
+            t2.x = q[16];
+            t2.y = q[17];
+            st<u32x2>(base + 64 * vh + 8 * s, t2);
+        }
+    }
+}
+
+__global__ void k_norm2_f64(const char *v, size_t n, double *partial) {
+    __shared__ double lds[16];
+    double acc = 0.0;
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<double> a = SpinorIO<SF_F64, double>::load(v, n, s);
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc += a.re[c] * a.re[c] + a.im[c] * a.im[c];
+    }
+    double w[1] = {acc};
+    block_sum<1>(w, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = w[0];
+}
+
+// ---------------------------------------------------------------------------
+// CG vector updates
+// ---------------------------------------------------------------------------
+
+template <int SF, class R>
+__global__ void k_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, double *partial, Guard gd) {
+    __shared__ double lds[32];
+    if (!gd.pass()) return;
+    const R a = (R)(*alpha);
+    double acc[2] = {0.0, 0.0};
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<R> ro = SpinorIO<SF, R>::load(r, n, s);
+        CVec<R> av = SpinorIO<SF, R>::load(ap, n, s);
+        CVec<R> rn;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            rn.re[c] = fma(-a, av.re[c], ro.re[c]);
+            rn.im[c] = fma(-a, av.im[c], ro.im[c]);
+        }
+        CVec<R> o = SpinorIO<SF, R>::store(r, n, s, rn);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[0] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+            acc[1] += (double)o.re[c] * (double)ro.re[c] + (double)o.im[c] * (double)ro.im[c];
+        }
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = acc[0];
+        partial[2 * blockIdx.x + 1] = acc[1];
+    }
+}
+
+template <int SF, class R>
+__global__ void k_cg_pupdate(char *pd, const char *r, const char *ps, const SolverCtrl *ctrl, size_t n, Guard gd) {
+    if (!gd.pass()) return;
+    const R ar = (R)ctrl->pa_re, ai = (R)ctrl->pa_im, b = (R)ctrl->pb;
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
+        CVec<R> pv = SpinorIO<SF, R>::load(ps, n, s);
+        CVec<R> o;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            o.re[c] = fma(ar, rv.re[c], fma(-ai, rv.im[c], b * pv.re[c]));
+            o.im[c] = fma(ar, rv.im[c], fma(ai, rv.re[c], b * pv.im[c]));
+        }
+        SpinorIO<SF, R>::store(pd, n, s, o);
+    }
+}
+
+template <int SF, class R>
+__global__ void k_flush_x(char *x64, SpinorList p, int count, const double *alpha_buf, size_t n, Guard gd) {
+    if (!gd.pass()) return;
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<double> x = SpinorIO<SF_F64, double>::load(x64, n, s);
+        for (int i = 0; i < count; i++) {
+            const double a = alpha_buf[i];
+            CVec<R> pv = SpinorIO<SF, R>::load(p.p[i], n, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                x.re[c] = fma(a, (double)pv.re[c], x.re[c]);
+                x.im[c] = fma(a, (double)pv.im[c], x.im[c]);
+            }
+        }
+        SpinorIO<SF_F64, double>::store(x64, n, s, x);
+    }
+}
+
+template <int SF, class R>
+__global__ void k_ru_convert(char *rs, const char *r64, const char *p, const char *ap, const double *alpha, size_t n,
+                             double *partial, Guard gd) {
+    __shared__ double lds[64];
+    if (!gd.pass()) return;
+    const R a = alpha ? (R)(*alpha) : R(0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<double> rt = SpinorIO<SF_F64, double>::load(r64, n, s);
+        CVec<R> rold;
+        if (ap) rold = SpinorIO<SF, R>::load(rs, n, s);
+        CVec<R> rn;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            rn.re[c] = (R)rt.re[c];
+            rn.im[c] = (R)rt.im[c];
+        }
+        CVec<R> o = SpinorIO<SF, R>::store(rs, n, s, rn);
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[0] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+        if (p) {
+            CVec<R> pv = SpinorIO<SF, R>::load(p, n, s);
+            // <r, p> = sum conj(r) p
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[1] += (double)o.re[c] * (double)pv.re[c] + (double)o.im[c] * (double)pv.im[c];
+                acc[2] += (double)o.re[c] * (double)pv.im[c] - (double)o.im[c] * (double)pv.re[c];
+            }
+        }
+        if (ap) {
+            // the previous iterated residual r_k = r_{k+1}^iter + alpha A p_k
+            CVec<R> av = SpinorIO<SF, R>::load(ap, n, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double pr = (double)rold.re[c] + (double)a * (double)av.re[c];
+                const double pi = (double)rold.im[c] + (double)a * (double)av.im[c];
+                acc[3] += (double)o.re[c] * pr + (double)o.im[c] * pi;
+            }
+        }
+    }
+    block_sum<4>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) partial[4 * blockIdx.x + k] = acc[k];
+    }
+}
+
+// one launch for every shifted system still being updated (Sec. 3.2)
+template <int SF, class R>
+__global__ void k_shift_update(SpinorList x64, SpinorList p, const char *r, const SolverCtrl *ctrl, int nshift, size_t n,
+                               Guard gd) {
+    if (!gd.pass()) return;
+    const int mask = ctrl->e_mask;
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
+        for (int i = 1; i < nshift; i++) {
+            if (!((mask >> i) & 1)) continue;
+            const double ai = ctrl->alpha_i[i];
+            const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
+            CVec<R> pv = SpinorIO<SF, R>::load(p.p[i], n, s);
+            CVec<double> xv = SpinorIO<SF_F64, double>::load(x64.p[i], n, s);
+            CVec<R> pn;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                xv.re[c] = fma(ai, (double)pv.re[c], xv.re[c]);
+                xv.im[c] = fma(ai, (double)pv.im[c], xv.im[c]);
+                pn.re[c] = fma(zi, rv.re[c], bi * pv.re[c]);
+                pn.im[c] = fma(zi, rv.im[c], bi * pv.im[c]);
+            }
+            SpinorIO<SF_F64, double>::store(x64.p[i], n, s, xv);
+            SpinorIO<SF, R>::store(p.p[i], n, s, pn);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched (nrhs independent systems) vector updates
+// ---------------------------------------------------------------------------
+
+template <int SF, class R>
+__global__ void k_bcg_axpy(char *r, const char *ap, const SolverCtrl *ctrl, size_t n, size_t fs, int nrhs,
+                           double *partial, Guard gd) {
+    __shared__ double lds[32];
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        double acc[2] = {0.0, 0.0};
+        if (ctrl->bactive[j]) {
+            const R a = (R)ctrl->balpha[j];
+            char *rj = r + j * fs;
+            const char *aj = ap + j * fs;
+            for (size_t s = gtid(); s < n; s += gstride()) {
+                CVec<R> ro = SpinorIO<SF, R>::load(rj, n, s);
+                CVec<R> av = SpinorIO<SF, R>::load(aj, n, s);
+                CVec<R> rn;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    rn.re[c] = fma(-a, av.re[c], ro.re[c]);
+                    rn.im[c] = fma(-a, av.im[c], ro.im[c]);
+                }
+                CVec<R> o = SpinorIO<SF, R>::store(rj, n, s, rn);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    acc[0] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+                    acc[1] += (double)o.re[c] * (double)ro.re[c] + (double)o.im[c] * (double)ro.im[c];
+                }
+            }
+        }
+        block_sum<2>(acc, lds);
+        if (threadIdx.x == 0) {
+            partial[((size_t)blockIdx.x * nrhs + j) * 2] = acc[0];
+            partial[((size_t)blockIdx.x * nrhs + j) * 2 + 1] = acc[1];
+        }
+        __syncthreads();
+    }
+}
+
+template <int SF, class R>
+__global__ void k_bcg_pupdate(char *pd, const char *r, const char *ps, const SolverCtrl *ctrl, size_t n, size_t fs,
+                              int nrhs, Guard gd) {
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        if (!ctrl->bactive[j]) continue;
+        const R ar = (R)ctrl->bpa_re[j], ai = (R)ctrl->bpa_im[j], b = (R)ctrl->bpb[j];
+        for (size_t s = gtid(); s < n; s += gstride()) {
+            CVec<R> rv = SpinorIO<SF, R>::load(r + j * fs, n, s);
+            CVec<R> pv = SpinorIO<SF, R>::load(ps + j * fs, n, s);
+            CVec<R> o;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                o.re[c] = fma(ar, rv.re[c], fma(-ai, rv.im[c], b * pv.re[c]));
+                o.im[c] = fma(ar, rv.im[c], fma(ai, rv.re[c], b * pv.im[c]));
+            }
+            SpinorIO<SF, R>::store(pd + j * fs, n, s, o);
+        }
+    }
+}
+
+template <int SF, class R>
+__global__ void k_bflush_x(char *x64, size_t fs64, SpinorList p, int count, const SolverCtrl *ctrl, size_t n, size_t fs,
+                           int nrhs, Guard gd) {
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        char *xj = x64 + j * fs64;
+        for (size_t s = gtid(); s < n; s += gstride()) {
+            CVec<double> x = SpinorIO<SF_F64, double>::load(xj, n, s);
+            for (int i = 0; i < count; i++) {
+                const double a = ctrl->balpha_buf[i][j];
+                if (a == 0.0) continue;
+                CVec<R> pv = SpinorIO<SF, R>::load(p.p[i] + j * fs, n, s);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    x.re[c] = fma(a, (double)pv.re[c], x.re[c]);
+                    x.im[c] = fma(a, (double)pv.im[c], x.im[c]);
+                }
+            }
+            SpinorIO<SF_F64, double>::store(xj, n, s, x);
+        }
+    }
+}
+
+template <int SF, class R>
+__global__ void k_bru_convert(char *rs, const char *r64, size_t fs64, const char *p, const char *ap,
+                              const SolverCtrl *ctrl, size_t n, size_t fs, int nrhs, double *partial, Guard gd) {
+    __shared__ double lds[64];
+    if (!gd.pass()) return;
+    for (int j = 0; j < nrhs; j++) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const R a = (R)ctrl->balpha[j];
+        char *rsj = rs + j * fs;
+        for (size_t s = gtid(); s < n; s += gstride()) {
+            CVec<double> rt = SpinorIO<SF_F64, double>::load(r64 + j * fs64, n, s);
+            CVec<R> rold;
+            if (ap) rold = SpinorIO<SF, R>::load(rsj, n, s);
+            CVec<R> rn;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                rn.re[c] = (R)rt.re[c];
+                rn.im[c] = (R)rt.im[c];
+            }
+            CVec<R> o = SpinorIO<SF, R>::store(rsj, n, s, rn);
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[0] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+            if (p) {
+                CVec<R> pv = SpinorIO<SF, R>::load(p + j * fs, n, s);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    acc[1] += (double)o.re[c] * (double)pv.re[c] + (double)o.im[c] * (double)pv.im[c];
+                    acc[2] += (double)o.re[c] * (double)pv.im[c] - (double)o.im[c] * (double)pv.re[c];
+                }
+            }
+            if (ap) {
+                CVec<R> av = SpinorIO<SF, R>::load(ap + j * fs, n, s);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const double pr = (double)rold.re[c] + (double)a * (double)av.re[c];
+                    const double pi = (double)rold.im[c] + (double)a * (double)av.im[c];
+                    acc[3] += (double)o.re[c] * pr + (double)o.im[c] * pi;
+                }
+            }
+        }
+        block_sum<4>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) partial[((size_t)blockIdx.x * nrhs + j) * 4 + k] = acc[k];
+        }
+        __syncthreads();
+    }
+}
+
+// dispatch on the sloppy triplet's spinor format and compute precision
+#define HISQ_DISPATCH_SC(sf, compute, CALL)                                           \
+    do {                                                                              \
+        switch ((sf) * 2 + ((compute) == 64)) {                                       \
+        case SF_F64 * 2 + 1: { constexpr int SFc = SF_F64; typedef double Rc; CALL; } break;   \
+        case SF_F32 * 2 + 0: { constexpr int SFc = SF_F32; typedef float Rc; CALL; } break;    \
+        case SF_HALF16 * 2 + 0: { constexpr int SFc = SF_HALF16; typedef float Rc; CALL; } break; \
+        case SF_INT20 * 2 + 0: { constexpr int SFc = SF_INT20; typedef float Rc; CALL; } break; \
+        case SF_INT30 * 2 + 1: { constexpr int SFc = SF_INT30; typedef double Rc; CALL; } break; \
+        case SF_INT30 * 2 + 0: { constexpr int SFc = SF_INT30; typedef float Rc; CALL; } break; \
+        default: return hipErrorInvalidValue;                                         \
+        }                                                                             \
+    } while (0)
+
+#define HISQ_DISPATCH_SF(sf, CALL)                                                    \
+    do {                                                                              \
+        switch (sf) {                                                                 \
+        case SF_F64: { constexpr int SFc = SF_F64; CALL; } break;                    \
+        case SF_F32: { constexpr int SFc = SF_F32; CALL; } break;                    \
+        case SF_HALF16: { constexpr int SFc = SF_HALF16; CALL; } break;              \
+        case SF_INT20: { constexpr int SFc = SF_INT20; CALL; } break;                \
+        case SF_INT30: { constexpr int SFc = SF_INT30; CALL; } break;                \
+        default: return hipErrorInvalidValue;                                         \
+        }                                                                             \
+    } while (0)
+
+}  // namespace
+
+hipError_t launch_spinor_pack(char *dst, const double *src, size_t n, int sf, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    HISQ_DISPATCH_SF(sf, hipLaunchKernelGGL((k_spinor_pack<SFc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, dst, src, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_unpack(double *dst, const char *src, size_t n, int sf, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    HISQ_DISPATCH_SF(sf, hipLaunchKernelGGL((k_spinor_unpack<SFc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, dst, src, n));
+    return hipGetLastError();
+}
+
+namespace {
+template <int SFD>
+hipError_t convert_from(char *dst, const char *src, int sf_src, size_t n, hipStream_t st) {
+    HISQ_DISPATCH_SF(sf_src, hipLaunchKernelGGL((k_spinor_convert<SFD, SFc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, dst, src, n));
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_spinor_convert(char *dst, int sf_dst, const char *src, int sf_src, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    switch (sf_dst) {
+    case SF_F64: return convert_from<SF_F64>(dst, src, sf_src, n, st);
+    case SF_F32: return convert_from<SF_F32>(dst, src, sf_src, n, st);
+    case SF_HALF16: return convert_from<SF_HALF16>(dst, src, sf_src, n, st);
+    case SF_INT20: return convert_from<SF_INT20>(dst, src, sf_src, n, st);
+    case SF_INT30: return convert_from<SF_INT30>(dst, src, sf_src, n, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_absmax(const double *src, size_t n, double *partial, int *nblocks, hipStream_t st) {
+    const int nb = blas_blocks(n);
+    *nblocks = nb;
+    hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(BLAS_BLOCK), 0, st, src, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_max(const double *partial, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(1024), 0, st, partial, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_pack(char *dst, const double *src, const Geom &g, int gf, const double *absmax, hipStream_t st) {
+    const size_t n = 8 * (size_t)g.vh;
+    const int nb = blas_blocks(n);
+    switch (gf) {
+    case GF_F64: hipLaunchKernelGGL((k_gauge_pack<GF_F64>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
+    case GF_F32: hipLaunchKernelGGL((k_gauge_pack<GF_F32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
+    case GF_FIX16: hipLaunchKernelGGL((k_gauge_pack<GF_FIX16>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
+    case GF_FIX32: hipLaunchKernelGGL((k_gauge_pack<GF_FIX32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nblocks, hipStream_t st) {
+    const int nb = blas_blocks(n);
+    *nblocks = nb;
+    hipLaunchKernelGGL(k_norm2_f64, dim3(nb), dim3(BLAS_BLOCK), 0, st, v, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, int sf, int compute, double *partial,
+                          Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_axpy<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r, ap, alpha, n, partial, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, size_t n, int sf,
+                             int compute, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_pupdate<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, p_dst, r, p_src, ctrl, n, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const double *alpha_buf, size_t n, int sf,
+                          int compute, Guard gd, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_flush_x<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, count, alpha_buf, n, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const char *ap, const double *alpha, size_t n,
+                             int sf, int compute, double *partial, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_ru_convert<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r_s, r64, p, ap, alpha, n, partial, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
+                               int nshift, size_t n, int sf, int compute, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_bcg_axpy(char *r, const char *ap, const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs, int sf,
+                           int compute, double *partial, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_bcg_axpy<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r, ap, ctrl, n, stride, nrhs, partial, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_bcg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, size_t n,
+                              size_t stride, int nrhs, int sf, int compute, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_bcg_pupdate<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, p_dst, r, p_src, ctrl, n, stride, nrhs, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_bflush_x(char *x64, size_t stride64, const SpinorList &p, int count, const SolverCtrl *ctrl,
+                           size_t n, size_t stride, int nrhs, int sf, int compute, Guard gd, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_bflush_x<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, stride64, p, count, ctrl, n, stride, nrhs, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_bru_convert(char *r_s, const char *r64, size_t stride64, const char *p, const char *ap,
+                              const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs, int sf, int compute,
+                              double *partial, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_bru_convert<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r_s, r64, stride64, p, ap, ctrl, n, stride, nrhs, partial, gd));
+    return hipGetLastError();
+}
+
+}  // namespace hisq

@@ -1,0 +1,439 @@
+// hisq_device.h -- device-side building blocks of libhisq for gfx950:
+// storage codecs (unpack to IEEE registers, pack back), structure-of-arrays
+// field addressing, lattice geometry, the XCD-aware block order and the
+// deterministic wavefront/block reductions.
+//
+// Field layouts in HBM (all little-endian):
+//  * A spinor field of n sites is stored as planes of 16-byte chunks: chunk k
+//    of site s lives at byte k*16*n + 16*s; formats whose site record is not
+//    a multiple of 16 bytes keep the last 8 bytes in a trailing plane at
+//    K*16*n + 8*s.  Each lane of a wavefront therefore issues 16- or 8-byte
+//    loads and a wavefront touches one contiguous 1 KiB (512 B) span.
+//      F64    48 B: 3 planes (colour c: re, im)
+//      F32    24 B: plane 0 (c0re c0im c1re c1im), tail (c2re c2im)
+//      HALF16 16 B: plane 0 (q0|q1<<16, q2|q3<<16, q4|q5<<16, FP32 site max)
+//      INT20  16 B: plane 0 (the four words of the 20-bit record)
+//      INT30  24 B: plane 0 (words 0-3), tail (words 4-5)
+//  * A link field holds 4*V matrices as 8 sub-fields (direction mu, parity p)
+//    of Vh matrices each, sub-field index mu*2+p, site = checkerboard index;
+//    within a sub-field the 18 reals (row-major, re/im interleaved) are cut
+//    into 16-byte planes plus a tail plane:
+//      F64   144 B: 9 planes (one complex element each)
+//      F32    72 B: 4 planes (2 elements each) + 8-byte tail (element 8)
+//      FIX16  36 B: 2 planes (4 elements each) + 4-byte tail (element 8)
+//      FIX32  72 B: 4 planes + 8-byte tail
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hisq {
+
+enum SpinorFmt { SF_F64 = 0, SF_F32 = 1, SF_HALF16 = 2, SF_INT20 = 3, SF_INT30 = 4 };
+enum GaugeFmt { GF_F64 = 0, GF_F32 = 1, GF_FIX16 = 2, GF_FIX32 = 3 };
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// bytes per site record / per link matrix
+__host__ __device__ constexpr int spinor_site_bytes(int sf) {
+    return sf == SF_F64 ? 48 : (sf == SF_F32 || sf == SF_INT30) ? 24 : 16;
+}
+__host__ __device__ constexpr int gauge_matrix_bytes(int gf) {
+    return gf == GF_F64 ? 144 : gf == GF_FIX16 ? 36 : 72;
+}
+
+// ---------------------------------------------------------------------------
+// register types
+// ---------------------------------------------------------------------------
+
+template <class R> struct CVec {
+    R re[3], im[3];
+};
+
+template <class R> struct Mat {
+    R re[9], im[9];  // element (a,b) at 3a+b
+};
+
+template <class R> __device__ __forceinline__ void cvec_zero(CVec<R> &v) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) v.re[a] = v.im[a] = R(0);
+}
+
+// acc += U v
+template <class R> __device__ __forceinline__ void mv_add(CVec<R> &acc, const Mat<R> &U, const CVec<R> &v) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            acc.re[a] = fma(U.re[3 * a + b], v.re[b], acc.re[a]);
+            acc.re[a] = fma(-U.im[3 * a + b], v.im[b], acc.re[a]);
+            acc.im[a] = fma(U.re[3 * a + b], v.im[b], acc.im[a]);
+            acc.im[a] = fma(U.im[3 * a + b], v.re[b], acc.im[a]);
+        }
+    }
+}
+
+// acc -= U^dagger v
+template <class R> __device__ __forceinline__ void mdv_sub(CVec<R> &acc, const Mat<R> &U, const CVec<R> &v) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            // conj(U[b][a]) * v[b] = (ur - i ui)(vr + i vi)
+            acc.re[a] = fma(-U.re[3 * b + a], v.re[b], acc.re[a]);
+            acc.re[a] = fma(-U.im[3 * b + a], v.im[b], acc.re[a]);
+            acc.im[a] = fma(-U.re[3 * b + a], v.im[b], acc.im[a]);
+            acc.im[a] = fma(U.im[3 * b + a], v.re[b], acc.im[a]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// raw loads / stores
+// ---------------------------------------------------------------------------
+
+template <class T> __device__ __forceinline__ T ld(const char *p) { return *reinterpret_cast<const T *>(p); }
+// streaming load (links are read once per application): non-temporal hint
+template <class T> __device__ __forceinline__ T ld_nt(const char *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+}
+template <class T> __device__ __forceinline__ void st(char *p, T v) { *reinterpret_cast<T *>(p) = v; }
+
+__device__ __forceinline__ int sext16(unsigned u) { return (int)(short)(unsigned short)(u & 0xffffu); }
+__device__ __forceinline__ int sext20(unsigned u) { return (int)((u & 0xfffffu) ^ 0x80000u) - 0x80000; }
+__device__ __forceinline__ int sext30(unsigned u) { return (int)((u & 0x3fffffffu) ^ 0x20000000u) - 0x20000000; }
+
+// 2^(e-127) for an 8-bit biased exponent e in [1,254]
+__device__ __forceinline__ float pow2_f32(unsigned e) { return __uint_as_float(e << 23); }
+__device__ __forceinline__ double pow2_f64(unsigned e) {
+    return __longlong_as_double((long long)((unsigned long long)(e + 896u) << 52));
+}
+
+// ---------------------------------------------------------------------------
+// spinor codecs
+// ---------------------------------------------------------------------------
+
+template <int SF, class R> struct SpinorIO;
+
+template <class R> struct SpinorIO<SF_F64, R> {
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t n, size_t s) {
+        CVec<R> v;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            f64x2 w = ld<f64x2>(base + c * 16 * n + 16 * s);
+            v.re[c] = (R)w.x;
+            v.im[c] = (R)w.y;
+        }
+        return v;
+    }
+    // stores v; returns the value as stored (what a later load returns)
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t n, size_t s, const CVec<R> &v) {
+        CVec<R> o;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            f64x2 w;
+            w.x = (double)v.re[c];
+            w.y = (double)v.im[c];
+            st<f64x2>(base + c * 16 * n + 16 * s, w);
+            o.re[c] = (R)w.x;
+            o.im[c] = (R)w.y;
+        }
+        return o;
+    }
+};
+
+template <class R> struct SpinorIO<SF_F32, R> {
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t n, size_t s) {
+        f32x4 a = ld<f32x4>(base + 16 * s);
+        f32x2 b = ld<f32x2>(base + 16 * n + 8 * s);
+        CVec<R> v;
+        v.re[0] = a.x; v.im[0] = a.y; v.re[1] = a.z; v.im[1] = a.w; v.re[2] = b.x; v.im[2] = b.y;
+        return v;
+    }
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t n, size_t s, const CVec<R> &v) {
+        f32x4 a;
+        f32x2 b;
+        a.x = (float)v.re[0]; a.y = (float)v.im[0]; a.z = (float)v.re[1]; a.w = (float)v.im[1];
+        b.x = (float)v.re[2]; b.y = (float)v.im[2];
+        st<f32x4>(base + 16 * s, a);
+        st<f32x2>(base + 16 * n + 8 * s, b);
+        CVec<R> o;
+        o.re[0] = a.x; o.im[0] = a.y; o.re[1] = a.z; o.im[1] = a.w; o.re[2] = b.x; o.im[2] = b.y;
+        return o;
+    }
+};
+
+// QUDA half: q = rint(v * (32767/M)) with M the FP32 site max; v = q * (M * (1/32767)).
+// A site whose M is zero or whose 32767/M overflows stores zeros with M = 0.
+template <class R> struct SpinorIO<SF_HALF16, R> {
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
+        float d = __uint_as_float(w.w) * (1.0f / 32767.0f);
+        CVec<R> v;
+        v.re[0] = (float)sext16(w.x) * d; v.im[0] = (float)sext16(w.x >> 16) * d;
+        v.re[1] = (float)sext16(w.y) * d; v.im[1] = (float)sext16(w.y >> 16) * d;
+        v.re[2] = (float)sext16(w.z) * d; v.im[2] = (float)sext16(w.z >> 16) * d;
+        return v;
+    }
+    static __device__ __forceinline__ u32x4 encode(const CVec<R> &vin) {
+        float f[6] = {(float)vin.re[0], (float)vin.im[0], (float)vin.re[1],
+                      (float)vin.im[1], (float)vin.re[2], (float)vin.im[2]};
+        float m = fabsf(f[0]);
+#pragma unroll
+        for (int k = 1; k < 6; k++) m = fmaxf(m, fabsf(f[k]));
+        float c = 32767.0f / m;
+        u32x4 w;
+        if (!(m > 0.0f) || !__builtin_isfinite(c)) {
+            w.x = w.y = w.z = w.w = 0u;
+            return w;
+        }
+        unsigned q[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) q[k] = (unsigned)(int)__builtin_rintf(f[k] * c);
+        w.x = (q[0] & 0xffffu) | (q[1] << 16);
+        w.y = (q[2] & 0xffffu) | (q[3] << 16);
+        w.z = (q[4] & 0xffffu) | (q[5] << 16);
+        w.w = __float_as_uint(m);
+        return w;
+    }
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t, size_t s) {
+        return decode(ld<u32x4>(base + 16 * s));
+    }
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t, size_t s, const CVec<R> &v) {
+        u32x4 w = encode(v);
+        st<u32x4>(base + 16 * s, w);
+        return decode(w);
+    }
+};
+
+// 20-bit shared exponent (Appendix A): E = biased exponent of fl(M/(2^19-1)) + 1,
+// q = rint(v * 2^(127-E)), v = q * 2^(E-127).
+template <class R> struct SpinorIO<SF_INT20, R> {
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
+        float sc = pow2_f32(w.w >> 24);
+        CVec<R> v;
+        v.re[0] = (float)sext20(w.x) * sc;
+        v.im[0] = (float)sext20(((w.x >> 20) << 8) | (w.y & 0xffu)) * sc;
+        v.re[1] = (float)sext20(w.y >> 8) * sc;
+        v.im[1] = (float)sext20(((w.y >> 28) << 16) | (w.z & 0xffffu)) * sc;
+        v.re[2] = (float)sext20(((w.z >> 16) << 4) | (w.w & 0xfu)) * sc;
+        v.im[2] = (float)sext20(w.w >> 4) * sc;
+        return v;
+    }
+    static __device__ __forceinline__ u32x4 encode(const CVec<R> &vin) {
+        float f[6] = {(float)vin.re[0], (float)vin.im[0], (float)vin.re[1],
+                      (float)vin.im[1], (float)vin.re[2], (float)vin.im[2]};
+        float m = fabsf(f[0]);
+#pragma unroll
+        for (int k = 1; k < 6; k++) m = fmaxf(m, fabsf(f[k]));
+        float t = m / 524287.0f;
+        unsigned e = ((__float_as_uint(t) >> 23) & 0xffu) + 1u;
+        e = e > 254u ? 254u : e;
+        float inv = __uint_as_float((254u - e) << 23);
+        unsigned u[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) u[k] = (unsigned)(int)__builtin_rintf(f[k] * inv) & 0xfffffu;
+        u32x4 w;
+        w.x = u[0] | ((u[1] >> 8) << 20);
+        w.y = (u[1] & 0xffu) | (u[2] << 8) | ((u[3] >> 16) << 28);
+        w.z = (u[3] & 0xffffu) | ((u[4] >> 4) << 16);
+        w.w = (u[4] & 0xfu) | (u[5] << 4) | (e << 24);
+        return w;
+    }
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t, size_t s) {
+        return decode(ld<u32x4>(base + 16 * s));
+    }
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t, size_t s, const CVec<R> &v) {
+        u32x4 w = encode(v);
+        st<u32x4>(base + 16 * s, w);
+        return decode(w);
+    }
+};
+
+// 30-bit shared exponent: the 20-bit rule with scale 2^29-1 in FP64.
+template <class R> struct SpinorIO<SF_INT30, R> {
+    static __device__ __forceinline__ CVec<R> decode(u32x4 a, u32x2 b) {
+        R sc = (R)pow2_f64((b.y >> 20) & 0xffu);
+        CVec<R> v;
+        v.re[0] = (R)sext30(a.x) * sc;
+        v.im[0] = (R)sext30(((a.x >> 30) << 28) | (a.y & 0x0fffffffu)) * sc;
+        v.re[1] = (R)sext30(((a.y >> 28) << 26) | (a.z & 0x03ffffffu)) * sc;
+        v.im[1] = (R)sext30(((a.z >> 26) << 24) | (a.w & 0x00ffffffu)) * sc;
+        v.re[2] = (R)sext30(((a.w >> 24) << 22) | (b.x & 0x003fffffu)) * sc;
+        v.im[2] = (R)sext30(((b.x >> 22) << 20) | (b.y & 0x000fffffu)) * sc;
+        return v;
+    }
+    static __device__ __forceinline__ void encode(const CVec<R> &vin, u32x4 &a, u32x2 &b) {
+        double f[6] = {(double)vin.re[0], (double)vin.im[0], (double)vin.re[1],
+                       (double)vin.im[1], (double)vin.re[2], (double)vin.im[2]};
+        double m = fabs(f[0]);
+#pragma unroll
+        for (int k = 1; k < 6; k++) m = fmax(m, fabs(f[k]));
+        double t = m / 536870911.0;
+        int e = 1;
+        if (t > 0.0) {
+            int field = (int)((__double_as_longlong(t) >> 52) & 0x7ff);
+            e = field - 895;  // (field - 1023) + 1 + 127
+            e = e < 1 ? 1 : (e > 254 ? 254 : e);
+        }
+        double inv = pow2_f64((unsigned)(254 - e));  // 2^(127-e)
+        unsigned u[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) u[k] = (unsigned)(int)__builtin_rint(f[k] * inv) & 0x3fffffffu;
+        a.x = u[0] | ((u[1] >> 28) << 30);
+        a.y = (u[1] & 0x0fffffffu) | ((u[2] >> 26) << 28);
+        a.z = (u[2] & 0x03ffffffu) | ((u[3] >> 24) << 26);
+        a.w = (u[3] & 0x00ffffffu) | ((u[4] >> 22) << 24);
+        b.x = (u[4] & 0x003fffffu) | ((u[5] >> 20) << 22);
+        b.y = (u[5] & 0x000fffffu) | ((unsigned)e << 20);
+    }
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t n, size_t s) {
+        return decode(ld<u32x4>(base + 16 * s), ld<u32x2>(base + 16 * n + 8 * s));
+    }
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t n, size_t s, const CVec<R> &v) {
+        u32x4 a;
+        u32x2 b;
+        encode(v, a, b);
+        st<u32x4>(base + 16 * s, a);
+        st<u32x2>(base + 16 * n + 8 * s, b);
+        return decode(a, b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// gauge codecs: load one 3x3 complex matrix of sub-field `sub` (Vh matrices)
+// ---------------------------------------------------------------------------
+
+template <int GF, class R> struct GaugeIO;
+
+template <class R> struct GaugeIO<GF_F64, R> {
+    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R) {
+        Mat<R> U;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            f64x2 w = ld_nt<f64x2>(sub + k * 16 * vh + 16 * s);
+            U.re[k] = (R)w.x;
+            U.im[k] = (R)w.y;
+        }
+        return U;
+    }
+};
+
+template <class R> struct GaugeIO<GF_F32, R> {
+    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R) {
+        Mat<R> U;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            f32x4 w = ld_nt<f32x4>(sub + k * 16 * vh + 16 * s);
+            U.re[2 * k] = w.x; U.im[2 * k] = w.y; U.re[2 * k + 1] = w.z; U.im[2 * k + 1] = w.w;
+        }
+        f32x2 t = ld_nt<f32x2>(sub + 64 * vh + 8 * s);
+        U.re[8] = t.x;
+        U.im[8] = t.y;
+        return U;
+    }
+};
+
+// 16-bit fixed point: u = q * g, g = (compute precision)(max/32767)
+template <class R> struct GaugeIO<GF_FIX16, R> {
+    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R g) {
+        Mat<R> U;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            u32x4 w = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+            unsigned ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                U.re[4 * k + j] = (R)sext16(ws[j]) * g;
+                U.im[4 * k + j] = (R)sext16(ws[j] >> 16) * g;
+            }
+        }
+        unsigned t = ld_nt<unsigned>(sub + 32 * vh + 4 * s);
+        U.re[8] = (R)sext16(t) * g;
+        U.im[8] = (R)sext16(t >> 16) * g;
+        return U;
+    }
+};
+
+template <class R> struct GaugeIO<GF_FIX32, R> {
+    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R g) {
+        Mat<R> U;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            u32x4 w = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+            U.re[2 * k] = (R)(int)w.x * g; U.im[2 * k] = (R)(int)w.y * g;
+            U.re[2 * k + 1] = (R)(int)w.z * g; U.im[2 * k + 1] = (R)(int)w.w * g;
+        }
+        u32x2 t = ld_nt<u32x2>(sub + 64 * vh + 8 * s);
+        U.re[8] = (R)(int)t.x * g;
+        U.im[8] = (R)(int)t.y * g;
+        return U;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// lattice geometry (checkerboarded, X even)
+// ---------------------------------------------------------------------------
+
+struct Geom {
+    int X, Y, Z, T;
+    int X2;        // X/2
+    int vh;        // sites per parity
+    int sy, sz, st;  // checkerboard strides of +y, +z, +t: X2, X2*Y, X2*Y*Z
+};
+
+// ---------------------------------------------------------------------------
+// launch order and reductions
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b%8).
+// Remap so that every XCD sweeps one contiguous eighth of the sites in order:
+// a site's +-1/+-3 neighbours are then read from the same XCD's L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+    return (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// deterministic block sum of NV doubles; result valid in thread 0
+template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) lds[w * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            double s = 0.0;
+            for (int j = 0; j < nw; j++) s += lds[j * NV + k];
+            v[k] = s;
+        }
+    }
+}
+
+// Solver iteration guard: a kernel that belongs to iteration j of a block of
+// iterations runs iff j < *stop (strict) or j <= *stop; the solver's scalar
+// kernels lower *stop to end a block early (reliable update, convergence).
+struct Guard {
+    const int *stop;
+    int j;
+    int strict;
+    __device__ __forceinline__ bool pass() const {
+        if (!stop) return true;
+        int s = *(volatile const int *)stop;
+        return strict ? (j < s) : (j <= s);
+    }
+};
+
+}  // namespace hisq

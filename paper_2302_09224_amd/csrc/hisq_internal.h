@@ -1,0 +1,174 @@
+// hisq_internal.h -- declarations shared by the translation units of libhisq
+// (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hisq.h"
+#include "hisq_device.h"
+
+namespace hisq {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+hisq_status set_error(hisq_status st, const char *fmt, ...);
+
+#define HISQ_TRY_HIP(call)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return ::hisq::set_error(HISQ_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                                     __FILE__, __LINE__);                                       \
+    } while (0)
+
+#define HISQ_TRY(expr)                      \
+    do {                                    \
+        hisq_status s_ = (expr);            \
+        if (s_ != HISQ_OK) return s_;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry and sizes
+// ---------------------------------------------------------------------------
+
+bool dims_ok(const int dims[4]);
+Geom make_geom(const int dims[4]);
+size_t spinor_field_bytes(size_t nsites, int sf);
+size_t gauge_field_bytes(const int dims[4], int gf);
+bool triplet_ok(const hisq_fmt &f);
+bool aligned16(const void *p);
+
+// ---------------------------------------------------------------------------
+// Dslash
+// ---------------------------------------------------------------------------
+
+enum { RED_NONE = 0, RED_DOT_X = 1, RED_NORM = 2 };
+
+struct DslashArgs {
+    char *out;
+    const char *in;
+    const char *fat;
+    const char *lng;
+    const char *x;   // optional: out += a*x (format and parity of out)
+    const char *y;   // optional: out += c*y
+    double a, b, c;  // out = b*D(in) + a*x + c*y
+    double gfat, glong;  // fixed-point decode steps (max/Q), unused for IEEE formats
+    Geom g;
+    int parity;      // parity of the output sites
+    int red;         // RED_*: per-block partial of Re<x,out> or |out|^2 (values as stored)
+    double *partial;
+    Guard guard;
+    size_t field_stride;  // batched: bytes between consecutive right-hand-side fields
+    int nrhs;             // batched: right-hand sides in this launch
+};
+
+// blocks of a Dslash launch over vh sites (multiple of 8 for the XCD order)
+int dslash_blocks(int vh, int block);
+int dslash_block_size(const hisq_fmt &f, const Geom &g, int nrhs);
+hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st);
+hipError_t launch_dslash_batched(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// pack / unpack / reductions / solver BLAS
+// ---------------------------------------------------------------------------
+
+constexpr int BLAS_BLOCK = 256;
+int blas_blocks(size_t n);  // grid of the streaming kernels (fixed cap, grid-stride)
+
+hipError_t launch_spinor_pack(char *dst, const double *src, size_t n, int sf, hipStream_t st);
+hipError_t launch_spinor_unpack(double *dst, const char *src, size_t n, int sf, hipStream_t st);
+hipError_t launch_spinor_convert(char *dst, int sf_dst, const char *src, int sf_src, size_t n, hipStream_t st);
+hipError_t launch_absmax(const double *src, size_t n, double *partial, int *nblocks, hipStream_t st);
+hipError_t launch_reduce_max(const double *partial, int n, double *out, hipStream_t st);
+hipError_t launch_gauge_pack(char *dst, const double *src, const Geom &g, int gf, const double *absmax,
+                             hipStream_t st);
+hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nblocks, hipStream_t st);
+
+// solver control block, shared by the device scalar kernels and the host
+struct SolverCtrl {
+    int stop;        // guard value: block-local iteration index where the current block ends
+    int reason;      // STOP_*
+    int k;           // completed iterations
+    int done;        // last true-residual check met the target
+    int e_mask;      // multi-shift: shifts updated by this iteration's fused shift kernel
+    int active_mask; // multi-shift: shifts still being updated
+    int nshift;
+    int pr;          // Polak-Ribiere beta
+    int reproject;
+    int maxiter;
+    int breakdown;
+    int pad0;
+    double rho;      // |r|^2 of the iterated residual (stored values)
+    double rho_prev; // |r|^2 before the last iteration's update (beta at a reliable update)
+    double rho_new, gamma, pi, alpha, beta;
+    double pa_re, pa_im, pb;   // p_new = pa*r + pb*p
+    double rmax2;    // max |r|^2 since the last reliable update
+    double b2, tol2, delta2;
+    double r2_true;  // |b - A x|^2 at the last true-residual computation
+    double alpha_prev, beta_prev;
+    double floor2;   // multi-shift: sloppy floor^2
+    double alpha_buf[HISQ_MAX_GRAD_BUFFER];
+    double sh[HISQ_MAX_SHIFTS];       // shift_i - shift_0
+    double tol2_i[HISQ_MAX_SHIFTS];
+    double zeta[HISQ_MAX_SHIFTS], zeta_prev[HISQ_MAX_SHIFTS];
+    double alpha_i[HISQ_MAX_SHIFTS], beta_i[HISQ_MAX_SHIFTS];
+    int shift_stop_k[HISQ_MAX_SHIFTS];
+    // batched CG: per right-hand side scalars
+    double brho[16], brho_prev[16], brho_new[16], bgamma[16], bpi[16], balpha[16], bbeta[16];
+    double bpa_re[16], bpa_im[16], bpb[16], brmax2[16], bb2[16], br2_true[16];
+    double balpha_buf[HISQ_MAX_GRAD_BUFFER][16];
+    int bactive[16];   // 1 while right-hand side j is still iterating
+    int bdone[16];
+    int bk[16];
+};
+
+enum { STOP_NONE = 0, STOP_RU = 1, STOP_CONV = 2, STOP_BREAKDOWN = 3, STOP_MAXITER = 4, STOP_MSDONE = 5 };
+constexpr int STOP_NEVER = 0x3fffffff;
+
+struct SpinorList {
+    char *p[HISQ_MAX_SHIFTS];
+};
+
+// r = r - alpha*ap; partial (|r'|^2, Re<r', r>)
+hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, int sf, int compute,
+                          double *partial, Guard gd, hipStream_t st);
+// p_dst = pa*r + pb*p_src, (pa, pb) from the control block
+hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl,
+                             size_t n, int sf, int compute, Guard gd, hipStream_t st);
+// x64 += sum_i alpha_buf[i] p_i, i < count
+hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const double *alpha_buf, size_t n,
+                          int sf, int compute, Guard gd, hipStream_t st);
+// r_s = pack(r64); partial (|r_s|^2, Re<r_s,p>, Im<r_s,p>, Re<r_s, r_old + alpha ap>)
+hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const char *ap, const double *alpha,
+                             size_t n, int sf, int compute, double *partial, Guard gd, hipStream_t st);
+// multi-shift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i for the shifts of ctrl->e_mask
+hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
+                               int nshift, size_t n, int sf, int compute, Guard gd, hipStream_t st);
+
+// batched versions (nrhs consecutive fields of `stride` bytes)
+hipError_t launch_bcg_axpy(char *r, const char *ap, const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs,
+                           int sf, int compute, double *partial, Guard gd, hipStream_t st);
+hipError_t launch_bcg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, size_t n,
+                              size_t stride, int nrhs, int sf, int compute, Guard gd, hipStream_t st);
+hipError_t launch_bflush_x(char *x64, size_t stride64, const SpinorList &p, int count, const SolverCtrl *ctrl,
+                           size_t n, size_t stride, int nrhs, int sf, int compute, Guard gd, hipStream_t st);
+hipError_t launch_bru_convert(char *r_s, const char *r64, size_t stride64, const char *p, const char *ap,
+                              const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs, int sf, int compute,
+                              double *partial, Guard gd, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// library-owned per-device scratch for one-shot calls (reductions)
+// ---------------------------------------------------------------------------
+
+struct LibScratch {
+    double *dev;       // device doubles
+    size_t ndev;
+    double *host;      // pinned host doubles
+};
+hisq_status lib_scratch(LibScratch **out);
+
+}  // namespace hisq

@@ -1,0 +1,77 @@
+"""HIP storage codecs against the oracle, bit for bit (integer and byte work)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import gauge_reals, need_gpu, spinor_records
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def spread_spinor(n, seed, zero_every=97):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    v *= 10.0 ** rng.uniform(-25, 25, size=(n, 1))     # per-site magnitudes over 50 decades
+    v[::zero_every] = 0.0                              # all-zero sites
+    v[1::zero_every, 1] = 0.0                          # partially zero sites
+    return v
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 257, 5000])
+def test_spinor_pack_bit_exact(fmt, n):
+    hisq = need_gpu()
+    v = spread_spinor(n, 100 + fmt)
+    dev = torch.from_numpy(v).cuda()
+    packed = hisq.pack_spinor(dev, fmt)
+    torch.cuda.synchronize()
+    rec = spinor_records(packed.cpu().numpy(), n, fmt)
+    name = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}[fmt]
+    if name == "f64":
+        assert np.array_equal(rec.view(np.float64), v.view(np.float64))
+    elif name == "f32":
+        assert np.array_equal(rec, v.astype(np.complex64))
+    elif name == "half16":
+        q, nm = oracle.half16_encode(v)
+        assert np.array_equal(rec[0], q) and np.array_equal(rec[1].view(np.uint32), nm.view(np.uint32))
+    elif name == "int20":
+        assert np.array_equal(rec, oracle.int20_encode(v))
+    else:
+        assert np.array_equal(rec, oracle.int30_encode(v))
+    # decode: the library's unpack equals the oracle's decode of the same records, exactly
+    back = hisq.unpack_spinor(packed, n, fmt).cpu().numpy()
+    want = oracle.spinor_decode_records(rec, name)
+    assert np.array_equal(back.view(np.float64), want.view(np.float64))
+
+
+@pytest.mark.parametrize("gfmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 4)])
+def test_gauge_pack_bit_exact(gfmt, dims):
+    hisq = need_gpu()
+    fat, lng = inputs.make_links(dims, "haar", seed=321)
+    fat = fat * 1.7                                          # smeared-like scale above 1
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, gfmt)
+    torch.cuda.synchronize()
+    for src, packed, mx in ((fat.numpy(), pg.fat, pg.desc.fat_max), (lng.numpy(), pg.lng, pg.desc.long_max)):
+        got = gauge_reals(packed.cpu().numpy(), dims, gfmt)
+        assert mx == oracle.field_absmax(src)
+        reals = src.reshape(4, -1, 9).view(np.float64).reshape(4, -1, 18)
+        if gfmt == 0:
+            assert np.array_equal(got, reals)
+        elif gfmt == 1:
+            assert np.array_equal(got, reals.astype(np.float32))
+        else:
+            q, _ = oracle.fix_encode(src, 16 if gfmt == 2 else 32)
+            assert np.array_equal(got.reshape(-1), q)
+
+
+def test_gauge_pack_rejects_nonfinite():
+    hisq = need_gpu()
+    dims = (4, 4, 4, 4)
+    fat, lng = inputs.make_links(dims, "haar", seed=5)
+    fat[1, 7, 0, 2] = complex(float("nan"), 0.0)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16)
+    assert e.value.status == -7

@@ -1,0 +1,237 @@
+"""HIP Dslash against the FP64 oracle, element by element.
+
+Reference for a triplet gauge/fermion/compute: the oracle's FP64 Dslash of
+the inputs exactly as the storage formats hold them (links and spinor after
+an encode/decode round trip in the oracle's own codecs).  The kernel then
+differs from it only by (a) its own rounding in the compute precision and
+(b) the quantisation of the packed output, so per component
+  |y_gpu - y_ref| <= q_site/2 * (1 + 1e-3) + eps_c * max|y_ref|
+with q_site the output format's quantum at that site and eps_c = 1e-6 for
+FP32 compute (the FP32 tolerance of the Dslash, 16 mat-vecs of O(1)
+entries) and 1e-13 for FP64 compute.
+Pure FP64 and FP32 triplets are also checked against the unquantised FP64
+oracle at the tolerances 1e-13 and 1e-6 (max-norm relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import need_gpu, rel_inf
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32"]
+SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}
+GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+# 4^4: x+3mu and x-mu coincide; (6,8,10,12): Vh = 2880, a ragged last block;
+# (8,8,8,8): Vh = 2048, whole blocks; (4,6,4,8) non-cubic
+DIMS = [(4, 4, 4, 4), (6, 8, 10, 12), (8, 8, 8, 8), (4, 6, 4, 8)]
+_cache = {}
+
+
+def fields(dims, kind):
+    key = (dims, kind)
+    if key not in _cache:
+        fat, lng = inputs.make_links(dims, kind, seed=inputs.GAUGE_SEED + 7)
+        V = oracle.volume(dims)
+        psi = inputs.gaussian_spinor(V, inputs.SOURCE_SEED + 7).numpy()
+        psi[::53] = 0.0                                   # some all-zero sites
+        _cache[key] = (fat, lng, psi)
+    return _cache[key]
+
+
+def eps_c(compute):
+    return 1e-6 if compute == 32 else 1e-13
+
+
+def check_against_emulation(hisq, name, dims, kind, parity):
+    f = hisq.fmt(name)
+    fat, lng, psi = fields(dims, kind)
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    src_sites = oracle.parity_sites(dims, 1 - parity)
+    out_sites = oracle.parity_sites(dims, parity)
+    pin = hisq.pack_spinor(torch.from_numpy(psi[src_sites]).cuda(), f.spinor)
+    pout = hisq.dslash(pin, pg, parity, f)
+    y = hisq.unpack_spinor(pout, out_sites.size, f.spinor).cpu().numpy()
+    psi_in = np.zeros_like(psi)
+    psi_in[src_sites] = psi[src_sites]
+    ref = oracle.emulated_dslash(fat.numpy(), lng.numpy(), psi_in, dims, parity,
+                                 GF_NAME[f.gauge], SF_NAME[f.spinor], f.compute)[out_sites]
+    q = oracle.spinor_quantum(ref, SF_NAME[f.spinor])[:, None]
+    bound = 0.5 * q * (1 + 1e-3) + eps_c(f.compute) * np.abs(ref).max()
+    d = y - ref
+    err = np.maximum(np.abs(d.real), np.abs(d.imag))
+    worst = float((err / bound).max())
+    assert worst <= 1.0, f"{name} {dims} {kind} parity {parity}: max err/bound {worst:.3f}"
+    return y, ref
+
+
+@pytest.mark.parametrize("name", TRIPLETS)
+@pytest.mark.parametrize("dims", DIMS)
+def test_dslash_triplet(name, dims):
+    hisq = need_gpu()
+    for kind in ("near_unit", "haar"):
+        for parity in (0, 1):
+            check_against_emulation(hisq, name, dims, kind, parity)
+
+
+@pytest.mark.parametrize("name,tol", [("double", 1e-13), ("single", 1e-6)])
+def test_ieee_triplets_vs_pure_fp64(name, tol):
+    hisq = need_gpu()
+    dims = (6, 8, 10, 12)
+    f = hisq.fmt(name)
+    fat, lng, psi = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    for parity in (0, 1):
+        src, dst = oracle.parity_sites(dims, 1 - parity), oracle.parity_sites(dims, parity)
+        pin = hisq.pack_spinor(torch.from_numpy(psi[src]).cuda(), f.spinor)
+        y = hisq.unpack_spinor(hisq.dslash(pin, pg, parity, f), dst.size, f.spinor).cpu().numpy()
+        full = np.zeros_like(psi)
+        full[src] = psi[src]
+        ref = oracle.dslash(fat.numpy(), lng.numpy(), full, dims, parity)[dst]
+        assert rel_inf(y, ref) <= tol
+
+
+@pytest.mark.parametrize("name", ["double", "single", "half"])
+def test_xpay(name):
+    hisq = need_gpu()
+    dims = (6, 8, 10, 12)
+    f = hisq.fmt(name)
+    fat, lng, psi = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    parity = 0
+    src, dst = oracle.parity_sites(dims, 1), oracle.parity_sites(dims, 0)
+    xv = inputs.gaussian_spinor(dst.size, 99).numpy()
+    pin = hisq.pack_spinor(torch.from_numpy(psi[src]).cuda(), f.spinor)
+    px = hisq.pack_spinor(torch.from_numpy(xv).cuda(), f.spinor)
+    out = torch.empty_like(px)
+    a, b = 0.37, -1.25
+    hisq.hisq_dslash_xpay(out, pin, pg.desc, parity, f, a, px, b)
+    y = hisq.unpack_spinor(out, dst.size, f.spinor).cpu().numpy()
+    full = np.zeros_like(psi)
+    full[src] = psi[src]
+    ref = a * oracle.spinor_roundtrip(xv, SF_NAME[f.spinor]) + b * oracle.emulated_dslash(
+        fat.numpy(), lng.numpy(), full, dims, parity, GF_NAME[f.gauge], SF_NAME[f.spinor], f.compute)[dst]
+    q = oracle.spinor_quantum(ref, SF_NAME[f.spinor])[:, None]
+    bound = 0.5 * q * (1 + 1e-3) + 2 * eps_c(f.compute) * np.abs(ref).max()
+    d = y - ref
+    assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= bound).all()
+
+
+@pytest.mark.parametrize("name,tol", [("double", 1e-13), ("single", 2e-6), ("int30", 1e-8), ("int20", 2e-4),
+                                      ("half", 2e-4)])
+def test_normal_op(name, tol):
+    """(4m^2+s) p - D_eo D_oe p; the intermediate D_oe p is stored in the
+    sloppy format, so the bound is the format's precision (max-norm relative)"""
+    hisq = need_gpu()
+    dims = (6, 8, 10, 12)
+    f = hisq.fmt(name)
+    fat, lng, psi = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    ev = oracle.parity_sites(dims, 0)
+    p = psi[ev]
+    pin = hisq.pack_spinor(torch.from_numpy(p).cuda(), f.spinor)
+    out = torch.empty_like(pin)
+    tmp = torch.empty_like(pin)
+    mass, shift = 0.05, 0.01
+    hisq.hisq_normal_op(out, pin, tmp, pg.desc, mass, shift, f)
+    y = hisq.unpack_spinor(out, ev.size, f.spinor).cpu().numpy()
+    full = np.zeros_like(psi)
+    full[ev] = p
+    ref = oracle.normal_op(fat.numpy(), lng.numpy(), full, dims, mass, shift)[ev]
+    assert rel_inf(y, ref) <= tol
+
+
+@pytest.mark.parametrize("name", ["double", "single", "half", "int20", "int30"])
+@pytest.mark.parametrize("nrhs", [1, 3, 16])
+def test_batched_matches_single(name, nrhs):
+    """one link load for a block of right-hand sides gives every right-hand
+    side the same result as its own Dslash"""
+    hisq = need_gpu()
+    dims = (6, 8, 10, 12)
+    f = hisq.fmt(name)
+    fat, lng, _ = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    odd = oracle.parity_sites(dims, 1)
+    vh = odd.size
+    srcs = inputs.gaussian_spinor(vh, 500, nrhs=nrhs).numpy()
+    packed = [hisq.pack_spinor(torch.from_numpy(srcs[j]).cuda(), f.spinor) for j in range(nrhs)]
+    nb = hisq.hisq_spinor_bytes(vh, f.spinor)
+    pin = torch.cat([pk[:nb] for pk in packed]).contiguous()
+    pout = torch.empty_like(pin)
+    hisq.hisq_dslash_batched(pout, pin, pg.desc, 0, f, nrhs)
+    for j in range(nrhs):
+        single = hisq.dslash(packed[j], pg, 0, f)
+        yb = hisq.unpack_spinor(pout[j * nb:(j + 1) * nb].contiguous(), vh, f.spinor).cpu().numpy()
+        ys = hisq.unpack_spinor(single, vh, f.spinor).cpu().numpy()
+        q = oracle.spinor_quantum(ys, SF_NAME[f.spinor])[:, None]
+        d = yb - ys
+        assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= q + eps_c(f.compute) * np.abs(ys).max()).all()
+
+
+def test_full_size_sampled():
+    """48^3x96 (the benchmark lattice), launch configuration of the benchmark:
+    sampled output sites against the oracle evaluated site by site"""
+    hisq = need_gpu()
+    dims = (48, 48, 48, 96)
+    V = oracle.volume(dims)
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 3, device="cuda")
+    psi = inputs.gaussian_spinor(V // 2, inputs.SOURCE_SEED + 3, device="cuda")
+    rng = np.random.default_rng(1)
+    parity = 0
+    out_sites = oracle.parity_sites(dims, parity)
+    odd_sites = oracle.parity_sites(dims, 1)
+    samp_cb = np.unique(np.concatenate([rng.integers(0, V // 2, 3000), [0, V // 2 - 1]]))
+    samp = out_sites[samp_cb]
+    # every link and neighbour the sampled sites touch, gathered on the device
+    X, Y, Z, T = dims
+    c = [samp % X, (samp // X) % Y, (samp // (X * Y)) % Z, samp // (X * Y * Z)]
+    need_links, need_sp = set(), set()
+    for mu in range(4):
+        for h in (1, -1, 3, -3):
+            cc = [v.copy() for v in c]
+            cc[mu] = (cc[mu] + h) % dims[mu]
+            nb = ((cc[3] * Z + cc[2]) * Y + cc[1]) * X + cc[0]
+            need_sp.update(nb.tolist())
+            if h > 0:
+                need_links.update((mu * V + samp).tolist())
+            else:
+                need_links.update((mu * V + nb).tolist())
+    lidx = np.array(sorted(need_links))
+    sidx = np.array(sorted(need_sp))
+    full_fat = np.zeros((4 * V, 3, 3), dtype=np.complex128)   # lazily allocated; only touched entries used
+    full_lng = np.zeros((4 * V, 3, 3), dtype=np.complex128)
+    full_psi = np.zeros((V, 3), dtype=np.complex128)
+    fat_h = fat.reshape(4 * V, 3, 3)[torch.from_numpy(lidx).cuda()].cpu().numpy()
+    lng_h = lng.reshape(4 * V, 3, 3)[torch.from_numpy(lidx).cuda()].cpu().numpy()
+    pos = np.searchsorted(odd_sites, sidx)                     # cb index of each needed odd site
+    psi_h = psi[torch.from_numpy(pos).cuda()].cpu().numpy()
+    fmax = float(torch.view_as_real(fat).abs().amax())
+    lmax = float(torch.view_as_real(lng).abs().amax())
+    for name in ("half", "int20", "int30", "single", "double"):
+        f = hisq.fmt(name)
+        pg = hisq.pack_gauge(fat, lng, dims, f.gauge)
+        pin = hisq.pack_spinor(psi, f.spinor)
+        y = hisq.unpack_spinor(hisq.dslash(pin, pg, parity, f), V // 2, f.spinor)[torch.from_numpy(samp_cb).cuda()]
+        y = y.cpu().numpy()
+        del pg, pin
+        gname, sname = GF_NAME[f.gauge], SF_NAME[f.spinor]
+        if gname in ("fix16", "fix32"):
+            bits = 16 if gname == "fix16" else 32
+            qf, _ = oracle.fix_encode(fat_h, bits, absmax=fmax)
+            ql, _ = oracle.fix_encode(lng_h, bits, absmax=lmax)
+            full_fat[lidx] = oracle.fix_decode(qf, fmax, f.compute, shape=fat_h.shape)
+            full_lng[lidx] = oracle.fix_decode(ql, lmax, f.compute, shape=lng_h.shape)
+        else:
+            full_fat[lidx] = oracle.gauge_roundtrip(fat_h, gname, f.compute)
+            full_lng[lidx] = oracle.gauge_roundtrip(lng_h, gname, f.compute)
+        full_psi[sidx] = oracle.spinor_roundtrip(psi_h, sname)
+        ref = oracle.dslash_sites(full_fat.reshape(4, V, 3, 3), full_lng.reshape(4, V, 3, 3), full_psi, dims, samp)
+        q = oracle.spinor_quantum(ref, sname)[:, None]
+        bound = 0.5 * q * (1 + 1e-3) + eps_c(f.compute) * np.abs(ref).max()
+        d = y - ref
+        worst = float((np.maximum(np.abs(d.real), np.abs(d.imag)) / bound).max())
+        assert worst <= 1.0, f"{name}: max err/bound {worst:.3f}"
+        torch.cuda.empty_cache()

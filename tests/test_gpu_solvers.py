@@ -1,0 +1,177 @@
+"""HIP solvers against the oracle: the solution of (4m^2 + s - D_eo D_oe) x = b
+is unique, so every mixed-precision solve must reach the requested true
+residual (measured by the oracle's FP64 operator) and agree with the
+oracle's FP64 solve to the accuracy the condition number allows."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import need_gpu
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def setup(dims, kind, seed=inputs.GAUGE_SEED):
+    key = (dims, kind, seed)
+    if key not in _cache:
+        fat, lng = inputs.make_links(dims, kind, seed)
+        ev = oracle.parity_sites(dims, 0)
+        b = inputs.gaussian_spinor(ev.size, inputs.SOURCE_SEED).numpy()
+        _cache[key] = (fat, lng, ev, b)
+    return _cache[key]
+
+
+def packed(hisq, fat, lng, dims, names):
+    out = {}
+    for n in names:
+        g = hisq.fmt(n).gauge
+        if g not in out:
+            out[g] = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, g)
+    return out
+
+
+def full(dims, ev, v):
+    f = np.zeros((oracle.volume(dims), 3), dtype=np.complex128)
+    f[ev] = v
+    return f
+
+
+def test_cg_config0_dense():
+    """4^4 rough links, m = 0.1, FP64 CG against a dense LAPACK solve"""
+    hisq = need_gpu()
+    import pins
+    dims, mass = (4, 4, 4, 4), 0.1
+    fat, lng, ev, b = setup(dims, "haar")
+    pg = packed(hisq, fat, lng, dims, ["double"])
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], pg[0], mass, tol=1e-10, sloppy="double")
+    x = x.cpu().numpy()
+    A = pins.dense_normal(fat.numpy(), lng.numpy(), dims, mass)
+    xd = np.linalg.solve(A, b.ravel())
+    assert st["status"] == "HISQ_OK"
+    assert np.linalg.norm(x.ravel() - xd) / np.linalg.norm(xd) < 1e-8
+    assert oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass) <= 1e-10
+
+
+@pytest.mark.parametrize("sloppy", ["double", "single", "half", "int20", "int30", "int30_fp32"])
+@pytest.mark.parametrize("dims,kind,mass", [((8, 8, 8, 8), "near_unit", 0.05), ((6, 8, 10, 12), "haar", 0.2)])
+def test_cg_mixed(sloppy, dims, kind, mass):
+    hisq = need_gpu()
+    fat, lng, ev, b = setup(dims, kind)
+    pg = packed(hisq, fat, lng, dims, ["double", sloppy])
+    gs = pg[hisq.fmt(sloppy).gauge]
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], gs, mass, tol=1e-10, sloppy=sloppy)
+    x = x.cpu().numpy()
+    assert st["status"] == "HISQ_OK", st
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass)
+    assert res <= 1e-10 * (1 + 1e-6), (res, st)
+    assert abs(res - st["true_resid"]) <= 1e-3 * res + 1e-15
+    xo, it, ores, _ = oracle.cg(fat.numpy(), lng.numpy(), full(dims, ev, b), dims, mass, tol=1e-12)
+    assert np.linalg.norm(x - xo[ev]) / np.linalg.norm(xo[ev]) < 1e-8
+
+
+@pytest.mark.parametrize("opts", [dict(grad_buffer=1), dict(grad_buffer=8), dict(use_graph=0),
+                                  dict(pr_beta=0), dict(reproject=0), dict(poll_every=3, grad_buffer=2),
+                                  dict(delta=0.5)])
+def test_cg_options(opts):
+    hisq = need_gpu()
+    dims, mass = (6, 8, 10, 12), 0.1
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "half"])
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], pg[2], mass, tol=1e-10, sloppy="half", **opts)
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x.cpu().numpy()), full(dims, ev, b), dims, mass)
+    assert st["status"] == "HISQ_OK" and res <= 1e-10 * (1 + 1e-6), (opts, st, res)
+
+
+def test_cg_initial_guess_and_zero_rhs():
+    hisq = need_gpu()
+    dims, mass = (6, 8, 10, 12), 0.1
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "single"])
+    xo, *_ = oracle.cg(fat.numpy(), lng.numpy(), full(dims, ev, b), dims, mass, tol=1e-13)
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], pg[1], mass, tol=1e-10, sloppy="single",
+                          x0=torch.from_numpy(xo[ev]).cuda())
+    assert st["status"] == "HISQ_OK" and st["iters"] == 0
+    z = torch.zeros((ev.size, 3), dtype=torch.complex128, device="cuda")
+    x, st = hisq.cg_solve(z, pg[0], pg[1], mass, tol=1e-10, sloppy="single")
+    assert st["status"] == "HISQ_OK" and float(x.abs().max()) == 0.0
+
+
+def test_cg_maxiter_reports_noconv():
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.01
+    fat, lng, ev, b = setup(dims, "haar")
+    pg = packed(hisq, fat, lng, dims, ["double", "single"])
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], pg[1], mass, tol=1e-12, sloppy="single", maxiter=5)
+    assert st["status"] == "HISQ_ENOCONV" and st["iters"] >= 5
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x.cpu().numpy()), full(dims, ev, b), dims, mass)
+    assert abs(res - st["true_resid"]) <= 1e-6 * res
+
+
+@pytest.mark.parametrize("ms,ref", [("single", "half"), ("int30", "int20"), ("double", "double"), ("single", "single")])
+def test_multishift(ms, ref):
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
+    tol = [1e-10] * len(shifts)
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", ms, ref])
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[hisq.fmt(ms).gauge],
+                                      pg[hisq.fmt(ref).gauge], mass, ms_fmt=ms, ref_fmt=ref)
+    assert st["status"] == "HISQ_OK", st
+    out = oracle.multishift_cg(fat.numpy(), lng.numpy(), full(dims, ev, b), dims, mass, shifts, 1e-12)
+    for i, s in enumerate(shifts):
+        x = xs[i].cpu().numpy()
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass, s)
+        assert res <= tol[i] * (1 + 1e-6), (i, res, st)
+        xo = out["x"][i][ev]
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+
+
+def test_multishift_per_shift_tolerances():
+    """RHMC-like: every shift has its own target (Sec. 6.2 footnote)"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    shifts = [1e-5, 3e-4, 1e-2, 0.3, 10.0]
+    tol = [1e-6, 1e-8, 1e-10, 1e-11, 1e-12]
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "int30", "int20"])
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[3], pg[2], mass,
+                                      ms_fmt="int30", ref_fmt="int20")
+    assert st["status"] == "HISQ_OK", st
+    for i, s in enumerate(shifts):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[i].cpu().numpy()), full(dims, ev, b),
+                                   dims, mass, s)
+        assert res <= tol[i] * (1 + 1e-6), (i, res)
+
+
+def test_multishift_single_shift():
+    hisq = need_gpu()
+    dims, mass = (6, 8, 10, 12), 0.1
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "single", "half"])
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), [0.02], [1e-10], pg[0], pg[1], pg[2], mass)
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[0].cpu().numpy()), full(dims, ev, b),
+                               dims, mass, 0.02)
+    assert st["status"] == "HISQ_OK" and res <= 1e-10 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "double"])
+@pytest.mark.parametrize("nrhs", [1, 4, 16])
+def test_batched_cg(sloppy, nrhs):
+    hisq = need_gpu()
+    dims, mass = (6, 8, 10, 12), 0.1
+    fat, lng, ev, _ = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", sloppy])
+    bs = inputs.gaussian_spinor(ev.size, inputs.RHS_SEED, nrhs=nrhs).numpy()
+    bs[nrhs // 2] *= 1e-3          # right-hand sides of very different norms
+    x, st = hisq.cg_solve_batched(torch.from_numpy(bs).cuda(), pg[0], pg[hisq.fmt(sloppy).gauge], mass, tol=1e-10,
+                                  sloppy=sloppy)
+    assert st["status"] == "HISQ_OK", st
+    x = x.cpu().numpy()
+    for j in range(nrhs):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x[j]), full(dims, ev, bs[j]), dims, mass)
+        assert res <= 1e-10 * (1 + 1e-6), (j, res)

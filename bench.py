@@ -1,0 +1,246 @@
+"""Benchmark: mixed-precision multi-shift CG on the HISQ operator (one MI355X).
+
+Workload (one "step" = one pass of the whole hot path): 48^3x96 lattice,
+near-unit links, m = 0.005, 12 shifts log-spaced from 1e-5 to 10, every shift
+solved to a 1e-10 true relative residual.  A step packs the FP64 links (already
+resident in HBM) into the solver's storage formats and runs the multi-shift
+solve: multi-shift phase in 32-bit links / 30-bit fermions / FP64 compute with
+FP64 reliable updates, then CG refinement in 16-bit links / 20-bit fermions /
+FP32 compute (the paper's improved variant, Sec. 6.2).
+
+Printed (one JSON line): whole-step algorithmic HBM GB/s (value), the
+per-triplet Dslash GB/s and GFLOP/s measured with HIP events (the Fig. 3
+analog), the roofline of the dominant kernel, the FP64 GPU multi-shift
+comparator (time to the same residuals), and the FP64 CPU oracle timed on the
+host cores as a reported baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-fp64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FLOP_PER_SITE = 1146
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", type=str, default="48,48,48,96")
+    ap.add_argument("--mass", type=float, default=0.005)
+    ap.add_argument("--nshift", type=int, default=12)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--ms", type=str, default="int30")
+    ap.add_argument("--ref", type=str, default="int20")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--dslash-reps", type=int, default=20)
+    ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2302_09224_amd import hisq, inputs
+
+    hisq.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dims = tuple(int(v) for v in args.dims.split(","))
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    vh = V // 2
+    shifts = [10.0 ** (-5 + 6 * i / (args.nshift - 1)) for i in range(args.nshift)] if args.nshift > 1 else [1e-5]
+    tols = [args.tol] * len(shifts)
+
+    t0 = time.time()
+    log(f"[bench] generating near-unit links on {dims} (seed {inputs.GAUGE_SEED + 3})")
+    fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 3, device=dev)
+    b = inputs.gaussian_spinor(vh, inputs.SOURCE_SEED + 3, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready in {time.time() - t0:.1f}s")
+
+    fms, fref = hisq.fmt(args.ms), hisq.fmt(args.ref)
+    f64 = hisq.fmt("double")
+
+    # ---------------- per-triplet Dslash (Fig. 3 analog) ----------------
+    kernels = {}
+    gauges = {}
+
+    def gauge(gf):
+        if gf not in gauges:
+            gauges[gf] = hisq.pack_gauge(fat, lng, dims, gf)
+        return gauges[gf]
+
+    stream = torch.cuda.current_stream()
+    for name in ("double", "single", "half", "int20", "int30", "int30_fp32"):
+        f = hisq.fmt(name)
+        pg = gauge(f.gauge)
+        pin = hisq.pack_spinor(b, f.spinor)
+        out = torch.empty_like(pin)
+        for _ in range(3):
+            hisq.hisq_dslash(out, pin, pg.desc, 1, f)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(args.dslash_reps):
+            hisq.hisq_dslash(out, pin, pg.desc, 1, f)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.dslash_reps
+        nbytes = vh * (16 * hisq.GAUGE_BYTES[f.gauge] + 2 * hisq.SPINOR_BYTES[f.spinor])
+        kernels[name] = dict(triplet=repr(f), us=round(ms * 1e3, 2), alg_bytes=nbytes,
+                             gbs=round(nbytes / ms / 1e6, 1), gflops=round(FLOP_PER_SITE * vh / ms / 1e6, 1),
+                             frac_hbm=round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4))
+        log(f"[bench] dslash {name:11s} {kernels[name]['us']:9.1f} us  {kernels[name]['gbs']:7.1f} GB/s "
+            f"{kernels[name]['gflops']:7.1f} GFLOP/s  ({100 * kernels[name]['frac_hbm']:.1f}% HBM)")
+        del pin, out
+    if args.kernels_only:
+        print(json.dumps(dict(kernels=kernels)))
+        return
+    for gf in list(gauges):
+        if gf not in (hisq.GAUGE_F64, fms.gauge, fref.gauge):
+            del gauges[gf]
+    gauges.clear()
+    torch.cuda.empty_cache()
+
+    # ---------------- the timed step ----------------
+    def step():
+        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+        gms = hisq.pack_gauge(fat, lng, dims, fms.gauge)
+        gref = gms if fref.gauge == fms.gauge else hisq.pack_gauge(fat, lng, dims, fref.gauge)
+        xs, st = hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=args.ms,
+                                          ref_fmt=args.ref)
+        return xs, st
+
+    for w in range(args.warmup):
+        log(f"[bench] warmup {w + 1}/{args.warmup}")
+        xs, st = step()
+        log(f"[bench]   {st['seconds']:.2f}s, ms iters {st['iters']}, refine {st['refine_iters']}, "
+            f"resid max {max(st['shift_resid']):.2e}")
+        del xs
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        xs, st = step()
+        stats.append(st)
+        log(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.2f}s, ms iters {st['iters']}, "
+            f"refine {st['refine_iters']}, resid max {max(st['shift_resid']):.2e}")
+        if k + 1 < args.steps:
+            del xs
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed / args.steps * 1e3
+    pack_bytes = 2 * 4 * V * (144 + 144 + hisq.GAUGE_BYTES[fms.gauge]
+                              + (hisq.GAUGE_BYTES[fref.gauge] + 144 if fref.gauge != fms.gauge else 0))
+    step_bytes = float(np.mean([s["alg_bytes"] for s in stats])) + pack_bytes
+    value = step_bytes / (ms_per_step / 1e3) / 1e9
+    last = stats[-1]
+    resid_ok = all(r <= t * (1 + 1e-6) for r, t in zip(last["shift_resid"], tols))
+
+    # ---------------- FP64 GPU multi-shift comparator ----------------
+    fp64 = None
+    if not args.no_fp64:
+        log("[bench] FP64 multi-shift comparator")
+        del xs
+        torch.cuda.empty_cache()
+        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xs64, st64 = hisq.multishift_cg_solve(b, shifts, tols, g64, g64, g64, args.mass, ms_fmt="double",
+                                              ref_fmt="double", delta=0.0)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        fp64 = dict(seconds=round(t64, 3), iters=st64["iters"], refine_iters=st64["refine_iters"],
+                    resid_max=max(st64["shift_resid"]), speedup_mixed=round(t64 / (ms_per_step / 1e3), 3))
+        log(f"[bench]   FP64: {t64:.2f}s, iters {st64['iters']}, refine {st64['refine_iters']}")
+        del xs64, g64
+        torch.cuda.empty_cache()
+
+    # ---------------- roofline of the dominant kernel ----------------
+    dom = args.ms
+    kd = kernels[dom]
+    roofline = dict(bound="hbm", achieved=kd["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(kd["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel=f"k_dslash<{kd['triplet']}>", alg_bytes_per_launch=kd["alg_bytes"],
+                    us_per_launch=kd["us"])
+
+    # ---------------- CPU oracle baseline ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        olib = oracle.load()
+        nthr = oracle.threads(olib)
+        log(f"[bench] CPU oracle baseline ({nthr} threads)")
+        # bounded sample: the oracle's FP64 Dslash at a fixed random sample of
+        # output sites of the same lattice and fields, repeated for ~10 s
+        fat_h = fat.cpu().numpy()
+        lng_h = lng.cpu().numpy()
+        full = np.zeros((V, 3), dtype=np.complex128)
+        odd = np.nonzero(((np.arange(V) % dims[0]) + (np.arange(V) // dims[0]) % dims[1]
+                          + (np.arange(V) // (dims[0] * dims[1])) % dims[2]
+                          + np.arange(V) // (dims[0] * dims[1] * dims[2])) % 2 == 1)[0]
+        full[odd] = b.cpu().numpy()
+        rng = np.random.default_rng(0)
+        even = np.setdiff1d(np.arange(V), odd, assume_unique=True)
+        sample = np.sort(rng.choice(even, size=min(even.size, 1 << 20), replace=False))
+        done_sites, tc = 0, 0.0
+        while tc < 10.0:
+            t2 = time.perf_counter()
+            oracle.dslash_sites(fat_h, lng_h, full, dims, sample, lib=olib)
+            tc += time.perf_counter() - t2
+            done_sites += sample.size
+        gbs_cpu = done_sites * (16 * 144 + 2 * 48) / tc / 1e9
+        cpu = dict(value=round(gbs_cpu, 3), unit="GB/s", cores=nthr, kind="oracle",
+                   sample=f"FP64 oracle Dslash at {sample.size} random even sites of the {dims} lattice, "
+                          f"repeated {done_sites // sample.size}x ({tc:.1f}s); algorithmic bytes 2400/site",
+                   vs_gpu_fp64_dslash=round(kernels['double']['gbs'] / gbs_cpu, 1))
+        del fat_h, lng_h, full
+
+    line = {
+        "metric": "HISQ Dslash GB/s (% HBM peak); multi-shift CG s to 1e-10 vs FP64 CG",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic (seeded near-unit SU(3) links exp(0.3iH), Gaussian source)",
+        "config": {"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "lattice": list(dims),
+                   "mass": args.mass, "shifts": [float(f"{s:.4g}") for s in shifts], "tol": args.tol,
+                   "ms_triplet": repr(fms), "refine_triplet": repr(fref), "parallelism": "single GPU"},
+        "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
+                       "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],
+                       "resid_after_ms": [float(f"{r:.3g}") for r in last["shift_resid_ms"]],
+                       "resid": [float(f"{r:.3g}") for r in last["shift_resid"]], "all_converged": resid_ok,
+                       "step_alg_bytes": step_bytes, "fp64_gpu": fp64},
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,6 +53,8 @@ def _declare(lib):
     lib.hisq_oracle_multishift_cg.argtypes = [vp, vp, vp, vp, _c_int_p, ctypes.c_int, ctypes.c_double,
                                               vp, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.hisq_oracle_multishift_cg.restype = ctypes.c_int
+    lib.hisq_oracle_threads.argtypes = []
+    lib.hisq_oracle_threads.restype = ctypes.c_int
     for name in ("half16_encode",):
         getattr(lib, "hisq_oracle_" + name).argtypes = [vp, vp, vp, ctypes.c_long]
     lib.hisq_oracle_half16_decode.argtypes = [vp, vp, vp, ctypes.c_long]
@@ -126,6 +128,11 @@ def from_full(full, dims, parity):
 # ---------------------------------------------------------------------------
 # operator and solvers
 # ---------------------------------------------------------------------------
+
+def threads(lib=None):
+    """number of OpenMP threads the oracle's site loops use"""
+    return (lib or load()).hisq_oracle_threads()
+
 
 def dslash(fat, lng, psi, dims, parity=-1, out=None, lib=None):
     """(D psi) on the sites of `parity` (all sites for -1); other sites of

@@ -29,6 +29,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -69,6 +70,18 @@ static int site_parity(long i, const int *d)
 }
 
 static long lattice_volume(const int *d) { return (long)d[0] * d[1] * d[2] * d[3]; }
+
+/* threads the site loops use (OpenMP) */
+int hisq_oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
 
 /* link matrix of direction mu at site i: row-major 3x3 */
 static const cplx *link(const cplx *field, int mu, long i, long V)

@@ -35,6 +35,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, reps=10):
+    """Block of 16 right-hand sides (one link load per site for the block)
+    against 16 single-right-hand-side applications, 32^3x64."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    vh = V // 2
+    fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 4, device=dev)
+    srcs = inputs.gaussian_spinor(vh, inputs.RHS_SEED, device=dev, nrhs=nrhs)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name in ("half", "int20", "single"):
+        f = hisq.fmt(name)
+        pg = hisq.pack_gauge(fat, lng, dims, f.gauge)
+        nb = hisq.hisq_spinor_bytes(vh, f.spinor)
+        pin = torch.cat([hisq.pack_spinor(srcs[j], f.spinor)[:nb] for j in range(nrhs)]).contiguous()
+        pout = torch.empty_like(pin)
+        for _ in range(2):
+            hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tb = e0.elapsed_time(e1) / reps
+        # 16 single-right-hand-side applications: kernel time of one application x 16
+        one_in, one_out = pin[:nb], pout[:nb]
+        hisq.hisq_dslash(one_out, one_in, pg.desc, 1, f)
+        e0.record(stream)
+        for _ in range(reps * 4):
+            hisq.hisq_dslash(one_out, one_in, pg.desc, 1, f)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts = e0.elapsed_time(e1) / (reps * 4) * nrhs
+        nbytes = vh * (16 * hisq.GAUGE_BYTES[f.gauge] + nrhs * 2 * hisq.SPINOR_BYTES[f.spinor])
+        out[name] = dict(dims=list(dims), nrhs=nrhs, us_batched=round(tb * 1e3, 1), us_16_single=round(ts * 1e3, 1),
+                         speedup=round(ts / tb, 2), gbs=round(nbytes / tb / 1e6, 1),
+                         gflops=round(nrhs * FLOP_PER_SITE * vh / tb / 1e6, 1))
+        log(f"[bench] batched {name:6s} {out[name]}")
+        del pg, pin, pout
+    del fat, lng, srcs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +94,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 16-right-hand-side Dslash on 32^3x64 against 16 single applications")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -69,6 +117,14 @@ def main():
     vh = V // 2
     shifts = [10.0 ** (-5 + 6 * i / (args.nshift - 1)) for i in range(args.nshift)] if args.nshift > 1 else [1e-5]
     tols = [args.tol] * len(shifts)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
 
     t0 = time.time()
     log(f"[bench] generating near-unit links on {dims} (seed {inputs.GAUGE_SEED + 3})")
@@ -111,8 +167,14 @@ def main():
         log(f"[bench] dslash {name:11s} {kernels[name]['us']:9.1f} us  {kernels[name]['gbs']:7.1f} GB/s "
             f"{kernels[name]['gflops']:7.1f} GFLOP/s  ({100 * kernels[name]['frac_hbm']:.1f}% HBM)")
         del pin, out
+    batched = None
+    if args.batched:
+        batched = bench_batched(args, hisq, inputs, torch, dev)
+    tuning = hisq.hisq_tune_report().strip().splitlines()
+    for line in tuning:
+        log(f"[bench] tuned: {line}")
     if args.kernels_only:
-        print(json.dumps(dict(kernels=kernels)))
+        print(json.dumps(dict(kernels=kernels, batched=batched, tuning=tuning)))
         return
     for gf in list(gauges):
         if gf not in (hisq.GAUGE_F64, fms.gauge, fref.gauge):
@@ -236,6 +298,7 @@ def main():
                        "resid": [float(f"{r:.3g}") for r in last["shift_resid"]], "all_converged": resid_ok,
                        "step_alg_bytes": step_bytes, "fp64_gpu": fp64},
         "kernels": kernels,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -247,6 +247,15 @@ hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hi
                                   hisq_fmt sloppy, const hisq_solver_params *p, void *ws,
                                   size_t ws_bytes, hisq_solver_stats *stats, void *stream);
 
+/* Launch shapes chosen by the Dslash autotuner so far (one text line per
+ * triplet, lattice and right-hand-side block: right-hand sides per lane, lanes
+ * per site, hops per load stage, block size, measured time).  Writes at most
+ * len bytes (NUL-terminated) into buf if buf is not NULL; returns the size the
+ * full report needs.  The autotuner times each candidate shape with HIP events
+ * on the first application of a shape key (never inside stream capture);
+ * environment HISQ_TUNE=0 selects fixed defaults instead. */
+size_t hisq_tune_report(char *buf, size_t len);
+
 /* Thread-local message of the calling thread's last non-OK status. */
 const char *hisq_last_error(void);
 

@@ -38,12 +38,25 @@ __device__ __forceinline__ void bsum(const double *partial, int nb, int nrhs, in
     __syncthreads();
 }
 
-__global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, int nb, int nrhs, int jb, Guard gd) {
+// Dslash partials: right-hand side j owns column partial[j*pstride + b], b < nb[j]
+struct NbList {
+    int nb[16];
+    size_t pstride;
+};
+
+__device__ __forceinline__ void csum(const double *col, int nb, double (&v)[1], double *lds) {
+    v[0] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += col[b];
+    block_sum<1>(v, lds);
+    __syncthreads();
+}
+
+__global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, NbList nl, int nrhs, int jb, Guard gd) {
     __shared__ double lds[16];
     if (!gd.pass()) return;
     for (int j = 0; j < nrhs; j++) {
         double v[1];
-        bsum<1>(partial, nb, nrhs, j, v, lds);
+        csum(partial + (size_t)j * nl.pstride, nl.nb[j], v, lds);
         if (threadIdx.x) continue;
         const double pi = v[0];
         c->bpi[j] = pi;
@@ -103,12 +116,12 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
     }
 }
 
-__global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, int nb, int nrhs) {
+__global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, NbList nl, int nrhs) {
     __shared__ double lds[16];
     int all = 1;
     for (int j = 0; j < nrhs; j++) {
         double v[1];
-        bsum<1>(partial, nb, nrhs, j, v, lds);
+        csum(partial + (size_t)j * nl.pstride, nl.nb[j], v, lds);
         if (threadIdx.x) continue;
         const double r2 = v[0];
         c->br2_true[j] = r2;
@@ -163,7 +176,7 @@ struct BBuf {
 };
 
 size_t partial_len(const Geom &g, int nrhs) {
-    const size_t a = (size_t)dslash_blocks(g.vh, 64) * nrhs;
+    const size_t a = dslash_max_blocks(g.vh) * nrhs;
     const size_t b = (size_t)4096 * 4 * nrhs;
     return std::max(a, b);
 }
@@ -206,6 +219,25 @@ struct BRun {
     long iters = 0, rus = 0, dsl = 0, d64 = 0;
     double alg = 0.0;
     hipGraphExec_t exec = nullptr;
+    DslashPlan plan_s{}, plan_64{};
+    NbList nl_s{}, nl_64{};
+
+    // launch shapes (autotuned on first use, outside capture) and the block
+    // count each right-hand side's Dslash partials use
+    void setup_plans() {
+        const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
+        DslashArgs ps = dargs(gs, fmt, B->ts, B->rs, 1);
+        plan_s = dslash_plan(fmt, g, nrhs, &ps, st);
+        DslashArgs p64 = dargs(g64, f64, B->t64, B->x64, 1);
+        plan_64 = dslash_plan(f64, g, nrhs, &p64, st);
+        nl_s.pstride = nl_64.pstride = dslash_max_blocks(g.vh);
+        for (int i = 0; i < plan_s.n; i++)
+            for (int j = 0; j < plan_s.tile[i].nr * plan_s.tile[i].rg; j++)
+                nl_s.nb[plan_s.rhs0[i] + j] = dslash_blocks(g.vh * plan_s.tile[i].rg, plan_s.tile[i].block);
+        for (int i = 0; i < plan_64.n; i++)
+            for (int j = 0; j < plan_64.tile[i].nr * plan_64.tile[i].rg; j++)
+                nl_64.nb[plan_64.rhs0[i] + j] = dslash_blocks(g.vh * plan_64.tile[i].rg, plan_64.tile[i].block);
+    }
 
     ~BRun() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -236,17 +268,17 @@ struct BRun {
         const Guard gns{&c->stop, j, 0}, gsn{&c->stop, j, 1};
         DslashArgs A = dargs(gs, fmt, B->ts, B->p[jb], 1);
         A.guard = gns;
-        HISQ_TRY_HIP(launch_dslash_batched(A, fmt, 256, st));
+        HISQ_TRY_HIP(launch_dslash(A, fmt, plan_s, st, nullptr));
         DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
         Bk.a = c_;
         Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
+        Bk.pstride = nl_s.pstride;
         Bk.guard = gns;
-        HISQ_TRY_HIP(launch_dslash_batched(Bk, fmt, 256, st));
-        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, dslash_blocks(g.vh, 256),
-                           nrhs, jb, gns);
+        HISQ_TRY_HIP(launch_dslash(Bk, fmt, plan_s, st, nullptr));
+        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, nl_s, nrhs, jb, gns);
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_bcg_axpy(B->rs, B->aps, c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_bfin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs, gns);
@@ -270,7 +302,7 @@ struct BRun {
                                          Guard{nullptr, 0, 0}, st));
         }
         DslashArgs A = dargs(g64, f64, B->t64, B->x64, 1);
-        HISQ_TRY_HIP(launch_dslash_batched(A, f64, 256, st));
+        HISQ_TRY_HIP(launch_dslash(A, f64, plan_64, st, nullptr));
         DslashArgs Bk = dargs(g64, f64, B->r64, B->t64, 0);
         Bk.x = B->x64;
         Bk.a = -c_;
@@ -278,8 +310,9 @@ struct BRun {
         Bk.c = 1.0;
         Bk.red = RED_NORM;
         Bk.partial = B->partial;
-        HISQ_TRY_HIP(launch_dslash_batched(Bk, f64, 256, st));
-        hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, dslash_blocks(g.vh, 256), nrhs);
+        Bk.pstride = nl_64.pstride;
+        HISQ_TRY_HIP(launch_dslash(Bk, f64, plan_64, st, nullptr));
+        hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, nl_64, nrhs);
         HISQ_TRY_HIP(hipGetLastError());
         d64 += 2;
         alg += 2.0 * vh * (16.0 * 144 + nrhs * 2.0 * 48) + 2.0 * vh * nrhs * 48;
@@ -446,6 +479,7 @@ extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrh
         }
         HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
     }
+    R.setup_plans();
     hisq_status status = R.enq_reliable(1, 0, nullptr);
     if (status == HISQ_OK) status = R.read_ctrl(h);
     long k0 = 0;

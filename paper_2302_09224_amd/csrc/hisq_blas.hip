@@ -13,7 +13,7 @@ namespace hisq {
 
 int blas_blocks(size_t n) {
     size_t nb = (n + BLAS_BLOCK - 1) / BLAS_BLOCK;
-    if (nb > 4096) nb = 4096;
+    if (nb > BLAS_MAX_BLOCKS) nb = BLAS_MAX_BLOCKS;
     if (nb < 1) nb = 1;
     return (int)nb;
 }

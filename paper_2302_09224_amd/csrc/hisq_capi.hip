@@ -44,6 +44,9 @@ Geom make_geom(const int dims[4]) {
     g.sy = g.X2;
     g.sz = g.X2 * g.Y;
     g.st = g.X2 * g.Y * g.Z;
+    g.dX2 = make_fastdiv((unsigned)g.X2);
+    g.dY = make_fastdiv((unsigned)g.Y);
+    g.dZ = make_fastdiv((unsigned)g.Z);
     return g;
 }
 
@@ -208,7 +211,8 @@ extern "C" hisq_status hisq_dslash(void *out, const void *in, const hisq_gauge *
                                    void *stream) {
     HISQ_TRY(dslash_common(out, in, g, parity, fmt, "hisq_dslash"));
     DslashArgs a = base_args(g, out, in, parity);
-    HISQ_TRY_HIP(launch_dslash(a, fmt, dslash_block_size(fmt, a.g, 1), (hipStream_t)stream));
+    const DslashPlan plan = dslash_plan(fmt, a.g, 1, &a, (hipStream_t)stream);
+    HISQ_TRY_HIP(launch_dslash(a, fmt, plan, (hipStream_t)stream, nullptr));
     return HISQ_OK;
 }
 
@@ -221,7 +225,8 @@ extern "C" hisq_status hisq_dslash_xpay(void *out, const void *in, const hisq_ga
     d.b = b;
     d.x = (const char *)x;
     d.a = a;
-    HISQ_TRY_HIP(launch_dslash(d, fmt, dslash_block_size(fmt, d.g, 1), (hipStream_t)stream));
+    const DslashPlan plan = dslash_plan(fmt, d.g, 1, &d, (hipStream_t)stream);
+    HISQ_TRY_HIP(launch_dslash(d, fmt, plan, (hipStream_t)stream, nullptr));
     return HISQ_OK;
 }
 
@@ -231,13 +236,13 @@ extern "C" hisq_status hisq_normal_op(void *out, const void *in, void *tmp, cons
     if (!out || !aligned16(out)) return set_error(HISQ_EALIGN, "hisq_normal_op: out null or unaligned");
     if (out == in || out == tmp) return set_error(HISQ_EINVAL, "hisq_normal_op: out must not alias in or tmp");
     DslashArgs d1 = base_args(g, tmp, in, 1);
-    const int block = dslash_block_size(fmt, d1.g, 1);
-    HISQ_TRY_HIP(launch_dslash(d1, fmt, block, (hipStream_t)stream));
+    const DslashPlan plan = dslash_plan(fmt, d1.g, 1, &d1, (hipStream_t)stream);
+    HISQ_TRY_HIP(launch_dslash(d1, fmt, plan, (hipStream_t)stream, nullptr));
     DslashArgs d2 = base_args(g, out, tmp, 0);
     d2.b = -1.0;
     d2.x = (const char *)in;
     d2.a = 4.0 * mass * mass + shift;
-    HISQ_TRY_HIP(launch_dslash(d2, fmt, block, (hipStream_t)stream));
+    HISQ_TRY_HIP(launch_dslash(d2, fmt, plan, (hipStream_t)stream, nullptr));
     return HISQ_OK;
 }
 
@@ -250,6 +255,7 @@ extern "C" hisq_status hisq_dslash_batched(void *out, const void *in, const hisq
     DslashArgs a = base_args(g, out, in, parity);
     a.nrhs = nrhs;
     a.field_stride = spinor_field_bytes((size_t)a.g.vh, fmt.spinor);
-    HISQ_TRY_HIP(launch_dslash_batched(a, fmt, dslash_block_size(fmt, a.g, nrhs), (hipStream_t)stream));
+    const DslashPlan plan = dslash_plan(fmt, a.g, nrhs, &a, (hipStream_t)stream);
+    HISQ_TRY_HIP(launch_dslash(a, fmt, plan, (hipStream_t)stream, nullptr));
     return HISQ_OK;
 }

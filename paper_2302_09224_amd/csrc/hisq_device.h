@@ -378,11 +378,32 @@ template <class R> struct GaugeIO<GF_FIX32, R> {
 // lattice geometry (checkerboarded, X even)
 // ---------------------------------------------------------------------------
 
+// n / d for 0 <= n < 2^31 as (n * m) >> (31 + sh), sh = ceil(log2 d),
+// m = ceil(2^(31+sh) / d) < 2^32: the rounding error n*(m - 2^(31+sh)/d) / 2^(31+sh)
+// is below 2^-sh <= 1/d, so the quotient is exact.
+struct FastDiv {
+    unsigned m;
+    int sh;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(unsigned d) {
+    FastDiv f;
+    f.sh = 0;
+    while ((1u << f.sh) < d) f.sh++;
+    f.m = (unsigned)(((1ull << (31 + f.sh)) + d - 1) / d);
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int n, FastDiv f) {
+    return (int)(((unsigned long long)(unsigned)n * f.m) >> (31 + f.sh));
+}
+
 struct Geom {
     int X, Y, Z, T;
     int X2;        // X/2
     int vh;        // sites per parity
     int sy, sz, st;  // checkerboard strides of +y, +z, +t: X2, X2*Y, X2*Y*Z
+    FastDiv dX2, dY, dZ;
 };
 
 // ---------------------------------------------------------------------------

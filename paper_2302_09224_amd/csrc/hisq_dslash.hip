@@ -1,13 +1,23 @@
 // hisq_dslash.hip -- dispatch of the Dslash launches on the precision triplet
-// gauge/fermion/compute (Sec. 4); the kernels themselves are instantiated in
-// hisq_dslash_t_*.hip (one translation unit per triplet).
+// gauge/fermion/compute (Sec. 4) and the launch-shape autotuner.  The kernels
+// are instantiated in hisq_dslash_t_*.hip (one translation unit per triplet).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
 #include "hisq_internal.h"
 
 namespace hisq {
 
-#define HISQ_DECL_TRIPLET(NAME)                                                           \
-    hipError_t dslash_launch_##NAME(const DslashArgs &a, int block, hipStream_t st);       \
-    hipError_t dslash_launch_batched_##NAME(const DslashArgs &a, int block, hipStream_t st);
+#define HISQ_DECL_TRIPLET(NAME) \
+    hipError_t dslash_launch_##NAME(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb);
 HISQ_DECL_TRIPLET(double)
 HISQ_DECL_TRIPLET(single)
 HISQ_DECL_TRIPLET(half)
@@ -16,37 +26,166 @@ HISQ_DECL_TRIPLET(int30)
 HISQ_DECL_TRIPLET(int30_fp32)
 
 namespace {
+
 inline int triplet_key(const hisq_fmt &f) { return f.gauge * 100 + f.spinor * 10 + (f.compute == 64 ? 1 : 0); }
+
+hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const DslashTile &t, hipStream_t st, int *nb) {
+    switch (triplet_key(f)) {
+    case GF_F64 * 100 + SF_F64 * 10 + 1: return dslash_launch_double(a, rhs0, t, st, nb);
+    case GF_F32 * 100 + SF_F32 * 10 + 0: return dslash_launch_single(a, rhs0, t, st, nb);
+    case GF_FIX16 * 100 + SF_HALF16 * 10 + 0: return dslash_launch_half(a, rhs0, t, st, nb);
+    case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_launch_int20(a, rhs0, t, st, nb);
+    case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_launch_int30(a, rhs0, t, st, nb);
+    case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_launch_int30_fp32(a, rhs0, t, st, nb);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+typedef std::tuple<int, int, int, int, int, int> TuneKey;  // triplet, X, Y, Z, T, rhs block
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<DslashTile, float>> g_tuned;
+
+bool tuning_enabled() {
+    const char *e = getenv("HISQ_TUNE");
+    return !(e && e[0] == '0');
+}
+
+// candidate shapes for a block of c right-hand sides (c a power of two <= 16)
+// grids: 0 = one tile per block; 256*k = a persistent grid of k blocks per CU
+std::vector<DslashTile> candidates(int c, bool batched_ok) {
+    std::vector<DslashTile> v;
+    if (c == 1) {
+        for (int st : {1, 2, 4, 8})
+            for (int blk : {128, 256})
+                for (int per_cu : {0, 4, 8}) v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk)});
+        return v;
+    }
+    if (!batched_ok) return v;
+    for (int nr : {1, 2, 4, 8, 16}) {
+        if (nr > c) break;
+        const int rg = c / nr;
+        for (int grid : {0, 2048}) {
+            v.push_back(DslashTile{nr, rg, 1, 256, grid});
+            if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid});
+        }
+    }
+    return v;
+}
+
+DslashTile default_tile(int c) {
+    if (c == 1) return DslashTile{1, 1, 8, 256, 0};
+    return DslashTile{1, c, 1, 256, 0};
+}
+
+// time one shape on the probe arguments (pure Dslash, idempotent: no xpay, no reduction)
+float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t, hipStream_t st) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float best = -1.f;
+    int nb = 0;
+    if (launch_one(probe, f, 0, t, st, &nb) == hipSuccess) {
+        const int reps = 3;
+        hipError_t e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_one(probe, f, 0, t, st, &nb);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = ms / reps;
+    }
+    (void)hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *probe, hipStream_t st) {
+    const TuneKey key{triplet_key(f), g.X, g.Y, g.Z, g.T, c};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second.first;
+    const bool batched_ok = !(f.gauge == GF_FIX32 && f.compute == 32);
+    DslashTile best = default_tile(c);
+    if (!probe || !tuning_enabled()) return best;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return best;
+    DslashArgs p = *probe;
+    p.x = p.y = nullptr;
+    p.red = RED_NONE;
+    p.guard = Guard{nullptr, 0, 0};
+    p.nrhs = c;
+    float tbest = -1.f;
+    for (const DslashTile &t : candidates(c, batched_ok)) {
+        const float ms = time_tile(p, f, t, st);
+        if (ms > 0.f && (tbest < 0.f || ms < tbest)) {
+            tbest = ms;
+            best = t;
+        }
+    }
+    g_tuned[key] = std::make_pair(best, tbest);
+    return best;
+}
+
 }  // namespace
 
-int dslash_blocks(int vh, int block) {
-    int nb = (vh + block - 1) / block;
+int dslash_blocks(int n, int block) {
+    int nb = (n + block - 1) / block;
     return (nb + 7) & ~7;
 }
 
-int dslash_block_size(const hisq_fmt &, const Geom &, int) { return 256; }
+size_t dslash_max_blocks(int vh) { return (size_t)dslash_blocks(vh * 16, 128); }
 
-hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st) {
-    switch (triplet_key(f)) {
-    case GF_F64 * 100 + SF_F64 * 10 + 1: return dslash_launch_double(a, block, st);
-    case GF_F32 * 100 + SF_F32 * 10 + 0: return dslash_launch_single(a, block, st);
-    case GF_FIX16 * 100 + SF_HALF16 * 10 + 0: return dslash_launch_half(a, block, st);
-    case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_launch_int20(a, block, st);
-    case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_launch_int30(a, block, st);
-    case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_launch_int30_fp32(a, block, st);
-    default: return hipErrorInvalidValue;
+DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st) {
+    DslashPlan plan;
+    plan.n = 0;
+    int done = 0;
+    while (done < nrhs && plan.n < 5) {
+        int c = 16;
+        while (c > nrhs - done) c >>= 1;
+        plan.rhs0[plan.n] = done;
+        plan.tile[plan.n] = tile_for(f, g, c, probe, st);
+        plan.n++;
+        done += c;
     }
+    return plan;
 }
 
-hipError_t launch_dslash_batched(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st) {
-    switch (triplet_key(f)) {
-    case GF_F64 * 100 + SF_F64 * 10 + 1: return dslash_launch_batched_double(a, block, st);
-    case GF_F32 * 100 + SF_F32 * 10 + 0: return dslash_launch_batched_single(a, block, st);
-    case GF_FIX16 * 100 + SF_HALF16 * 10 + 0: return dslash_launch_batched_half(a, block, st);
-    case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_launch_batched_int20(a, block, st);
-    case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_launch_batched_int30(a, block, st);
-    default: return hipErrorInvalidValue;
+hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPlan &plan, hipStream_t st, int *nblocks) {
+    for (int i = 0; i < plan.n; i++) {
+        int nb = 0;
+        const DslashTile &t = plan.tile[i];
+        hipError_t e = launch_one(a, f, plan.rhs0[i], t, st, &nb);
+        if (e != hipSuccess) return e;
+        if (nblocks)
+            for (int j = 0; j < t.nr * t.rg; j++) nblocks[plan.rhs0[i] + j] = nb;
     }
+    return hipSuccess;
 }
 
 }  // namespace hisq
+
+extern "C" size_t hisq_tune_report(char *buf, size_t len) {
+    std::string s;
+    {
+        std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
+        for (const auto &kv : hisq::g_tuned) {
+            char line[256];
+            const auto &k = kv.first;
+            const auto &t = kv.second.first;
+            snprintf(line, sizeof(line),
+                     "triplet %03d lattice %dx%dx%dx%d rhs-block %d: nr %d rg %d stage %d block %d grid %d (%.1f us)\n",
+                     std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                     t.nr, t.rg, t.stage, t.block, t.grid, kv.second.second * 1e3);
+            s += line;
+        }
+    }
+    if (buf && len) {
+        const size_t n = s.size() < len - 1 ? s.size() : len - 1;
+        memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return s.size() + 1;
+}

@@ -6,48 +6,185 @@
 //                 + L_mu(x) in(x+3mu) - L_mu(x-3mu)^dag in(x-3mu) ]
 // for the sites x of one parity (the stencil the paper benchmarks, Secs. 5.2-5.3).
 //
-// One lane per output site.  The kernel is bound by HBM bandwidth: every link
-// matrix is read exactly once per application (non-temporal, it is not reused),
-// while each input spinor is read by up to 16 neighbouring sites and must come
-// from L2 / the MALL after its first use.  The XCD-aware block order keeps the
-// +-3 neighbours of a contiguous site range inside one XCD's L2.  Storage is
-// unpacked to IEEE registers, the 16 3x3 complex mat-vecs run in the compute
-// precision of the triplet, and the result is packed again before the single
-// coalesced store (Sec. 1: the bandwidth-bound stencil gives the computational
-// budget for the unpack/pack work).  Optional epilogue: out = b*D(in) + a*x + c*y
-// and a per-block partial of Re<x,out> or |out|^2 taken on the stored values,
-// which fuses the solver's xpay and the first reduction of each CG step.
+// The kernel is bound by HBM bandwidth: every link matrix is read exactly once
+// per application (non-temporal loads: it is not reused), while each input
+// spinor is read by up to 16 neighbouring sites and comes from L2 / the MALL
+// after its first use.  The XCD-aware block order keeps the +-3 neighbours of a
+// contiguous site range inside one XCD's L2.
+//
+// Staging: the 16 hops are processed in stages of STAGE hops.  A stage first
+// issues the raw loads of its links and spinors (storage words, no decoding),
+// then a scheduling barrier, then unpacks to IEEE registers and accumulates the
+// mat-vecs in the compute precision.  STAGE sets how many bytes each lane keeps
+// in flight against how many registers it holds, i.e. memory-level parallelism
+// against occupancy; the autotuner picks it per triplet and lattice.
+//
+// Right-hand-side blocks (Sec. 1, "Block solvers"): a lane accumulates NR
+// right-hand sides for one site, and rg lanes (adjacent, same wavefront) share
+// a site and cover rg*NR right-hand sides, so each link is fetched from memory
+// once per block of right-hand sides while the register footprint per lane
+// stays bounded.  Single right-hand side: NR = rg = 1.
+//
+// Epilogue: out = b*D(in) + a*x + c*y, then the packed store and optionally a
+// per-block partial of Re<x,out> or |out|^2 on the stored values (per
+// right-hand side), which fuses the solver's xpay and first reduction.
 #pragma once
 #include "hisq_internal.h"
 
 namespace hisq {
 namespace dsl {
 
-template <int GF, int SF, class R>
-__device__ __forceinline__ void hop4(CVec<R> &acc, const char *in, size_t vh, const char *fat_fwd,
-                                     const char *fat_bwd, const char *lng_fwd, const char *lng_bwd, int s,
-                                     int f1, int b1, int f3, int b3, R gf, R gl) {
-    {
-        Mat<R> U = GaugeIO<GF, R>::load(fat_fwd, vh, s, gf);
-        CVec<R> v = SpinorIO<SF, R>::load(in, vh, f1);
-        mv_add(acc, U, v);
-    }
-    {
-        Mat<R> U = GaugeIO<GF, R>::load(fat_bwd, vh, b1, gf);
-        CVec<R> v = SpinorIO<SF, R>::load(in, vh, b1);
-        mdv_sub(acc, U, v);
-    }
-    {
-        Mat<R> U = GaugeIO<GF, R>::load(lng_fwd, vh, s, gl);
-        CVec<R> v = SpinorIO<SF, R>::load(in, vh, f3);
-        mv_add(acc, U, v);
-    }
-    {
-        Mat<R> U = GaugeIO<GF, R>::load(lng_bwd, vh, b3, gl);
-        CVec<R> v = SpinorIO<SF, R>::load(in, vh, b3);
-        mdv_sub(acc, U, v);
-    }
+// ---------------------------------------------------------------------------
+// raw storage words of one link / one site
+// ---------------------------------------------------------------------------
+
+template <int GF> struct LinkRaw;
+template <> struct LinkRaw<GF_F64> { f64x2 w[9]; };
+template <> struct LinkRaw<GF_F32> { f32x4 w[4]; f32x2 t; };
+template <> struct LinkRaw<GF_FIX16> { u32x4 w[2]; unsigned t; };
+template <> struct LinkRaw<GF_FIX32> { u32x4 w[4]; u32x2 t; };
+
+template <int GF> __device__ __forceinline__ LinkRaw<GF> link_load(const char *sub, size_t vh, size_t s);
+
+template <> __device__ __forceinline__ LinkRaw<GF_F64> link_load<GF_F64>(const char *sub, size_t vh, size_t s) {
+    LinkRaw<GF_F64> L;
+#pragma unroll
+    for (int k = 0; k < 9; k++) L.w[k] = ld_nt<f64x2>(sub + k * 16 * vh + 16 * s);
+    return L;
 }
+template <> __device__ __forceinline__ LinkRaw<GF_F32> link_load<GF_F32>(const char *sub, size_t vh, size_t s) {
+    LinkRaw<GF_F32> L;
+#pragma unroll
+    for (int k = 0; k < 4; k++) L.w[k] = ld_nt<f32x4>(sub + k * 16 * vh + 16 * s);
+    L.t = ld_nt<f32x2>(sub + 64 * vh + 8 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw<GF_FIX16> link_load<GF_FIX16>(const char *sub, size_t vh, size_t s) {
+    LinkRaw<GF_FIX16> L;
+    L.w[0] = ld_nt<u32x4>(sub + 16 * s);
+    L.w[1] = ld_nt<u32x4>(sub + 16 * vh + 16 * s);
+    L.t = ld_nt<unsigned>(sub + 32 * vh + 4 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw<GF_FIX32> link_load<GF_FIX32>(const char *sub, size_t vh, size_t s) {
+    LinkRaw<GF_FIX32> L;
+#pragma unroll
+    for (int k = 0; k < 4; k++) L.w[k] = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+    L.t = ld_nt<u32x2>(sub + 64 * vh + 8 * s);
+    return L;
+}
+
+template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_F64> &L, R) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        U.re[k] = (R)L.w[k].x;
+        U.im[k] = (R)L.w[k].y;
+    }
+    return U;
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_F32> &L, R) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        U.re[2 * k] = L.w[k].x; U.im[2 * k] = L.w[k].y; U.re[2 * k + 1] = L.w[k].z; U.im[2 * k + 1] = L.w[k].w;
+    }
+    U.re[8] = L.t.x;
+    U.im[8] = L.t.y;
+    return U;
+}
+// 16-bit fixed point: u = q * g, g = (compute precision)(max/32767)
+template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_FIX16> &L, R g) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const unsigned ws[4] = {L.w[k].x, L.w[k].y, L.w[k].z, L.w[k].w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            U.re[4 * k + j] = (R)sext16(ws[j]) * g;
+            U.im[4 * k + j] = (R)sext16(ws[j] >> 16) * g;
+        }
+    }
+    U.re[8] = (R)sext16(L.t) * g;
+    U.im[8] = (R)sext16(L.t >> 16) * g;
+    return U;
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_FIX32> &L, R g) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        U.re[2 * k] = (R)(int)L.w[k].x * g; U.im[2 * k] = (R)(int)L.w[k].y * g;
+        U.re[2 * k + 1] = (R)(int)L.w[k].z * g; U.im[2 * k + 1] = (R)(int)L.w[k].w * g;
+    }
+    U.re[8] = (R)(int)L.t.x * g;
+    U.im[8] = (R)(int)L.t.y * g;
+    return U;
+}
+
+template <int SF> struct SpinRaw;
+template <> struct SpinRaw<SF_F64> { f64x2 w[3]; };
+template <> struct SpinRaw<SF_F32> { f32x4 a; f32x2 b; };
+template <> struct SpinRaw<SF_HALF16> { u32x4 w; };
+template <> struct SpinRaw<SF_INT20> { u32x4 w; };
+template <> struct SpinRaw<SF_INT30> { u32x4 a; u32x2 b; };
+
+template <int SF> __device__ __forceinline__ SpinRaw<SF> spin_load(const char *base, size_t n, size_t s);
+template <> __device__ __forceinline__ SpinRaw<SF_F64> spin_load<SF_F64>(const char *base, size_t n, size_t s) {
+    SpinRaw<SF_F64> P;
+#pragma unroll
+    for (int c = 0; c < 3; c++) P.w[c] = ld<f64x2>(base + c * 16 * n + 16 * s);
+    return P;
+}
+template <> __device__ __forceinline__ SpinRaw<SF_F32> spin_load<SF_F32>(const char *base, size_t n, size_t s) {
+    SpinRaw<SF_F32> P;
+    P.a = ld<f32x4>(base + 16 * s);
+    P.b = ld<f32x2>(base + 16 * n + 8 * s);
+    return P;
+}
+template <> __device__ __forceinline__ SpinRaw<SF_HALF16> spin_load<SF_HALF16>(const char *base, size_t, size_t s) {
+    SpinRaw<SF_HALF16> P;
+    P.w = ld<u32x4>(base + 16 * s);
+    return P;
+}
+template <> __device__ __forceinline__ SpinRaw<SF_INT20> spin_load<SF_INT20>(const char *base, size_t, size_t s) {
+    SpinRaw<SF_INT20> P;
+    P.w = ld<u32x4>(base + 16 * s);
+    return P;
+}
+template <> __device__ __forceinline__ SpinRaw<SF_INT30> spin_load<SF_INT30>(const char *base, size_t n, size_t s) {
+    SpinRaw<SF_INT30> P;
+    P.a = ld<u32x4>(base + 16 * s);
+    P.b = ld<u32x2>(base + 16 * n + 8 * s);
+    return P;
+}
+
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_F64> &P) {
+    CVec<R> v;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        v.re[c] = (R)P.w[c].x;
+        v.im[c] = (R)P.w[c].y;
+    }
+    return v;
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_F32> &P) {
+    CVec<R> v;
+    v.re[0] = P.a.x; v.im[0] = P.a.y; v.re[1] = P.a.z; v.im[1] = P.a.w; v.re[2] = P.b.x; v.im[2] = P.b.y;
+    return v;
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_HALF16> &P) {
+    return SpinorIO<SF_HALF16, R>::decode(P.w);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT20> &P) {
+    return SpinorIO<SF_INT20, R>::decode(P.w);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT30> &P) {
+    return SpinorIO<SF_INT30, R>::decode(P.a, P.b);
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
 
 // checkerboard indices of the +-1, +-3 neighbours of site s along each direction
 struct Nbrs {
@@ -62,12 +199,12 @@ __device__ __forceinline__ int wrap_add(int c, int h, int L) {
 }
 
 __device__ __forceinline__ Nbrs neighbours(const Geom &g, int s, int parity) {
-    const int xcb = s % g.X2;
-    int r = s / g.X2;
-    const int y = r % g.Y;
-    r /= g.Y;
-    const int z = r % g.Z;
-    const int t = r / g.Z;
+    int r = fdiv(s, g.dX2);
+    const int xcb = s - r * g.X2;
+    int r2 = fdiv(r, g.dY);
+    const int y = r - r2 * g.Y;
+    const int t = fdiv(r2, g.dZ);
+    const int z = r2 - t * g.Z;
     const int x = 2 * xcb + ((y + z + t + parity) & 1);
     const int row = s - xcb;
     Nbrs n;
@@ -90,124 +227,134 @@ __device__ __forceinline__ Nbrs neighbours(const Geom &g, int s, int parity) {
     return n;
 }
 
-template <int GF, int SF, class R, bool RED>
-__global__ void __launch_bounds__(256) k_dslash(DslashArgs A) {
-    __shared__ double lds[16];
-    if (!A.guard.pass()) return;
-    const Geom g = A.g;
-    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    double red = 0.0;
-    if (s < g.vh) {
-        const size_t vh = (size_t)g.vh;
-        const int p = A.parity, q = 1 - p;
-        const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
-        const R gf = (R)A.gfat, gl = (R)A.glong;
-        const Nbrs n = neighbours(g, s, p);
-        CVec<R> acc;
-        cvec_zero(acc);
-#pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            hop4<GF, SF, R>(acc, A.in, vh, A.fat + (2 * mu + p) * sub, A.fat + (2 * mu + q) * sub,
-                            A.lng + (2 * mu + p) * sub, A.lng + (2 * mu + q) * sub, s, n.f1[mu], n.b1[mu],
-                            n.f3[mu], n.b3[mu], gf, gl);
-        }
-        const R b = (R)A.b;
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            acc.re[c] *= b;
-            acc.im[c] *= b;
-        }
-        CVec<R> xv;
-        cvec_zero(xv);
-        if (A.x) {
-            xv = SpinorIO<SF, R>::load(A.x, vh, s);
-            const R a = (R)A.a;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc.re[c] = fma(a, xv.re[c], acc.re[c]);
-                acc.im[c] = fma(a, xv.im[c], acc.im[c]);
-            }
-        }
-        if (A.y) {
-            CVec<R> yv = SpinorIO<SF, R>::load(A.y, vh, s);
-            const R cc = (R)A.c;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc.re[c] = fma(cc, yv.re[c], acc.re[c]);
-                acc.im[c] = fma(cc, yv.im[c], acc.im[c]);
-            }
-        }
-        CVec<R> o = SpinorIO<SF, R>::store(A.out, vh, s, acc);
-        if (RED) {
-            if (A.red == RED_DOT_X) {
-#pragma unroll
-                for (int c = 0; c < 3; c++) red += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; c++) red += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
-            }
-        }
-    }
-    if (RED) {
-        double v[1] = {red};
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0) A.partial[blockIdx.x] = v[0];
-    }
+// hop h = 4*mu + kind, kind 0: F_mu(x) in(x+mu); 1: -F_mu(x-mu)^dag in(x-mu);
+// 2: L_mu(x) in(x+3mu); 3: -L_mu(x-3mu)^dag in(x-3mu)
+__device__ __forceinline__ int hop_spinor_site(const Nbrs &n, int h) {
+    const int mu = h >> 2, kind = h & 3;
+    return kind == 0 ? n.f1[mu] : kind == 1 ? n.b1[mu] : kind == 2 ? n.f3[mu] : n.b3[mu];
 }
 
-// Block of NR right-hand sides: each link matrix is loaded once and applied to
-// all NR spinors of the block (Sec. 1, "Block solvers").  Fields j of in/out/x
-// are at byte offset j*field_stride.  Partials: [block][rhs0 + j] with row
-// length A.nrhs (the total number of right-hand sides).
-template <int GF, int SF, class R, int NR, bool RED>
-__global__ void __launch_bounds__(256) k_dslash_batched(DslashArgs A, int rhs0) {
-    __shared__ double lds[4 * NR];
-    if (!A.guard.pass()) return;
+// site coordinates of checkerboard index s (parity p)
+struct Coords {
+    int x, y, z, t, row;
+};
+
+__device__ __forceinline__ Coords coords_of(const Geom &g, int s, int parity) {
+    Coords c;
+    const int r = fdiv(s, g.dX2);
+    const int xcb = s - r * g.X2;
+    const int r2 = fdiv(r, g.dY);
+    c.y = r - r2 * g.Y;
+    c.t = fdiv(r2, g.dZ);
+    c.z = r2 - c.t * g.Z;
+    c.x = 2 * xcb + ((c.y + c.z + c.t + parity) & 1);
+    c.row = s - xcb;
+    return c;
+}
+
+// spinor (and backward-link) site of hop h computed at run time
+__device__ __forceinline__ int hop_site_rt(const Geom &g, const Coords &c, int s, int h) {
+    const int mu = h >> 2, kind = h & 3;
+    const int d = ((kind & 2) ? 3 : 1) * ((kind & 1) ? -1 : 1);
+    if (mu == 0) return c.row + (wrap_add(c.x, d, g.X) >> 1);
+    const int co = mu == 1 ? c.y : mu == 2 ? c.z : c.t;
+    const int L = mu == 1 ? g.Y : mu == 2 ? g.Z : g.T;
+    const int stride = mu == 1 ? g.sy : mu == 2 ? g.sz : g.st;
+    return s + (wrap_add(co, d, L) - co) * stride;
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+
+// GUARD: launched inside a solver's block of iterations (may return at once);
+// standalone applications use the unguarded instantiation.
+template <int GF, int SF, class R, int NR, int STAGE, bool RED, bool GUARD>
+__global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, FastDiv drg) {
+    __shared__ double lds[64];
+    if (GUARD && !A.guard.pass()) return;
     const Geom g = A.g;
-    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const size_t fs = A.field_stride;
     double red[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) red[j] = 0.0;
+    // Tiles of blockDim lanes; XCD k (blocks b with b % 8 == k) sweeps the
+    // contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
+    // gridDim/8 blocks taking every (gridDim/8)-th tile: one tile per block when
+    // the grid covers the lattice, a persistent grid-stride sweep otherwise.
+    const int ntile = (int)(((long long)g.vh * rg + blockDim.x - 1) / blockDim.x);
+    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7;
+    const int tend = (int)(((long long)ntile * (xcd + 1)) >> 3);
+    for (int tile = (int)(((long long)ntile * xcd) >> 3) + (int)(blockIdx.x >> 3); tile < tend; tile += per) {
+    const int tid = tile * blockDim.x + threadIdx.x;
+    const int s = rg == 1 ? tid : fdiv(tid, drg);
+    const int grp = tid - s * rg;
+    const int r0 = rhs0 + grp * NR;
     if (s < g.vh) {
         const size_t vh = (size_t)g.vh;
         const int p = A.parity, q = 1 - p;
         const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
         const R gf = (R)A.gfat, gl = (R)A.glong;
-        const Nbrs n = neighbours(g, s, p);
-        const char *in = A.in + (size_t)rhs0 * fs;
+        const char *in = A.in + (size_t)r0 * fs;
         CVec<R> acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
+        if (NR > 1) {
+            // several right-hand sides per lane: one hop at a time (bounded registers)
+            const Coords c = coords_of(g, s, p);
+#pragma unroll 1
+            for (int h = 0; h < 16; h++) {
+                const int ss = hop_site_rt(g, c, s, h);
+                const int ls = (h & 1) ? ss : s;
+                const char *field = (h & 2) ? A.lng : A.fat;
+                const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + ((h & 1) ? q : p)) * sub, vh, ls);
+                SpinRaw<SF> Pr[NR];
 #pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            const char *fsub[2] = {A.fat + (2 * mu + p) * sub, A.fat + (2 * mu + q) * sub};
-            const char *lsub[2] = {A.lng + (2 * mu + p) * sub, A.lng + (2 * mu + q) * sub};
-            {
-                Mat<R> U = GaugeIO<GF, R>::load(fsub[0], vh, s, gf);
+                for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
+                const Mat<R> U = link_decode<R>(Lr, (h & 2) ? gl : gf);
+                if (h & 1) {
 #pragma unroll
-                for (int j = 0; j < NR; j++) mv_add(acc[j], U, SpinorIO<SF, R>::load(in + j * fs, vh, n.f1[mu]));
-            }
-            {
-                Mat<R> U = GaugeIO<GF, R>::load(fsub[1], vh, n.b1[mu], gf);
+                    for (int j = 0; j < NR; j++) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
+                } else {
 #pragma unroll
-                for (int j = 0; j < NR; j++) mdv_sub(acc[j], U, SpinorIO<SF, R>::load(in + j * fs, vh, n.b1[mu]));
-            }
-            {
-                Mat<R> U = GaugeIO<GF, R>::load(lsub[0], vh, s, gl);
-#pragma unroll
-                for (int j = 0; j < NR; j++) mv_add(acc[j], U, SpinorIO<SF, R>::load(in + j * fs, vh, n.f3[mu]));
-            }
-            {
-                Mat<R> U = GaugeIO<GF, R>::load(lsub[1], vh, n.b3[mu], gl);
-#pragma unroll
-                for (int j = 0; j < NR; j++) mdv_sub(acc[j], U, SpinorIO<SF, R>::load(in + j * fs, vh, n.b3[mu]));
+                    for (int j = 0; j < NR; j++) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
+                }
             }
         }
-        const R b = (R)A.b, a = (R)A.a;
+        const Nbrs n = neighbours(g, s, p);
+#pragma unroll
+        for (int h0 = 0; h0 < (NR > 1 ? 0 : 16); h0 += STAGE) {
+            LinkRaw<GF> L[STAGE];
+            SpinRaw<SF> P[STAGE][NR];
+#pragma unroll
+            for (int i = 0; i < STAGE; i++) {
+                const int h = h0 + i;
+                const int ss = hop_spinor_site(n, h);
+                const int ls = (h & 1) ? ss : s;
+                const char *field = (h & 2) ? A.lng : A.fat;
+                L[i] = link_load<GF>(field + (size_t)(2 * (h >> 2) + ((h & 1) ? q : p)) * sub, vh, ls);
+#pragma unroll
+                for (int j = 0; j < NR; j++) P[i][j] = spin_load<SF>(in + j * fs, vh, ss);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < STAGE; i++) {
+                const int h = h0 + i;
+                const Mat<R> U = link_decode<R>(L[i], (h & 2) ? gl : gf);
+#pragma unroll
+                for (int j = 0; j < NR; j++) {
+                    const CVec<R> v = spin_decode<R>(P[i][j]);
+                    if (h & 1)
+                        mdv_sub(acc[j], U, v);
+                    else
+                        mv_add(acc[j], U, v);
+                }
+            }
+        }
+        const R b = (R)A.b, a = (R)A.a, cc = (R)A.c;
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-            const size_t off = (size_t)(rhs0 + j) * fs;
+            const size_t off = (size_t)(r0 + j) * fs;
             CVec<R> xv;
             cvec_zero(xv);
 #pragma unroll
@@ -224,81 +371,95 @@ __global__ void __launch_bounds__(256) k_dslash_batched(DslashArgs A, int rhs0) 
                 }
             }
             if (A.y) {
-                CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
-                const R cc = (R)A.c;
+                const CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     acc[j].re[c] = fma(cc, yv.re[c], acc[j].re[c]);
                     acc[j].im[c] = fma(cc, yv.im[c], acc[j].im[c]);
                 }
             }
-            CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
+            const CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
             if (RED) {
                 if (A.red == RED_DOT_X) {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
+                    for (int c = 0; c < 3; c++)
+                        red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+                    for (int c = 0; c < 3; c++)
+                        red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
                 }
             }
         }
     }
+    }
     if (RED) {
-        block_sum<NR>(red, lds);
-        if (threadIdx.x == 0) {
+        // per right-hand side: sum over the lanes of the same group (lanes l with
+        // l % rg == grp; rg is a power of two dividing 64), then over the waves
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-            for (int j = 0; j < NR; j++) A.partial[(size_t)blockIdx.x * A.nrhs + rhs0 + j] = red[j];
+        for (int j = 0; j < NR; j++) {
+            double v = red[j];
+            for (int o = 32; o >= rg; o >>= 1) v += __shfl_xor(v, o, 64);
+            red[j] = v;
+        }
+        if (lane < rg) {
+#pragma unroll
+            for (int j = 0; j < NR; j++) lds[w * rg * NR + lane * NR + j] = red[j];
+        }
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < rg * NR) {
+            double v = 0.0;
+            for (int ww = 0; ww < nw; ww++) v += lds[ww * rg * NR + k];
+            A.partial[(size_t)(rhs0 + k) * A.pstride + blockIdx.x] = v;
         }
     }
 }
 
-template <int GF, int SF, class R>
-hipError_t launch_one(const DslashArgs &a, int block, hipStream_t st) {
-    const int nb = dslash_blocks(a.g.vh, block);
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int GF, int SF, class R, int NR, int STAGE>
+hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, hipStream_t st, int *nblocks) {
+    int nb = dslash_blocks(a.g.vh * rg, block);
+    if (grid > 0 && grid < nb) nb = grid;
+    if (nblocks) *nblocks = nb;
+    const FastDiv drg = make_fastdiv((unsigned)rg);
     if (a.red != RED_NONE)
-        hipLaunchKernelGGL((k_dslash<GF, SF, R, true>), dim3(nb), dim3(block), 0, st, a);
+        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+    else if (a.guard.stop)
+        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
     else
-        hipLaunchKernelGGL((k_dslash<GF, SF, R, false>), dim3(nb), dim3(block), 0, st, a);
+        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
     return hipGetLastError();
 }
 
-template <int GF, int SF, class R, int NR>
-hipError_t launch_batched_nr(const DslashArgs &a, int rhs0, int block, hipStream_t st) {
-    const int nb = dslash_blocks(a.g.vh, block);
-    if (a.red != RED_NONE)
-        hipLaunchKernelGGL((k_dslash_batched<GF, SF, R, NR, true>), dim3(nb), dim3(block), 0, st, a, rhs0);
-    else
-        hipLaunchKernelGGL((k_dslash_batched<GF, SF, R, NR, false>), dim3(nb), dim3(block), 0, st, a, rhs0);
-    return hipGetLastError();
-}
-
-template <int GF, int SF, class R>
-hipError_t launch_batched(const DslashArgs &a, int block, hipStream_t st) {
-    // split nrhs into blocks of 16, 8, 4, 2, 1 right-hand sides
-    int done = 0;
-    while (done < a.nrhs) {
-        const int left = a.nrhs - done;
-        hipError_t e;
-        if (left >= 16) {
-            e = launch_batched_nr<GF, SF, R, 16>(a, done, block, st);
-            done += 16;
-        } else if (left >= 8) {
-            e = launch_batched_nr<GF, SF, R, 8>(a, done, block, st);
-            done += 8;
-        } else if (left >= 4) {
-            e = launch_batched_nr<GF, SF, R, 4>(a, done, block, st);
-            done += 4;
-        } else if (left >= 2) {
-            e = launch_batched_nr<GF, SF, R, 2>(a, done, block, st);
-            done += 2;
-        } else {
-            e = launch_batched_nr<GF, SF, R, 1>(a, done, block, st);
-            done += 1;
-        }
-        if (e != hipSuccess) return e;
+// one launch covering right-hand sides [rhs0, rhs0 + nr*rg) with the tile (nr, rg, stage);
+// rg must be a power of two <= 16 and nr*rg <= 16 (the per-group reduction)
+template <int GF, int SF, class R, bool BATCHED>
+hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nblocks) {
+    if (t.rg < 1 || t.rg > 16 || (t.rg & (t.rg - 1)) || t.nr * t.rg > 16 || (t.block != 128 && t.block != 256) ||
+        t.grid < 0 || (t.grid & 7))
+        return hipErrorInvalidValue;
+    switch (t.nr * 100 + t.stage) {
+    case 101: return launch_cfg<GF, SF, R, 1, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+    case 102: return launch_cfg<GF, SF, R, 1, 2>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+    case 104: return launch_cfg<GF, SF, R, 1, 4>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+    case 108: return launch_cfg<GF, SF, R, 1, 8>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+    default: break;
     }
-    return hipSuccess;
+    if (BATCHED) {
+        switch (t.nr * 100 + t.stage) {
+        case 201: return launch_cfg<GF, SF, R, 2, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+        case 401: return launch_cfg<GF, SF, R, 4, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+        case 801: return launch_cfg<GF, SF, R, 8, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+        case 1601: return launch_cfg<GF, SF, R, 16, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dsl

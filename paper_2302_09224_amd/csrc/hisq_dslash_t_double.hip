@@ -1,14 +1,10 @@
-// Dslash instantiation for the triplet GF_F64 / SF_F64 / double compute.
+// Dslash instantiations for the triplet GF_F64 / SF_F64 / double compute.
 #include "hisq_dslash_kernels.h"
 
 namespace hisq {
 
-hipError_t dslash_launch_double(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_one<GF_F64, SF_F64, double>(a, block, st);
-}
-
-hipError_t dslash_launch_batched_double(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_batched<GF_F64, SF_F64, double>(a, block, st);
+hipError_t dslash_launch_double(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb) {
+    return dsl::launch_tile<GF_F64, SF_F64, double, true>(a, rhs0, t, st, nb);
 }
 
 }  // namespace hisq

@@ -1,14 +1,10 @@
-// Dslash instantiation for the triplet GF_FIX16 / SF_HALF16 / float compute.
+// Dslash instantiations for the triplet GF_FIX16 / SF_HALF16 / float compute.
 #include "hisq_dslash_kernels.h"
 
 namespace hisq {
 
-hipError_t dslash_launch_half(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_one<GF_FIX16, SF_HALF16, float>(a, block, st);
-}
-
-hipError_t dslash_launch_batched_half(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_batched<GF_FIX16, SF_HALF16, float>(a, block, st);
+hipError_t dslash_launch_half(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb) {
+    return dsl::launch_tile<GF_FIX16, SF_HALF16, float, true>(a, rhs0, t, st, nb);
 }
 
 }  // namespace hisq

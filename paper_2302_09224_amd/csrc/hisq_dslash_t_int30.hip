@@ -1,14 +1,10 @@
-// Dslash instantiation for the triplet GF_FIX32 / SF_INT30 / double compute.
+// Dslash instantiations for the triplet GF_FIX32 / SF_INT30 / double compute.
 #include "hisq_dslash_kernels.h"
 
 namespace hisq {
 
-hipError_t dslash_launch_int30(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_one<GF_FIX32, SF_INT30, double>(a, block, st);
-}
-
-hipError_t dslash_launch_batched_int30(const DslashArgs &a, int block, hipStream_t st) {
-    return dsl::launch_batched<GF_FIX32, SF_INT30, double>(a, block, st);
+hipError_t dslash_launch_int30(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb) {
+    return dsl::launch_tile<GF_FIX32, SF_INT30, double, true>(a, rhs0, t, st, nb);
 }
 
 }  // namespace hisq

@@ -63,20 +63,42 @@ struct DslashArgs {
     double *partial;
     Guard guard;
     size_t field_stride;  // batched: bytes between consecutive right-hand-side fields
-    int nrhs;             // batched: right-hand sides in this launch
+    int nrhs;             // right-hand sides of the whole application (partials per block)
+    size_t pstride;       // partial of right-hand side j, block b at partial[j*pstride + b]
 };
 
-// blocks of a Dslash launch over vh sites (multiple of 8 for the XCD order)
-int dslash_blocks(int vh, int block);
-int dslash_block_size(const hisq_fmt &f, const Geom &g, int nrhs);
-hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st);
-hipError_t launch_dslash_batched(const DslashArgs &a, const hisq_fmt &f, int block, hipStream_t st);
+// Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
+// sides of one site, `rg` adjacent lanes share a site (nr*rg right-hand sides
+// per launch), the 16 hops are loaded in stages of `stage`, `block` threads,
+// `grid` blocks (0: one tile of lanes per block; otherwise a persistent grid,
+// a multiple of 8, sweeping the tiles).
+struct DslashTile {
+    int nr, rg, stage, block, grid;
+};
+
+// A whole application: launches covering right-hand sides [rhs0[i], rhs0[i]+nr*rg)
+struct DslashPlan {
+    int n;
+    int rhs0[5];
+    DslashTile tile[5];
+};
+
+// blocks of a Dslash launch over n lanes (multiple of 8 for the XCD order)
+int dslash_blocks(int n, int block);
+// largest block count any plan for (vh, nrhs) can use, per right-hand side
+size_t dslash_max_blocks(int vh);
+// plan (autotuned on first use when a probe is given and the stream is not capturing)
+DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st);
+// launch a plan; nblocks[j] receives the block count used for right-hand side j
+hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPlan &plan, hipStream_t st,
+                         int *nblocks);
 
 // ---------------------------------------------------------------------------
 // pack / unpack / reductions / solver BLAS
 // ---------------------------------------------------------------------------
 
 constexpr int BLAS_BLOCK = 256;
+constexpr int BLAS_MAX_BLOCKS = 2048;  // 8 blocks per CU: the best streaming grid on MI355X
 int blas_blocks(size_t n);  // grid of the streaming kernels (fixed cap, grid-stride)
 
 hipError_t launch_spinor_pack(char *dst, const double *src, size_t n, int sf, hipStream_t st);

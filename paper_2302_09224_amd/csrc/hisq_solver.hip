@@ -235,7 +235,7 @@ struct Carver {
 };
 
 size_t partial_doubles(const Geom &g, int nrhs) {
-    const size_t a = (size_t)dslash_blocks(g.vh, 64) * std::max(1, nrhs);
+    const size_t a = dslash_max_blocks(g.vh) * std::max(1, nrhs);
     const size_t b = (size_t)4096 * 4 * std::max(1, nrhs);
     return std::max(a, b);
 }
@@ -315,6 +315,19 @@ struct Run {
     double alg_bytes = 0.0;
     int last_slot = 0;         // slot of the current gradient vector when the run ended
     hipGraphExec_t exec = nullptr;
+    DslashPlan plan_s{}, plan_64{};
+    int nb_s = 0, nb_64 = 0;
+
+    // launch shapes of the sloppy and FP64 Dslash (autotuned on first use, outside capture)
+    void setup_plans() {
+        const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
+        DslashArgs ps = dargs(gs, B->ts, B->rs, 1);
+        plan_s = dslash_plan(fmt, g, 1, &ps, st);
+        nb_s = dslash_blocks(g.vh * plan_s.tile[0].rg, plan_s.tile[0].block);
+        DslashArgs p64 = dargs(g64, B->t64, B->x64, 1);
+        plan_64 = dslash_plan(f64, g, 1, &p64, st);
+        nb_64 = dslash_blocks(g.vh * plan_64.tile[0].rg, plan_64.tile[0].block);
+    }
 
     DslashArgs dargs(const hisq_gauge *gg, char *out, const char *in, int parity) const {
         DslashArgs a;
@@ -338,10 +351,9 @@ struct Run {
         const int jb = j % nb, jn = (j + 1) % nb;
         SolverCtrl *c = B->ctrl;
         const Guard gns{&c->stop, j, 0}, gs_{&c->stop, j, 1};
-        const int block = 256;
         DslashArgs A = dargs(gs, B->ts, B->p[jb], 1);
         A.guard = gns;
-        HISQ_TRY_HIP(launch_dslash(A, fmt, block, st));
+        HISQ_TRY_HIP(launch_dslash(A, fmt, plan_s, st, nullptr));
         DslashArgs Bk = dargs(gs, B->aps, B->ts, 0);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
@@ -349,9 +361,9 @@ struct Run {
         Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
         Bk.guard = gns;
-        HISQ_TRY_HIP(launch_dslash(Bk, fmt, block, st));
+        HISQ_TRY_HIP(launch_dslash(Bk, fmt, plan_s, st, nullptr));
         hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial,
-                           dslash_blocks(g.vh, block), jb, gns);
+                           nb_s, jb, gns);
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_cg_axpy(B->rs, B->aps, &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), gns,
@@ -379,7 +391,7 @@ struct Run {
     hisq_status enq_true_residual() {
         const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
         DslashArgs A = dargs(g64, B->t64, B->x64, 1);
-        HISQ_TRY_HIP(launch_dslash(A, f64, 256, st));
+        HISQ_TRY_HIP(launch_dslash(A, f64, plan_64, st, nullptr));
         DslashArgs Bk = dargs(g64, B->r64, B->t64, 0);
         Bk.b = 1.0;
         Bk.x = B->x64;
@@ -388,9 +400,9 @@ struct Run {
         Bk.c = 1.0;
         Bk.red = RED_NORM;
         Bk.partial = B->partial;
-        HISQ_TRY_HIP(launch_dslash(Bk, f64, 256, st));
+        HISQ_TRY_HIP(launch_dslash(Bk, f64, plan_64, st, nullptr));
         hipLaunchKernelGGL(k_fin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, B->ctrl, B->partial,
-                           dslash_blocks(g.vh, 256));
+                           nb_64);
         HISQ_TRY_HIP(hipGetLastError());
         dslash_f64 += 2;
         alg_bytes += 2.0 * vh * (16.0 * 144 + 2 * 48) + 2.0 * vh * 48;
@@ -564,6 +576,7 @@ hisq_status cg_core(Run &R, const hisq_solver_params &p, double tol, int mode, c
     init_ctrl(h, p, tol, 0.0);
     h->rho_prev = rho_prev;
     HISQ_TRY_HIP(hipMemcpyAsync(R.B->ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, R.st));
+    R.setup_plans();
     HISQ_TRY(enq_b2(R));
     HISQ_TRY(R.enq_reliable(mode, 0, mode == 2 ? p_init : nullptr));
     HISQ_TRY(R.read_ctrl(h));
@@ -774,6 +787,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
             h->active_mask |= 1 << i;
         }
         HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
+        R.setup_plans();
         HISQ_TRY(enq_b2(R));
         HISQ_TRY(R.enq_reliable(1, 0, nullptr));  // x = 0: r = b, p_0 = r
         // every shifted gradient vector starts as p_i = b (stored in the sloppy format)

@@ -130,6 +130,7 @@ def load():
         "hisq_cg_solve_batched": (i, [vp, vp, i, G, G, d, d, d, hisq_fmt, P, vp, sz, S, vp]),
         "hisq_last_error": (ctypes.c_char_p, []),
         "hisq_version": (ctypes.c_char_p, []),
+        "hisq_tune_report": (sz, [ctypes.c_char_p, sz]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -268,6 +269,14 @@ def hisq_cg_solve_batched(x, b, nrhs, g64, gs, mass, shift, tol, sloppy, params,
 
 def hisq_last_error():
     return load().hisq_last_error().decode()
+
+
+def hisq_tune_report():
+    lib = load()
+    n = lib.hisq_tune_report(None, 0)
+    buf = ctypes.create_string_buffer(int(n))
+    lib.hisq_tune_report(buf, n)
+    return buf.value.decode()
 
 
 def hisq_version():

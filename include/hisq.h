@@ -77,18 +77,28 @@ typedef struct {
     int compute;
 } hisq_fmt;
 
-/* A packed pair of link fields, filled by hisq_gauge_pack. */
+/* Storage of the long (Naik) links: all 18 reals, or two rows (12 reals) from
+ * which the third is rebuilt (Sec. 1, "Compression": special unitary matrices). */
+#define HISQ_RECON_18 18
+#define HISQ_RECON_12 12
+
+/* A packed pair of link fields, filled by hisq_gauge_pack / hisq_gauge_pack_recon. */
 typedef struct {
     int dims[4];
     int fmt;              /* HISQ_GAUGE_* */
     const void *fat;      /* (device) packed one-link (fat) field */
     const void *lng;      /* (device) packed three-link (Naik) field */
     double fat_max;       /* global max |real component| of the fat field (fixed-point scale) */
-    double long_max;      /* same for the long field */
+    double long_max;      /* same for the long field (two-row storage: max |component| of U) */
+    int long_recon;       /* HISQ_RECON_18 or HISQ_RECON_12 */
+    double long_coeff;    /* two-row storage: L_mu(x) = long_coeff * phase_mu(x) * U, U in SU(3) */
 } hisq_gauge;
 
 /* Bytes of ONE packed link field (fat or long): 4*V matrices. */
 size_t hisq_gauge_bytes(const int dims[4], int gauge_fmt);
+
+/* Bytes of the packed long field with HISQ_RECON_18 or HISQ_RECON_12 storage. */
+size_t hisq_gauge_long_bytes(const int dims[4], int gauge_fmt, int long_recon);
 
 /* Bytes of one packed single-parity spinor of `nsites` sites (Vh for a field). */
 size_t hisq_spinor_bytes(long nsites, int spinor_fmt);
@@ -103,6 +113,21 @@ size_t hisq_spinor_bytes(long nsites, int spinor_fmt);
 hisq_status hisq_gauge_pack(hisq_gauge *g, void *fat_dst, void *long_dst,
                             const double *fat_src, const double *long_src,
                             const int dims[4], int gauge_fmt, void *stream);
+
+/* As hisq_gauge_pack, with the long links stored as two rows when
+ * long_recon == HISQ_RECON_12 (long_dst: hisq_gauge_long_bytes bytes).  This
+ * requires L_mu(x) = lambda * sigma * phase_mu(x) * U_mu(x) with U in SU(3),
+ * lambda > 0 and sigma = +-1 global, phase_mu(x) the staggered phase
+ * eta_mu(x) (eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 =
+ * (-1)^(x+y+z)) times -1 for mu = t when t >= T-3 (antiperiodic time); HISQ
+ * Naik links (-1/24 times a product of three SU(3) links) with the phases and
+ * boundary folded in have this form.  The pack step verifies it (relative
+ * tolerance: 1e-13 for F64, 1e-7 for F32, 1e-5 for FIX16, 1e-9 for FIX32 storage)
+ * and returns HISQ_EINVAL otherwise.  The Dslash rebuilds row 3 = conj(row 1 x
+ * row 2) in its compute precision, cutting the long-link traffic by a third. */
+hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void *long_dst,
+                                  const double *fat_src, const double *long_src,
+                                  const int dims[4], int gauge_fmt, int long_recon, void *stream);
 
 /* Pack `nsites` canonical FP64 colour vectors (device complex128 [nsites][3])
  * into `spinor_fmt` at dst (device, hisq_spinor_bytes bytes).

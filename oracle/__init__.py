@@ -402,10 +402,79 @@ def spinor_quantum(v, fmt):
     raise ValueError(fmt)
 
 
-def emulated_dslash(fat, lng, psi, dims, parity, gauge_fmt, spinor_fmt, compute_bits, lib=None):
+# ---------------------------------------------------------------------------
+# two-row storage of the long links (Sec. 1, compression of special unitary
+# matrices): the third row of U in SU(3) is conj(row 1 x row 2), because the
+# rows are orthonormal and det U = 1.
+# ---------------------------------------------------------------------------
+
+def long_phases(dims):
+    """float64 [4, V]: eta_mu(x) (eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y),
+    eta_3 = (-1)^(x+y+z)) times -1 on the three-hop temporal link for
+    t >= T-3 (antiperiodic time), the sign the long links carry"""
+    X, Y, Z, T = dims
+    i = np.arange(volume(dims))
+    x, y, z, t = i % X, (i // X) % Y, (i // (X * Y)) % Z, i // (X * Y * Z)
+    e = np.stack([np.zeros_like(x), x, x + y, x + y + z])
+    e[3] += (t >= T - 3)
+    return np.where(e % 2 == 1, -1.0, 1.0)
+
+
+def su3_third_row(rows):
+    """rows [..., 2, 3] (first two rows of a special unitary matrix) -> the
+    third row conj(r1 x r2), [..., 3]"""
+    a, b = rows[..., 0, :], rows[..., 1, :]
+    c = np.empty(a.shape, dtype=np.complex128)
+    for k in range(3):
+        i, j = (k + 1) % 3, (k + 2) % 3
+        c[..., k] = np.conj(a[..., i] * b[..., j] - a[..., j] * b[..., i])
+    return c
+
+
+def long_link_split(lng, dims):
+    """L_mu(x) = c * phase_mu(x) * U_mu(x), U in SU(3), c real: returns
+    (c, U).  det L = c^3 phase (phase^3 = phase), so c is the real cube root
+    of phase * Re det L at every site; the sites must agree (c is global).
+    Raises ValueError when they do not or U is not special unitary."""
+    lng = np.asarray(lng, dtype=np.complex128)
+    ph = long_phases(dims)
+    det = np.linalg.det(lng.reshape(-1, 3, 3)).reshape(ph.shape)
+    cs = np.cbrt((ph * det).real)
+    c = float(np.mean(cs))
+    if c == 0.0 or np.abs(cs - c).max() > 1e-12 * abs(c) or np.abs(det.imag).max() > 1e-12 * abs(c) ** 3:
+        raise ValueError("long links are not c * phase * SU(3) with one real c")
+    u = lng / (c * ph)[..., None, None]
+    uh = np.conj(np.swapaxes(u, -1, -2))
+    if np.abs(uh @ u - np.eye(3)).max() > 1e-12:
+        raise ValueError("long links are not c * phase * SU(3): U is not unitary")
+    return c, u
+
+
+def long_recon_roundtrip(lng, dims, fmt, compute_bits, lib=None):
+    """long links as a Dslash sees them when only two rows of U are stored in
+    `fmt` (fixed-point scale: max |real component| of the whole of U) and the
+    third is rebuilt; the rebuild is exact here (FP64), the kernel's own
+    rounding of it is covered by the compute-precision tolerance"""
+    c, u = long_link_split(lng, dims)
+    rows = np.ascontiguousarray(u[..., :2, :])
+    if fmt in ("fix16", "fix32"):
+        scale = max(np.abs(u.real).max(), np.abs(u.imag).max())
+        q, _ = fix_encode(rows, 16 if fmt == "fix16" else 32, absmax=scale, lib=lib)
+        rows = fix_decode(q, scale, compute_bits, shape=rows.shape, lib=lib)
+    elif fmt == "f32" or compute_bits == 32:
+        rows = rows.astype(np.complex64).astype(np.complex128)
+    full = np.concatenate([rows, su3_third_row(rows)[..., None, :]], axis=-2)
+    return c * long_phases(dims)[..., None, None] * full
+
+
+def emulated_dslash(fat, lng, psi, dims, parity, gauge_fmt, spinor_fmt, compute_bits, lib=None, long_recon=18):
     """FP64 Dslash of the inputs as the storage formats hold them (links and
-    spinor after a round trip), before the output is stored."""
+    spinor after a round trip), before the output is stored.  long_recon=12:
+    the long links kept as two rows (long_recon_roundtrip)."""
     f = gauge_roundtrip(fat, gauge_fmt, compute_bits, lib)
-    l = gauge_roundtrip(lng, gauge_fmt, compute_bits, lib)
+    if long_recon == 12:
+        l = long_recon_roundtrip(lng, dims, gauge_fmt, compute_bits, lib)
+    else:
+        l = gauge_roundtrip(lng, gauge_fmt, compute_bits, lib)
     p = spinor_roundtrip(psi, spinor_fmt, lib)
     return dslash(f, l, p, dims, parity, lib=lib)

@@ -256,9 +256,7 @@ struct BRun {
         a.red = RED_NONE;
         a.nrhs = nrhs;
         a.field_stride = spinor_field_bytes(vh, f.spinor);
-        const double q = gg->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
-        a.gfat = gg->fat_max / q;
-        a.glong = gg->long_max / q;
+        gauge_args(a, gg);
         return a;
     }
 

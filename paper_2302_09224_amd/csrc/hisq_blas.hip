@@ -171,6 +171,142 @@ template <int GF> __global__ void k_gauge_pack(char *dst, const double *src, Geo
     }
 }
 
+// staggered phase of a three-hop link starting at (x,y,z,t) along mu: eta_mu(x)
+// times -1 when the hop crosses the time boundary (the convention of the inputs)
+__device__ __forceinline__ double link_phase3(int mu, int x, int y, int z, int t, int T) {
+    const int e = mu == 0 ? 0 : mu == 1 ? x : mu == 2 ? x + y : x + y + z;
+    const int b = (mu == 3 && t >= T - 3) ? 1 : 0;
+    return ((e + b) & 1) ? -1.0 : 1.0;
+}
+
+// Long links for two-row storage: every L_mu(x) must be lambda * sigma * phase * U
+// with U in SU(3), lambda > 0 and sigma = +-1 global.  Per block:
+// [min lambda_x, max lambda_x, #sigma_x>0, #sigma_x<0, max unitarity defect,
+//  max |Im det| / |det|, max |component| / lambda_x], lambda_x = |det L|^(1/3).
+__global__ void k_long_check(const double *src, Geom g, double *partial) {
+    __shared__ double lds[7][8];
+    const size_t V = 2 * (size_t)g.vh;
+    double mn = 1e300, mx = 0.0, np = 0.0, nn = 0.0, defect = 0.0, imr = 0.0, cmax = 0.0;
+    for (size_t idx = gtid(); idx < 4 * V; idx += gstride()) {
+        const int mu = (int)(idx / V);
+        size_t r = idx - (size_t)mu * V;
+        const int x = (int)(r % g.X); r /= g.X;
+        const int y = (int)(r % g.Y); r /= g.Y;
+        const int z = (int)(r % g.Z);
+        const int t = (int)(r / g.Z);
+        const double *u = src + idx * 18;
+        double ar[9], ai[9];
+        for (int k = 0; k < 9; k++) {
+            ar[k] = u[2 * k];
+            ai[k] = u[2 * k + 1];
+        }
+        // det by cofactors along row 0
+        double dr = 0.0, di = 0.0;
+        for (int k = 0; k < 3; k++) {
+            const int i = (k + 1) % 3, j = (k + 2) % 3;
+            const double cr = ar[3 + i] * ar[6 + j] - ai[3 + i] * ai[6 + j] - (ar[3 + j] * ar[6 + i] - ai[3 + j] * ai[6 + i]);
+            const double ci = ar[3 + i] * ai[6 + j] + ai[3 + i] * ar[6 + j] - (ar[3 + j] * ai[6 + i] + ai[3 + j] * ar[6 + i]);
+            dr += ar[k] * cr - ai[k] * ci;
+            di += ar[k] * ci + ai[k] * cr;
+        }
+        const double ad = sqrt(dr * dr + di * di);
+        const double lam = cbrt(ad);
+        mn = fmin(mn, lam);
+        mx = fmax(mx, lam);
+        imr = fmax(imr, ad > 0 ? fabs(di) / ad : 1.0);
+        const double sg = (dr >= 0 ? 1.0 : -1.0) * link_phase3(mu, x, y, z, t, g.T);
+        if (sg > 0) np += 1.0; else nn += 1.0;
+        const double inv = lam > 0 ? 1.0 / lam : 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double sr = 0.0, si = 0.0;  // (U^dag U)_ab
+                for (int k = 0; k < 3; k++) {
+                    sr += ar[3 * k + a] * ar[3 * k + b] + ai[3 * k + a] * ai[3 * k + b];
+                    si += ar[3 * k + a] * ai[3 * k + b] - ai[3 * k + a] * ar[3 * k + b];
+                }
+                sr = sr * inv * inv - (a == b ? 1.0 : 0.0);
+                si = si * inv * inv;
+                defect = fmax(defect, fmax(fabs(sr), fabs(si)));
+            }
+        for (int k = 0; k < 9; k++) cmax = fmax(cmax, fmax(fabs(ar[k]), fabs(ai[k])) * inv);
+    }
+    double v[7] = {mn, mx, np, nn, defect, imr, cmax};
+    for (int k = 0; k < 7; k++) {
+        double w = v[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            const double q = __shfl_xor(w, o, 64);
+            w = (k == 0) ? fmin(w, q) : (k == 2 || k == 3) ? w + q : fmax(w, q);
+        }
+        if ((threadIdx.x & 63) == 0) lds[k][threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 7; k++) {
+            double w = lds[k][0];
+            for (int j = 1; j < (int)(blockDim.x >> 6); j++)
+                w = (k == 0) ? fmin(w, lds[k][j]) : (k == 2 || k == 3) ? w + lds[k][j] : fmax(w, lds[k][j]);
+            partial[7 * blockIdx.x + k] = w;
+        }
+    }
+}
+
+// two rows of U = L / (lambda * sigma * phase) into the 12-real sub-fields;
+// fixed-point formats scale by umax (the global max |component| of U)
+template <int GF> __global__ void k_gauge_pack12(char *dst, const double *src, Geom g, double coef, double umax) {
+    const size_t V = 2 * (size_t)g.vh;
+    const size_t vh = g.vh;
+    const size_t sub = (size_t)gauge_matrix_bytes12(GF) * vh;
+    const double qs = GF == GF_FIX16 ? 32767.0 / umax : GF == GF_FIX32 ? 2147483647.0 / umax : 1.0;
+    for (size_t idx = gtid(); idx < 4 * V; idx += gstride()) {
+        const int mu = (int)(idx / V);
+        const size_t site = idx - (size_t)mu * V;
+        size_t r = site;
+        const int x = (int)(r % g.X); r /= g.X;
+        const int y = (int)(r % g.Y); r /= g.Y;
+        const int z = (int)(r % g.Z);
+        const int t = (int)(r / g.Z);
+        const int par = (x + y + z + t) & 1;
+        const size_t s = site >> 1;
+        char *base = dst + (size_t)(2 * mu + par) * sub;
+        const double *u = src + idx * 18;
+        const double inv = 1.0 / (coef * link_phase3(mu, x, y, z, t, g.T));
+        double w[12];
+        for (int k = 0; k < 12; k++) w[k] = u[k] * inv;
+        if (GF == GF_F64) {
+            for (int k = 0; k < 6; k++) {
+                f64x2 v;
+                v.x = w[2 * k];
+                v.y = w[2 * k + 1];
+                st<f64x2>(base + k * 16 * vh + 16 * s, v);
+            }
+        } else if (GF == GF_F32) {
+            for (int k = 0; k < 3; k++) {
+                f32x4 v;
+                v.x = (float)w[4 * k]; v.y = (float)w[4 * k + 1]; v.z = (float)w[4 * k + 2]; v.w = (float)w[4 * k + 3];
+                st<f32x4>(base + k * 16 * vh + 16 * s, v);
+            }
+        } else if (GF == GF_FIX16) {
+            unsigned q[12];
+            for (int k = 0; k < 12; k++) q[k] = (unsigned)(int)__builtin_rint(w[k] * qs) & 0xffffu;
+            u32x4 a;
+            a.x = q[0] | (q[1] << 16); a.y = q[2] | (q[3] << 16); a.z = q[4] | (q[5] << 16); a.w = q[6] | (q[7] << 16);
+            u32x2 b;
+            b.x = q[8] | (q[9] << 16);
+            b.y = q[10] | (q[11] << 16);
+            st<u32x4>(base + 16 * s, a);
+            st<u32x2>(base + 16 * vh + 8 * s, b);
+        } else {
+            unsigned q[12];
+            for (int k = 0; k < 12; k++) q[k] = (unsigned)(int)__builtin_rint(w[k] * qs);
+            for (int k = 0; k < 3; k++) {
+                u32x4 a;
+                a.x = q[4 * k]; a.y = q[4 * k + 1]; a.z = q[4 * k + 2]; a.w = q[4 * k + 3];
+                st<u32x4>(base + k * 16 * vh + 16 * s, a);
+            }
+        }
+    }
+}
+
 __global__ void k_norm2_f64(const char *v, size_t n, double *partial) {
     __shared__ double lds[16];
     double acc = 0.0;
@@ -299,30 +435,68 @@ __global__ void k_ru_convert(char *rs, const char *r64, const char *p, const cha
     }
 }
 
-// one launch for every shifted system still being updated (Sec. 3.2)
+// x += sum_{q <= last} ai_buf[q][i] * slot q of shift i's gradient ring
+template <int SF, class R>
+__device__ __forceinline__ void flush_shift(char *x64, const char *ring, size_t slot_bytes, const SolverCtrl *ctrl,
+                                            int i, int last, const CVec<R> *cur, size_t n, size_t s) {
+    CVec<double> xv = SpinorIO<SF_F64, double>::load(x64, n, s);
+    for (int q = 0; q <= last; q++) {
+        const double a = ctrl->ai_buf[q][i];
+        const CVec<R> pq = (cur && q == last) ? *cur : SpinorIO<SF, R>::load(ring + q * slot_bytes, n, s);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            xv.re[c] = fma(a, (double)pq.re[c], xv.re[c]);
+            xv.im[c] = fma(a, (double)pq.im[c], xv.im[c]);
+        }
+    }
+    SpinorIO<SF_F64, double>::store(x64, n, s, xv);
+}
+
+// One launch for every shifted system still being updated (Sec. 3.2).  The
+// shifted solutions are FP64 and, like the base solution, are updated from a
+// ring of buffered gradient vectors once every N_b iterations (Sec. 3.1 item 1)
+// and when the shift stops.
 template <int SF, class R>
 __global__ void k_shift_update(SpinorList x64, SpinorList p, const char *r, const SolverCtrl *ctrl, int nshift, size_t n,
-                               Guard gd) {
+                               size_t slot_bytes, int jb, int jn, int flush_all, Guard gd) {
     if (!gd.pass()) return;
-    const int mask = ctrl->e_mask;
+    const int mask = ctrl->e_mask, rm = ctrl->rm_mask;
     for (size_t s = gtid(); s < n; s += gstride()) {
         CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
         for (int i = 1; i < nshift; i++) {
             if (!((mask >> i) & 1)) continue;
-            const double ai = ctrl->alpha_i[i];
-            const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
-            CVec<R> pv = SpinorIO<SF, R>::load(p.p[i], n, s);
-            CVec<double> xv = SpinorIO<SF_F64, double>::load(x64.p[i], n, s);
-            CVec<R> pn;
+            const char *ring = p.p[i];
+            const CVec<R> pv = SpinorIO<SF, R>::load(ring + jb * slot_bytes, n, s);
+            const int stopped = (rm >> i) & 1;
+            if (flush_all || stopped) flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, &pv, n, s);
+            if (!stopped) {
+                const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
+                CVec<R> pn;
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                xv.re[c] = fma(ai, (double)pv.re[c], xv.re[c]);
-                xv.im[c] = fma(ai, (double)pv.im[c], xv.im[c]);
-                pn.re[c] = fma(zi, rv.re[c], bi * pv.re[c]);
-                pn.im[c] = fma(zi, rv.im[c], bi * pv.im[c]);
+                for (int c = 0; c < 3; c++) {
+                    pn.re[c] = fma(zi, rv.re[c], bi * pv.re[c]);
+                    pn.im[c] = fma(zi, rv.im[c], bi * pv.im[c]);
+                }
+                SpinorIO<SF, R>::store(p.p[i] + jn * slot_bytes, n, s, pn);
             }
-            SpinorIO<SF_F64, double>::store(x64.p[i], n, s, xv);
-            SpinorIO<SF, R>::store(p.p[i], n, s, pn);
+        }
+    }
+}
+
+// after a block of iterations ended at slot jb < N_b-1: flush the buffered
+// slots of the shifts still being updated and move their newest gradient
+// vector (slot jb+1) to slot 0, where the next block starts
+template <int SF, class R>
+__global__ void k_shift_realign(SpinorList x64, SpinorList p, const SolverCtrl *ctrl, int nshift, size_t n,
+                                size_t slot_bytes, int jb) {
+    const int mask = ctrl->active_mask;
+    for (size_t s = gtid(); s < n; s += gstride()) {
+        for (int i = 1; i < nshift; i++) {
+            if (!((mask >> i) & 1)) continue;
+            char *ring = p.p[i];
+            flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, nullptr, n, s);
+            const CVec<R> pn = SpinorIO<SF, R>::load(ring + (jb + 1) * slot_bytes, n, s);
+            SpinorIO<SF, R>::store(ring, n, s, pn);
         }
     }
 }
@@ -546,6 +720,26 @@ hipError_t launch_gauge_pack(char *dst, const double *src, const Geom &g, int gf
     return hipGetLastError();
 }
 
+hipError_t launch_long_check(const double *src, const Geom &g, double *partial, int *nblocks, hipStream_t st) {
+    const int nb = blas_blocks(8 * (size_t)g.vh);
+    *nblocks = nb;
+    hipLaunchKernelGGL(k_long_check, dim3(nb), dim3(BLAS_BLOCK), 0, st, src, g, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_pack12(char *dst, const double *src, const Geom &g, int gf, double coef, double umax,
+                               hipStream_t st) {
+    const int nb = blas_blocks(8 * (size_t)g.vh);
+    switch (gf) {
+    case GF_F64: hipLaunchKernelGGL((k_gauge_pack12<GF_F64>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
+    case GF_F32: hipLaunchKernelGGL((k_gauge_pack12<GF_F32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
+    case GF_FIX16: hipLaunchKernelGGL((k_gauge_pack12<GF_FIX16>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
+    case GF_FIX32: hipLaunchKernelGGL((k_gauge_pack12<GF_FIX32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nblocks, hipStream_t st) {
     const int nb = blas_blocks(n);
     *nblocks = nb;
@@ -579,8 +773,15 @@ hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const ch
 }
 
 hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
-                               int nshift, size_t n, int sf, int compute, Guard gd, hipStream_t st) {
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, gd));
+                               int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
+                               int compute, Guard gd, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, slot_bytes, jb, jn, flush_all, gd));
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_realign(const SpinorList &x64, const SpinorList &p, const SolverCtrl *ctrl, int nshift,
+                                size_t n, size_t slot_bytes, int jb, int sf, int compute, hipStream_t st) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_realign<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, ctrl, nshift, n, slot_bytes, jb));
     return hipGetLastError();
 }
 

@@ -5,8 +5,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "hisq_internal.h"
 
@@ -73,6 +75,16 @@ bool triplet_ok(const hisq_fmt &f) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+void gauge_args(DslashArgs &a, const hisq_gauge *g) {
+    a.fat = (const char *)g->fat;
+    a.lng = (const char *)g->lng;
+    const double q = g->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
+    a.gfat = g->fat_max / q;
+    a.glong = g->long_max / q;
+    a.long_recon = g->long_recon == HISQ_RECON_12 ? 12 : 18;
+    a.lcoef = g->long_coeff;
+}
+
 namespace {
 std::mutex g_scratch_mu;
 LibScratch g_scratch[64];
@@ -113,16 +125,12 @@ DslashArgs base_args(const hisq_gauge *g, void *out, const void *in, int parity)
     memset(&a, 0, sizeof(a));
     a.out = (char *)out;
     a.in = (const char *)in;
-    a.fat = (const char *)g->fat;
-    a.lng = (const char *)g->lng;
     a.b = 1.0;
     a.g = make_geom(g->dims);
     a.parity = parity;
     a.red = RED_NONE;
     a.nrhs = 1;
-    const double q = g->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
-    a.gfat = g->fat_max / q;
-    a.glong = g->long_max / q;
+    gauge_args(a, g);
     return a;
 }
 
@@ -152,10 +160,26 @@ extern "C" size_t hisq_spinor_bytes(long nsites, int spinor_fmt) {
     return spinor_field_bytes((size_t)nsites, spinor_fmt);
 }
 
+extern "C" size_t hisq_gauge_long_bytes(const int dims[4], int gauge_fmt, int long_recon) {
+    if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > 3) return 0;
+    if (long_recon == HISQ_RECON_18) return gauge_field_bytes(dims, gauge_fmt);
+    if (long_recon != HISQ_RECON_12) return 0;
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+    return 4 * V * (size_t)gauge_matrix_bytes12(gauge_fmt);
+}
+
 extern "C" hisq_status hisq_gauge_pack(hisq_gauge *g, void *fat_dst, void *long_dst, const double *fat_src,
                                        const double *long_src, const int dims[4], int gauge_fmt, void *stream) {
+    return hisq_gauge_pack_recon(g, fat_dst, long_dst, fat_src, long_src, dims, gauge_fmt, HISQ_RECON_18, stream);
+}
+
+extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void *long_dst, const double *fat_src,
+                                             const double *long_src, const int dims[4], int gauge_fmt, int long_recon,
+                                             void *stream) {
     if (!g || !fat_dst || !long_dst || !fat_src || !long_src || !dims)
         return set_error(HISQ_EINVAL, "hisq_gauge_pack: null argument");
+    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
+        return set_error(HISQ_EINVAL, "hisq_gauge_pack: long_recon must be 18 or 12");
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "hisq_gauge_pack: dims must be even and >= 4");
     if (gauge_fmt < 0 || gauge_fmt > 3) return set_error(HISQ_EINVAL, "hisq_gauge_pack: bad gauge format %d", gauge_fmt);
     if (!aligned16(fat_dst) || !aligned16(long_dst) || !aligned16(fat_src) || !aligned16(long_src))
@@ -180,14 +204,48 @@ extern "C" hisq_status hisq_gauge_pack(hisq_gauge *g, void *fat_dst, void *long_
     if (!std::isfinite(fmax_) || !std::isfinite(lmax_))
         return set_error(HISQ_ERANGE, "hisq_gauge_pack: non-finite link element");
     HISQ_TRY_HIP(launch_gauge_pack((char *)fat_dst, fat_src, geo, gauge_fmt, mx, st));
-    HISQ_TRY_HIP(launch_gauge_pack((char *)long_dst, long_src, geo, gauge_fmt, mx + 1, st));
+    double long_scale = lmax_, coeff = 1.0;
+    if (long_recon == HISQ_RECON_18) {
+        HISQ_TRY_HIP(launch_gauge_pack((char *)long_dst, long_src, geo, gauge_fmt, mx + 1, st));
+    } else {
+        // verify L = lambda * sigma * phase * SU(3) and find lambda, sigma and max |U|
+        int nbc = 0;
+        HISQ_TRY_HIP(launch_long_check(long_src, geo, part, &nbc, st));
+        std::vector<double> ck((size_t)7 * nbc);
+        HISQ_TRY_HIP(hipMemcpyAsync(ck.data(), part, ck.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HISQ_TRY_HIP(hipStreamSynchronize(st));
+        double mn = 1e300, mxl = 0.0, np = 0.0, nn = 0.0, defect = 0.0, imr = 0.0, umax = 0.0;
+        for (int b = 0; b < nbc; b++) {
+            const double *c = &ck[(size_t)7 * b];
+            mn = std::min(mn, c[0]);
+            mxl = std::max(mxl, c[1]);
+            np += c[2];
+            nn += c[3];
+            defect = std::max(defect, c[4]);
+            imr = std::max(imr, c[5]);
+            umax = std::max(umax, c[6]);
+        }
+        const double tol = gauge_fmt == HISQ_GAUGE_F64 ? 1e-13 : gauge_fmt == HISQ_GAUGE_F32 ? 1e-7
+                           : gauge_fmt == HISQ_GAUGE_FIX16 ? 1e-5 : 1e-9;
+        const double lam = 0.5 * (mn + mxl);
+        if (!(lam > 0.0) || (mxl - mn) > tol * lam || defect > tol || imr > tol || (np > 0 && nn > 0))
+            return set_error(HISQ_EINVAL,
+                             "hisq_gauge_pack_recon: long links are not lambda*phase*SU(3) within %g "
+                             "(lambda in [%g,%g], unitarity defect %g, |Im det|/|det| %g, sign counts %g/%g)",
+                             tol, mn, mxl, defect, imr, np, nn);
+        coeff = np > 0 ? lam : -lam;
+        long_scale = umax;
+        HISQ_TRY_HIP(launch_gauge_pack12((char *)long_dst, long_src, geo, gauge_fmt, coeff, umax, st));
+    }
     HISQ_TRY_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < 4; k++) g->dims[k] = dims[k];
     g->fmt = gauge_fmt;
     g->fat = fat_dst;
     g->lng = long_dst;
     g->fat_max = fmax_;
-    g->long_max = lmax_;
+    g->long_max = long_scale;
+    g->long_recon = long_recon;
+    g->long_coeff = coeff;
     return HISQ_OK;
 }
 

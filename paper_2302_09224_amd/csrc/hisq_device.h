@@ -45,6 +45,10 @@ __host__ __device__ constexpr int spinor_site_bytes(int sf) {
 __host__ __device__ constexpr int gauge_matrix_bytes(int gf) {
     return gf == GF_F64 ? 144 : gf == GF_FIX16 ? 36 : 72;
 }
+// two rows (12 reals) of a long link stored for reconstruction
+__host__ __device__ constexpr int gauge_matrix_bytes12(int gf) {
+    return gf == GF_F64 ? 96 : gf == GF_FIX16 ? 24 : 48;
+}
 
 // ---------------------------------------------------------------------------
 // register types

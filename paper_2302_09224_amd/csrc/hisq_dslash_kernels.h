@@ -121,6 +121,100 @@ template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<G
     return U;
 }
 
+// Long links stored as two rows (12 reals) of U, where L = c * s * U with U in
+// SU(3), c a global real constant and s = +-1 the staggered phase of the link
+// (Sec. 1 "Compression": a special unitary matrix is fixed by two of its rows).
+// Row 3 is rebuilt as conj(row1 x row2) in the compute precision.
+template <int GF> struct LinkRaw12;
+template <> struct LinkRaw12<GF_F64> { f64x2 w[6]; };
+template <> struct LinkRaw12<GF_F32> { f32x4 w[3]; };
+template <> struct LinkRaw12<GF_FIX16> { u32x4 w; u32x2 t; };
+template <> struct LinkRaw12<GF_FIX32> { u32x4 w[3]; };
+
+template <int GF> __device__ __forceinline__ LinkRaw12<GF> link_load12(const char *sub, size_t vh, size_t s);
+template <> __device__ __forceinline__ LinkRaw12<GF_F64> link_load12<GF_F64>(const char *sub, size_t vh, size_t s) {
+    LinkRaw12<GF_F64> L;
+#pragma unroll
+    for (int k = 0; k < 6; k++) L.w[k] = ld_nt<f64x2>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw12<GF_F32> link_load12<GF_F32>(const char *sub, size_t vh, size_t s) {
+    LinkRaw12<GF_F32> L;
+#pragma unroll
+    for (int k = 0; k < 3; k++) L.w[k] = ld_nt<f32x4>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw12<GF_FIX16> link_load12<GF_FIX16>(const char *sub, size_t vh, size_t s) {
+    LinkRaw12<GF_FIX16> L;
+    L.w = ld_nt<u32x4>(sub + 16 * s);
+    L.t = ld_nt<u32x2>(sub + 16 * vh + 8 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw12<GF_FIX32> link_load12<GF_FIX32>(const char *sub, size_t vh, size_t s) {
+    LinkRaw12<GF_FIX32> L;
+#pragma unroll
+    for (int k = 0; k < 3; k++) L.w[k] = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+
+// rows 1-2 -> full matrix; third row conj(r0 x r1); everything times c
+template <class R> __device__ __forceinline__ Mat<R> complete_su3(Mat<R> U, R c) {
+    const R ar[3] = {U.re[0], U.re[1], U.re[2]}, ai[3] = {U.im[0], U.im[1], U.im[2]};
+    const R br[3] = {U.re[3], U.re[4], U.re[5]}, bi[3] = {U.im[3], U.im[4], U.im[5]};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int i = (k + 1) % 3, j = (k + 2) % 3;
+        // (a_i b_j - a_j b_i), conjugated
+        const R re = ar[i] * br[j] - ai[i] * bi[j] - (ar[j] * br[i] - ai[j] * bi[i]);
+        const R im = ar[i] * bi[j] + ai[i] * br[j] - (ar[j] * bi[i] + ai[j] * br[i]);
+        U.re[6 + k] = re;
+        U.im[6 + k] = -im;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        U.re[k] *= c;
+        U.im[k] *= c;
+    }
+    return U;
+}
+
+template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_F64> &L, R, R c) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        U.re[k] = (R)L.w[k].x;
+        U.im[k] = (R)L.w[k].y;
+    }
+    return complete_su3(U, c);
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_F32> &L, R, R c) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        U.re[2 * k] = L.w[k].x; U.im[2 * k] = L.w[k].y; U.re[2 * k + 1] = L.w[k].z; U.im[2 * k + 1] = L.w[k].w;
+    }
+    return complete_su3(U, c);
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_FIX16> &L, R g, R c) {
+    Mat<R> U;
+    const unsigned ws[6] = {L.w.x, L.w.y, L.w.z, L.w.w, L.t.x, L.t.y};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        U.re[k] = (R)sext16(ws[k]) * g;
+        U.im[k] = (R)sext16(ws[k] >> 16) * g;
+    }
+    return complete_su3(U, c);
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_FIX32> &L, R g, R c) {
+    Mat<R> U;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        U.re[2 * k] = (R)(int)L.w[k].x * g; U.im[2 * k] = (R)(int)L.w[k].y * g;
+        U.re[2 * k + 1] = (R)(int)L.w[k].z * g; U.im[2 * k + 1] = (R)(int)L.w[k].w * g;
+    }
+    return complete_su3(U, c);
+}
+
 template <int SF> struct SpinRaw;
 template <> struct SpinRaw<SF_F64> { f64x2 w[3]; };
 template <> struct SpinRaw<SF_F32> { f32x4 a; f32x2 b; };
@@ -189,7 +283,16 @@ template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<
 // checkerboard indices of the +-1, +-3 neighbours of site s along each direction
 struct Nbrs {
     int f1[4], b1[4], f3[4], b3[4];
+    float lsf[4], lsb[4];  // phase s = +-1 of the forward link L(x) and the backward link L(x-3mu)
 };
+
+// staggered phase eta_mu(x) times the antiperiodic time sign of a three-hop
+// link starting at time t (negative when the hop crosses t = T)
+__device__ __forceinline__ float long_phase(int mu, int x, int y, int z, int t, int T) {
+    const int e = mu == 0 ? 0 : mu == 1 ? x : mu == 2 ? x + y : x + y + z;
+    const int b = (mu == 3 && t >= T - 3) ? 1 : 0;
+    return ((e + b) & 1) ? -1.0f : 1.0f;
+}
 
 __device__ __forceinline__ int wrap_add(int c, int h, int L) {
     int v = c + h;
@@ -224,6 +327,11 @@ __device__ __forceinline__ Nbrs neighbours(const Geom &g, int s, int parity) {
     n.b1[3] = s + (wrap_add(t, -1, g.T) - t) * g.st;
     n.f3[3] = s + (wrap_add(t, 3, g.T) - t) * g.st;
     n.b3[3] = s + (wrap_add(t, -3, g.T) - t) * g.st;
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        n.lsf[mu] = long_phase(mu, x, y, z, t, g.T);
+        n.lsb[mu] = long_phase(mu, x, y, z, wrap_add(t, mu == 3 ? -3 : 0, g.T), g.T);
+    }
     return n;
 }
 
@@ -269,7 +377,8 @@ __device__ __forceinline__ int hop_site_rt(const Geom &g, const Coords &c, int s
 
 // GUARD: launched inside a solver's block of iterations (may return at once);
 // standalone applications use the unguarded instantiation.
-template <int GF, int SF, class R, int NR, int STAGE, bool RED, bool GUARD>
+// LR: 18 = long links stored in full, 12 = two rows + reconstruction
+template <int GF, int SF, class R, int NR, int STAGE, bool RED, bool GUARD, int LR>
 __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, FastDiv drg) {
     __shared__ double lds[64];
     if (GUARD && !A.guard.pass()) return;
@@ -294,7 +403,8 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         const size_t vh = (size_t)g.vh;
         const int p = A.parity, q = 1 - p;
         const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
-        const R gf = (R)A.gfat, gl = (R)A.glong;
+        const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
+        const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
         const char *in = A.in + (size_t)r0 * fs;
         CVec<R> acc[NR];
 #pragma unroll
@@ -306,12 +416,23 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
             for (int h = 0; h < 16; h++) {
                 const int ss = hop_site_rt(g, c, s, h);
                 const int ls = (h & 1) ? ss : s;
-                const char *field = (h & 2) ? A.lng : A.fat;
-                const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + ((h & 1) ? q : p)) * sub, vh, ls);
+                const int lpar = (h & 1) ? q : p;
+                Mat<R> U;
                 SpinRaw<SF> Pr[NR];
+                if (LR == 12 && (h & 2)) {
+                    const int mu = h >> 2;
+                    const int tl = (mu == 3 && (h & 1)) ? wrap_add(c.t, -3, g.T) : c.t;
+                    const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
 #pragma unroll
-                for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
-                const Mat<R> U = link_decode<R>(Lr, (h & 2) ? gl : gf);
+                    for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
+                    U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
+                } else {
+                    const char *field = (h & 2) ? A.lng : A.fat;
+                    const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+#pragma unroll
+                    for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
+                    U = link_decode<R>(Lr, (h & 2) ? gl : gf);
+                }
                 if (h & 1) {
 #pragma unroll
                     for (int j = 0; j < NR; j++) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
@@ -325,14 +446,18 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 #pragma unroll
         for (int h0 = 0; h0 < (NR > 1 ? 0 : 16); h0 += STAGE) {
             LinkRaw<GF> L[STAGE];
+            LinkRaw12<GF> L12[STAGE];
             SpinRaw<SF> P[STAGE][NR];
 #pragma unroll
             for (int i = 0; i < STAGE; i++) {
                 const int h = h0 + i;
                 const int ss = hop_spinor_site(n, h);
                 const int ls = (h & 1) ? ss : s;
-                const char *field = (h & 2) ? A.lng : A.fat;
-                L[i] = link_load<GF>(field + (size_t)(2 * (h >> 2) + ((h & 1) ? q : p)) * sub, vh, ls);
+                const int lpar = (h & 1) ? q : p;
+                if (LR == 12 && (h & 2))
+                    L12[i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
+                else
+                    L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
                 for (int j = 0; j < NR; j++) P[i][j] = spin_load<SF>(in + j * fs, vh, ss);
             }
@@ -340,7 +465,9 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 #pragma unroll
             for (int i = 0; i < STAGE; i++) {
                 const int h = h0 + i;
-                const Mat<R> U = link_decode<R>(L[i], (h & 2) ? gl : gf);
+                const Mat<R> U = (LR == 12 && (h & 2))
+                                     ? link_decode12<R>(L12[i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
+                                     : link_decode<R>(L[i], (h & 2) ? gl : gf);
 #pragma unroll
                 for (int j = 0; j < NR; j++) {
                     const CVec<R> v = spin_decode<R>(P[i][j]);
@@ -427,12 +554,21 @@ hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid
     if (grid > 0 && grid < nb) nb = grid;
     if (nblocks) *nblocks = nb;
     const FastDiv drg = make_fastdiv((unsigned)rg);
-    if (a.red != RED_NONE)
-        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
-    else if (a.guard.stop)
-        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
-    else
-        hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+    if (a.long_recon == 12) {
+        if (a.red != RED_NONE)
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+        else if (a.guard.stop)
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+        else
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+    } else {
+        if (a.red != RED_NONE)
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+        else if (a.guard.stop)
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+        else
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+    }
     return hipGetLastError();
 }
 

@@ -65,6 +65,8 @@ struct DslashArgs {
     size_t field_stride;  // batched: bytes between consecutive right-hand-side fields
     int nrhs;             // right-hand sides of the whole application (partials per block)
     size_t pstride;       // partial of right-hand side j, block b at partial[j*pstride + b]
+    int long_recon;       // 18: long links stored in full; 12: two rows, L = lcoef * phase * SU(3)
+    double lcoef;
 };
 
 // Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
@@ -82,6 +84,9 @@ struct DslashPlan {
     int rhs0[5];
     DslashTile tile[5];
 };
+
+// link pointers, fixed-point steps and long-link storage of a packed gauge
+void gauge_args(DslashArgs &a, const hisq_gauge *g);
 
 // blocks of a Dslash launch over n lanes (multiple of 8 for the XCD order)
 int dslash_blocks(int n, int block);
@@ -109,6 +114,10 @@ hipError_t launch_reduce_max(const double *partial, int n, double *out, hipStrea
 hipError_t launch_gauge_pack(char *dst, const double *src, const Geom &g, int gf, const double *absmax,
                              hipStream_t st);
 hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nblocks, hipStream_t st);
+// two-row long links: per-block checks [min lambda, max lambda, #sigma+, #sigma-, defect, |Im det|/|det|, max|U|]
+hipError_t launch_long_check(const double *src, const Geom &g, double *partial, int *nblocks, hipStream_t st);
+hipError_t launch_gauge_pack12(char *dst, const double *src, const Geom &g, int gf, double coef, double umax,
+                               hipStream_t st);
 
 // solver control block, shared by the device scalar kernels and the host
 struct SolverCtrl {
@@ -138,6 +147,8 @@ struct SolverCtrl {
     double tol2_i[HISQ_MAX_SHIFTS];
     double zeta[HISQ_MAX_SHIFTS], zeta_prev[HISQ_MAX_SHIFTS];
     double alpha_i[HISQ_MAX_SHIFTS], beta_i[HISQ_MAX_SHIFTS];
+    double ai_buf[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];  // alpha_i of each buffered gradient slot
+    int rm_mask;     // multi-shift: shifts that stopped in this iteration (flush their buffers)
     int shift_stop_k[HISQ_MAX_SHIFTS];
     // batched CG: per right-hand side scalars
     double brho[16], brho_prev[16], brho_new[16], bgamma[16], bpi[16], balpha[16], bbeta[16];
@@ -167,9 +178,15 @@ hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const doubl
 // r_s = pack(r64); partial (|r_s|^2, Re<r_s,p>, Im<r_s,p>, Re<r_s, r_old + alpha ap>)
 hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const char *ap, const double *alpha,
                              size_t n, int sf, int compute, double *partial, Guard gd, hipStream_t st);
-// multi-shift: x_i += alpha_i p_i, p_i = zeta_i r + beta_i p_i for the shifts of ctrl->e_mask
+// multi-shift, one launch for every shift of ctrl->e_mask: p_i[jn] = zeta_i r + beta_i p_i[jb]
+// (ring of gradient slots `slot_bytes` apart starting at p.p[i]); x_i += sum_{q<=jb} ai_buf[q][i] p_i[q]
+// when flush_all or when shift i stopped in this iteration (buffered FP64 solution update)
 hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
-                               int nshift, size_t n, int sf, int compute, Guard gd, hipStream_t st);
+                               int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
+                               int compute, Guard gd, hipStream_t st);
+// multi-shift, shifts of ctrl->active_mask: flush slots 0..jb into x_i and move slot jb+1 to slot 0
+hipError_t launch_shift_realign(const SpinorList &x64, const SpinorList &p, const SolverCtrl *ctrl, int nshift,
+                                size_t n, size_t slot_bytes, int jb, int sf, int compute, hipStream_t st);
 
 // batched versions (nrhs consecutive fields of `stride` bytes)
 hipError_t launch_bcg_axpy(char *r, const char *ap, const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs,

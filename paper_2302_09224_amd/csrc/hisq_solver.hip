@@ -79,7 +79,7 @@ __global__ void k_fin_alpha(SolverCtrl *c, const double *partial, int n, int jb,
 }
 
 // beta and the decisions of one iteration; multi-shift: zeta recurrences
-__global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd, int multishift) {
+__global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd, int multishift, int jb) {
     __shared__ double lds[32];
     if (!gd.pass()) return;
     double v[2];
@@ -105,23 +105,26 @@ __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd
     int reason = STOP_NONE;
     if (multishift) {
         const double a = c->alpha, ap = c->alpha_prev, bp = c->beta_prev;
-        int amask = c->active_mask, emask = 0;
+        int amask = c->active_mask, emask = 0, rm = 0;
         for (int i = 1; i < c->nshift; i++) {
             if (!((amask >> i) & 1)) continue;
             const double z = c->zeta[i], zp = c->zeta_prev[i], s = c->sh[i];
             const double zn = z * zp * ap / (ap * zp * (1.0 + a * s) + a * bp * (zp - z));
             const double ratio = zn / z;
             c->alpha_i[i] = a * ratio;
+            c->ai_buf[jb][i] = a * ratio;
             c->beta_i[i] = beta * ratio * ratio;
             c->zeta_prev[i] = z;
             c->zeta[i] = zn;
             emask |= 1 << i;
             if (zn * zn * rn <= fmax(c->tol2_i[i], c->floor2) * c->b2) {
                 amask &= ~(1 << i);
+                rm |= 1 << i;
                 c->shift_stop_k[i] = k;
             }
         }
         c->e_mask = emask;
+        c->rm_mask = rm;
         c->active_mask = amask;
         c->alpha_prev = a;
         c->beta_prev = beta;
@@ -276,7 +279,7 @@ size_t carve_cg(CgBuffers *b, char *base, const Geom &g, int sloppy_bytes, int n
         B.pconv = cv.take(ref_bytes * vh);
         for (int i = 1; i < nshift; i++) {
             B.xs[i] = cv.take(48 * vh);
-            B.ps[i] = cv.take(ms_bytes * vh);
+            B.ps[i] = cv.take((size_t)nb * ms_bytes * vh);  // ring of nb gradient slots
         }
     }
     return cv.off;
@@ -341,9 +344,7 @@ struct Run {
         a.parity = parity;
         a.red = RED_NONE;
         a.nrhs = 1;
-        const double q = gg->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
-        a.gfat = gg->fat_max / q;
-        a.glong = gg->long_max / q;
+        gauge_args(a, gg);
         return a;
     }
 
@@ -367,7 +368,7 @@ struct Run {
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_cg_axpy(B->rs, B->aps, &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), gns,
-                           multishift ? 1 : 0);
+                           multishift ? 1 : 0, jb);
         HISQ_TRY_HIP(hipGetLastError());
         if (multishift) {
             SpinorList xl, pl;
@@ -375,7 +376,8 @@ struct Run {
                 xl.p[i] = B->xs[i];
                 pl.p[i] = B->ps[i];
             }
-            HISQ_TRY_HIP(launch_shift_update(xl, pl, B->rs, c, nshift, vh, fmt.spinor, fmt.compute, gns, st));
+            HISQ_TRY_HIP(launch_shift_update(xl, pl, B->rs, c, nshift, vh, slot_bytes(), jb, jn, jb == nb - 1,
+                                             fmt.spinor, fmt.compute, gns, st));
         }
         if (jb == nb - 1) {
             SpinorList pl;
@@ -386,6 +388,22 @@ struct Run {
         return HISQ_OK;
     }
     double c_ = 0.0;
+
+    // bytes between the gradient slots of one shift's ring
+    size_t slot_bytes() const { return (size_t)spinor_site_bytes(fmt.spinor) * vh; }
+
+    // a block ended at gradient slot jb: shifts still being updated flush their
+    // buffered slots and restart their ring at slot 0 like the base
+    hisq_status realign_shifts(int jb) {
+        if (!multishift || jb == nb - 1) return HISQ_OK;
+        SpinorList xl, pl;
+        for (int i = 0; i < HISQ_MAX_SHIFTS; i++) {
+            xl.p[i] = B->xs[i];
+            pl.p[i] = B->ps[i];
+        }
+        HISQ_TRY_HIP(launch_shift_realign(xl, pl, B->ctrl, nshift, vh, slot_bytes(), jb, fmt.spinor, fmt.compute, st));
+        return HISQ_OK;
+    }
 
     // r64 = b - (c x64 - D_eo D_oe x64), |r64|^2 -> done flag (FP64 operator)
     hisq_status enq_true_residual() {
@@ -484,9 +502,11 @@ struct Run {
             dslash_sloppy += 2 * dk;
             alg_bytes += dk * iter_bytes();
             if (multishift) {
+                // r once; per updated shift: its slot read and the next one written, plus
+                // the ring flush (N_b-1 more slots and an FP64 read-modify-write) every N_b
                 const double bs = spinor_site_bytes(fmt.spinor);
                 const int ne = __builtin_popcount((unsigned)h->e_mask);
-                alg_bytes += dk * (double)vh * (bs + ne * (2.0 * bs + 96.0));
+                alg_bytes += dk * (double)vh * (bs + ne * (2.0 * bs + ((nb - 1) * bs + 96.0) / nb));
             }
             if (h->stop == STOP_NEVER) continue;
             if (h->breakdown)
@@ -496,6 +516,7 @@ struct Run {
                 return set_error(HISQ_EBREAKDOWN, "inconsistent solver state (stop %d, reason %d)", h->stop, h->reason);
             const int js = h->stop, jb = js % nb;
             last_slot = jb;
+            HISQ_TRY(realign_shifts(jb));
             if (h->reason == STOP_MSDONE) {
                 SpinorList pl;
                 for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;

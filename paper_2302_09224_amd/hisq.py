@@ -44,7 +44,11 @@ class hisq_fmt(ctypes.Structure):
 
 class hisq_gauge(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("fmt", ctypes.c_int), ("fat", ctypes.c_void_p),
-                ("lng", ctypes.c_void_p), ("fat_max", ctypes.c_double), ("long_max", ctypes.c_double)]
+                ("lng", ctypes.c_void_p), ("fat_max", ctypes.c_double), ("long_max", ctypes.c_double),
+                ("long_recon", ctypes.c_int), ("long_coeff", ctypes.c_double)]
+
+
+RECON_18, RECON_12 = 18, 12
 
 
 class hisq_solver_params(ctypes.Structure):
@@ -114,6 +118,8 @@ def load():
         "hisq_gauge_bytes": (sz, [ip, i]),
         "hisq_spinor_bytes": (sz, [ctypes.c_long, i]),
         "hisq_gauge_pack": (i, [G, vp, vp, vp, vp, ip, i, vp]),
+        "hisq_gauge_pack_recon": (i, [G, vp, vp, vp, vp, ip, i, i, vp]),
+        "hisq_gauge_long_bytes": (sz, [ip, i, i]),
         "hisq_spinor_pack": (i, [vp, vp, ctypes.c_long, i, vp]),
         "hisq_spinor_unpack": (i, [vp, vp, ctypes.c_long, i, vp]),
         "hisq_dslash": (i, [vp, vp, G, i, hisq_fmt, vp]),
@@ -173,6 +179,18 @@ def _dims(dims):
 
 def hisq_gauge_bytes(dims, gauge_fmt):
     return load().hisq_gauge_bytes(_dims(dims), int(gauge_fmt))
+
+
+def hisq_gauge_long_bytes(dims, gauge_fmt, long_recon):
+    return load().hisq_gauge_long_bytes(_dims(dims), int(gauge_fmt), int(long_recon))
+
+
+def hisq_gauge_pack_recon(fat_dst, long_dst, fat_src, long_src, dims, gauge_fmt, long_recon, stream=None):
+    g = hisq_gauge()
+    _check(load().hisq_gauge_pack_recon(ctypes.byref(g), _ptr(fat_dst), _ptr(long_dst), _ptr(fat_src),
+                                        _ptr(long_src), _dims(dims), int(gauge_fmt), int(long_recon),
+                                        _stream(stream)), "hisq_gauge_pack_recon")
+    return g
 
 
 def hisq_spinor_bytes(nsites, spinor_fmt):
@@ -299,13 +317,14 @@ class PackedGauge:
         self.fat, self.lng, self.desc, self.dims, self.fmt = fat, lng, desc, tuple(dims), gauge_fmt
 
 
-def pack_gauge(fat, lng, dims, gauge_fmt, stream=None):
-    """canonical complex128 links [4,V,3,3] (device) -> PackedGauge"""
+def pack_gauge(fat, lng, dims, gauge_fmt, long_recon=RECON_18, stream=None):
+    """canonical complex128 links [4,V,3,3] (device) -> PackedGauge; long_recon=12
+    stores the long links as two rows (they must be lambda * phase * SU(3))"""
     fat = torch.view_as_real(fat.contiguous()) if fat.is_complex() else fat.contiguous()
     lng = torch.view_as_real(lng.contiguous()) if lng.is_complex() else lng.contiguous()
-    nb = hisq_gauge_bytes(dims, gauge_fmt)
-    fd, ld = _empty_bytes(nb, fat.device), _empty_bytes(nb, fat.device)
-    g = hisq_gauge_pack(fd, ld, fat, lng, dims, gauge_fmt, stream)
+    fd = _empty_bytes(hisq_gauge_bytes(dims, gauge_fmt), fat.device)
+    ld = _empty_bytes(hisq_gauge_long_bytes(dims, gauge_fmt, long_recon), fat.device)
+    g = hisq_gauge_pack_recon(fd, ld, fat, lng, dims, gauge_fmt, long_recon, stream)
     return PackedGauge(fd, ld, g, dims, gauge_fmt)
 
 

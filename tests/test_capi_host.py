@@ -44,6 +44,11 @@ def test_sizes(hisq):
     assert hisq.hisq_gauge_bytes((5, 4, 4, 4), 0) == 0          # odd extent
     assert hisq.hisq_gauge_bytes((2, 4, 4, 4), 0) == 0          # extent below 4
     assert hisq.hisq_spinor_bytes(10, 9) == 0                   # unknown format
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_FIX16, 18) == 4 * V * 36
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_FIX16, 12) == 4 * V * 24
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_F64, 12) == 4 * V * 96
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_FIX32, 12) == 4 * V * 48
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_F32, 8) == 0  # unknown storage
     p = hisq.hisq_solver_params_default()
     assert p.delta == 0.1 and p.grad_buffer == 4 and p.pr_beta == 1 and p.reproject == 1
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("half"), p) > 0
@@ -74,3 +79,5 @@ def test_argument_errors(hisq):
     assert lib.hisq_spinor_pack(4096 + 8, 4096, 10, 1, None) == -2
     dims = (ctypes.c_int * 4)(4, 4, 4, 3)
     assert lib.hisq_gauge_pack(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, None) == -1
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.hisq_gauge_pack_recon(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, 9, None) == -1

@@ -1,0 +1,146 @@
+"""Long links stored as two rows (the third rebuilt in the Dslash) against the
+oracle's emulation of the same storage, element by element, and the solvers
+with such a sloppy gauge against the oracle's FP64 solve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import need_gpu
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32"]
+SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}
+GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+
+
+def eps_c(compute):
+    return 1e-6 if compute == 32 else 1e-13
+
+
+@pytest.mark.parametrize("name", TRIPLETS)
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 8, 10, 12), (4, 6, 4, 8)])
+def test_dslash_recon12(name, dims):
+    hisq = need_gpu()
+    f = hisq.fmt(name)
+    for kind in ("near_unit", "haar"):
+        fat, lng = inputs.make_links(dims, kind, seed=inputs.GAUGE_SEED + 11)
+        V = oracle.volume(dims)
+        psi = inputs.gaussian_spinor(V, inputs.SOURCE_SEED + 11).numpy()
+        pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge, long_recon=hisq.RECON_12)
+        assert pg.desc.long_recon == 12 and abs(pg.desc.long_coeff + 1 / 24) < 1e-14
+        for parity in (0, 1):
+            src, dst = oracle.parity_sites(dims, 1 - parity), oracle.parity_sites(dims, parity)
+            pin = hisq.pack_spinor(torch.from_numpy(psi[src]).cuda(), f.spinor)
+            y = hisq.unpack_spinor(hisq.dslash(pin, pg, parity, f), dst.size, f.spinor).cpu().numpy()
+            full = np.zeros_like(psi)
+            full[src] = psi[src]
+            ref = oracle.emulated_dslash(fat.numpy(), lng.numpy(), full, dims, parity, GF_NAME[f.gauge],
+                                         SF_NAME[f.spinor], f.compute, long_recon=12)[dst]
+            q = oracle.spinor_quantum(ref, SF_NAME[f.spinor])[:, None]
+            # one quantum of the rebuilt-row rounding on top of the 18-real bound
+            bound = 0.5 * q * (1 + 1e-3) + 2 * eps_c(f.compute) * np.abs(ref).max()
+            d = y - ref
+            worst = float((np.maximum(np.abs(d.real), np.abs(d.imag)) / bound).max())
+            assert worst <= 1.0, f"{name} {dims} {kind} parity {parity}: max err/bound {worst:.3f}"
+
+
+@pytest.mark.parametrize("name", ["single", "half", "int20", "int30"])
+def test_batched_recon12_matches_single(name):
+    hisq = need_gpu()
+    dims, nrhs = (6, 8, 10, 12), 5
+    f = hisq.fmt(name)
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 12)
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge, long_recon=hisq.RECON_12)
+    vh = oracle.volume(dims) // 2
+    srcs = inputs.gaussian_spinor(vh, 501, nrhs=nrhs).numpy()
+    packed = [hisq.pack_spinor(torch.from_numpy(srcs[j]).cuda(), f.spinor) for j in range(nrhs)]
+    nb = hisq.hisq_spinor_bytes(vh, f.spinor)
+    pin = torch.cat([pk[:nb] for pk in packed]).contiguous()
+    pout = torch.empty_like(pin)
+    hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
+    for j in range(nrhs):
+        ys = hisq.unpack_spinor(hisq.dslash(packed[j], pg, 1, f), vh, f.spinor).cpu().numpy()
+        yb = hisq.unpack_spinor(pout[j * nb:(j + 1) * nb].contiguous(), vh, f.spinor).cpu().numpy()
+        q = oracle.spinor_quantum(ys, SF_NAME[f.spinor])[:, None]
+        d = yb - ys
+        assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= q + eps_c(f.compute) * np.abs(ys).max()).all()
+
+
+def test_pack_recon12_rejects_non_su3():
+    hisq = need_gpu()
+    dims = (4, 4, 4, 4)
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 13)
+    with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
+        hisq.pack_gauge(fat.cuda(), fat.cuda(), dims, hisq.GAUGE_FIX16, long_recon=hisq.RECON_12)
+    bad = lng.clone()
+    bad[2, 9] *= -1.0
+    with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
+        hisq.pack_gauge(fat.cuda(), bad.cuda(), dims, hisq.GAUGE_FIX16, long_recon=hisq.RECON_12)
+    # the free field is accepted: U = 1, coefficient c3
+    f1, l1 = inputs.unit_links(dims, c3=-0.125)
+    pg = hisq.pack_gauge(f1.cuda(), l1.cuda(), dims, hisq.GAUGE_FIX32, long_recon=hisq.RECON_12)
+    assert pg.desc.long_coeff == -0.125 and pg.desc.long_max == 1.0
+
+
+def _full(dims, ev, v):
+    f = np.zeros((oracle.volume(dims), 3), dtype=np.complex128)
+    f[ev] = v
+    return f
+
+
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single"])
+def test_cg_recon12_sloppy(sloppy):
+    """mixed CG whose sloppy operator reads two-row long links; the reliable
+    updates use the full FP64 operator, so the solution meets the target"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED)
+    ev = oracle.parity_sites(dims, 0)
+    b = inputs.gaussian_spinor(ev.size, inputs.SOURCE_SEED).numpy()
+    p64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    ps = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.fmt(sloppy).gauge, long_recon=hisq.RECON_12)
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), p64, ps, mass, tol=1e-10, sloppy=sloppy)
+    assert st["status"] == "HISQ_OK", st
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), _full(dims, ev, x.cpu().numpy()), _full(dims, ev, b),
+                               dims, mass)
+    assert res <= 1e-10 * (1 + 1e-6), (res, st)
+
+
+def test_multishift_recon12():
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED)
+    ev = oracle.parity_sites(dims, 0)
+    b = inputs.gaussian_spinor(ev.size, inputs.SOURCE_SEED).numpy()
+    shifts = [0.0, 0.01, 0.1, 1.0]
+    tol = [1e-10] * 4
+    p64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    pms = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX32, long_recon=hisq.RECON_12)
+    pref = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16, long_recon=hisq.RECON_12)
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, p64, pms, pref, mass,
+                                      ms_fmt="int30", ref_fmt="int20")
+    assert st["status"] == "HISQ_OK", st
+    for i, s in enumerate(shifts):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), _full(dims, ev, xs[i].cpu().numpy()),
+                                   _full(dims, ev, b), dims, mass, shift=s)
+        assert res <= 1e-10 * (1 + 1e-6), (i, res, st)
+
+
+def test_batched_cg_recon12():
+    hisq = need_gpu()
+    dims, mass, nrhs = (6, 8, 10, 12), 0.1, 4
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED)
+    ev = oracle.parity_sites(dims, 0)
+    bs = inputs.gaussian_spinor(ev.size, inputs.RHS_SEED, nrhs=nrhs).numpy()
+    p64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    ps = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16, long_recon=hisq.RECON_12)
+    x, st = hisq.cg_solve_batched(torch.from_numpy(bs).cuda(), p64, ps, mass, tol=1e-10, sloppy="int20")
+    assert st["status"] == "HISQ_OK", st
+    x = x.cpu().numpy()
+    for j in range(nrhs):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), _full(dims, ev, x[j]), _full(dims, ev, bs[j]),
+                                   dims, mass)
+        assert res <= 1e-10 * (1 + 1e-6), (j, res)

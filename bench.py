@@ -6,7 +6,8 @@ solved to a 1e-10 true relative residual.  A step packs the FP64 links (already
 resident in HBM) into the solver's storage formats and runs the multi-shift
 solve: multi-shift phase in 32-bit links / 30-bit fermions / FP64 compute with
 FP64 reliable updates, then CG refinement in 16-bit links / 20-bit fermions /
-FP32 compute (the paper's improved variant, Sec. 6.2).
+FP32 compute (the paper's improved variant, Sec. 6.2).  The low-precision
+operators keep the long links as two rows of an SU(3) matrix (--recon 12).
 
 Printed (one JSON line): whole-step algorithmic HBM GB/s (value), the
 per-triplet Dslash GB/s and GFLOP/s measured with HIP events (the Fig. 3
@@ -90,6 +91,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--ms", type=str, default="int30")
     ap.add_argument("--ref", type=str, default="int20")
+    ap.add_argument("--recon", type=int, default=12, choices=(12, 18),
+                    help="long-link storage of the solver's low-precision operators (12: two rows)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
@@ -140,15 +143,21 @@ def main():
     kernels = {}
     gauges = {}
 
-    def gauge(gf):
-        if gf not in gauges:
-            gauges[gf] = hisq.pack_gauge(fat, lng, dims, gf)
-        return gauges[gf]
+    def gauge(gf, recon):
+        if (gf, recon) not in gauges:
+            gauges[(gf, recon)] = hisq.pack_gauge(fat, lng, dims, gf, long_recon=recon)
+        return gauges[(gf, recon)]
+
+    def link_bytes(gf, recon):
+        return 8 * hisq.GAUGE_BYTES[gf] + 8 * (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12 else hisq.GAUGE_BYTES[gf])
 
     stream = torch.cuda.current_stream()
-    for name in ("double", "single", "half", "int20", "int30", "int30_fp32"):
+    table = [(n, 18) for n in ("double", "single", "half", "int20", "int30", "int30_fp32")]
+    table += [(n, 12) for n in ("double", "single", "half", "int20", "int30", "int30_fp32")]
+    for name, recon in table:
+        key = name if recon == 18 else f"{name}_r12"
         f = hisq.fmt(name)
-        pg = gauge(f.gauge)
+        pg = gauge(f.gauge, recon)
         pin = hisq.pack_spinor(b, f.spinor)
         out = torch.empty_like(pin)
         for _ in range(3):
@@ -160,12 +169,12 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.dslash_reps
-        nbytes = vh * (16 * hisq.GAUGE_BYTES[f.gauge] + 2 * hisq.SPINOR_BYTES[f.spinor])
-        kernels[name] = dict(triplet=repr(f), us=round(ms * 1e3, 2), alg_bytes=nbytes,
-                             gbs=round(nbytes / ms / 1e6, 1), gflops=round(FLOP_PER_SITE * vh / ms / 1e6, 1),
-                             frac_hbm=round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4))
-        log(f"[bench] dslash {name:11s} {kernels[name]['us']:9.1f} us  {kernels[name]['gbs']:7.1f} GB/s "
-            f"{kernels[name]['gflops']:7.1f} GFLOP/s  ({100 * kernels[name]['frac_hbm']:.1f}% HBM)")
+        nbytes = vh * (link_bytes(f.gauge, recon) + 2 * hisq.SPINOR_BYTES[f.spinor])
+        kernels[key] = dict(triplet=repr(f), long_recon=recon, us=round(ms * 1e3, 2), alg_bytes=nbytes,
+                            gbs=round(nbytes / ms / 1e6, 1), gflops=round(FLOP_PER_SITE * vh / ms / 1e6, 1),
+                            frac_hbm=round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4))
+        log(f"[bench] dslash {key:15s} {kernels[key]['us']:9.1f} us  {kernels[key]['gbs']:7.1f} GB/s "
+            f"{kernels[key]['gflops']:7.1f} GFLOP/s  ({100 * kernels[key]['frac_hbm']:.1f}% HBM)")
         del pin, out
     batched = None
     if args.batched:
@@ -176,17 +185,14 @@ def main():
     if args.kernels_only:
         print(json.dumps(dict(kernels=kernels, batched=batched, tuning=tuning)))
         return
-    for gf in list(gauges):
-        if gf not in (hisq.GAUGE_F64, fms.gauge, fref.gauge):
-            del gauges[gf]
     gauges.clear()
     torch.cuda.empty_cache()
 
     # ---------------- the timed step ----------------
     def step():
         g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
-        gms = hisq.pack_gauge(fat, lng, dims, fms.gauge)
-        gref = gms if fref.gauge == fms.gauge else hisq.pack_gauge(fat, lng, dims, fref.gauge)
+        gms = hisq.pack_gauge(fat, lng, dims, fms.gauge, long_recon=args.recon)
+        gref = gms if fref.gauge == fms.gauge else hisq.pack_gauge(fat, lng, dims, fref.gauge, long_recon=args.recon)
         xs, st = hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=args.ms,
                                           ref_fmt=args.ref)
         return xs, st
@@ -210,8 +216,13 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
-    pack_bytes = 2 * 4 * V * (144 + 144 + hisq.GAUGE_BYTES[fms.gauge]
-                              + (hisq.GAUGE_BYTES[fref.gauge] + 144 if fref.gauge != fms.gauge else 0))
+    # packing: every packed field reads its FP64 source once and writes its storage
+    def pack_field_bytes(gf, recon):
+        return 4 * V * (2 * 144 + hisq.GAUGE_BYTES[gf] + (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12
+                                                           else hisq.GAUGE_BYTES[gf]))
+    pack_bytes = pack_field_bytes(hisq.GAUGE_F64, 18) + pack_field_bytes(fms.gauge, args.recon)
+    if fref.gauge != fms.gauge:
+        pack_bytes += pack_field_bytes(fref.gauge, args.recon)
     step_bytes = float(np.mean([s["alg_bytes"] for s in stats])) + pack_bytes
     value = step_bytes / (ms_per_step / 1e3) / 1e9
     last = stats[-1]
@@ -224,20 +235,21 @@ def main():
         del xs
         torch.cuda.empty_cache()
         g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+        g64s = g64 if args.recon == 18 else hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=args.recon)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        xs64, st64 = hisq.multishift_cg_solve(b, shifts, tols, g64, g64, g64, args.mass, ms_fmt="double",
+        xs64, st64 = hisq.multishift_cg_solve(b, shifts, tols, g64, g64s, g64s, args.mass, ms_fmt="double",
                                               ref_fmt="double", delta=0.0)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
         fp64 = dict(seconds=round(t64, 3), iters=st64["iters"], refine_iters=st64["refine_iters"],
                     resid_max=max(st64["shift_resid"]), speedup_mixed=round(t64 / (ms_per_step / 1e3), 3))
         log(f"[bench]   FP64: {t64:.2f}s, iters {st64['iters']}, refine {st64['refine_iters']}")
-        del xs64, g64
+        del xs64, g64, g64s
         torch.cuda.empty_cache()
 
     # ---------------- roofline of the dominant kernel ----------------
-    dom = args.ms
+    dom = args.ms if args.recon == 18 else f"{args.ms}_r12"
     kd = kernels[dom]
     roofline = dict(bound="hbm", achieved=kd["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(kd["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
@@ -273,7 +285,7 @@ def main():
         cpu = dict(value=round(gbs_cpu, 3), unit="GB/s", cores=nthr, kind="oracle",
                    sample=f"FP64 oracle Dslash at {sample.size} random even sites of the {dims} lattice, "
                           f"repeated {done_sites // sample.size}x ({tc:.1f}s); algorithmic bytes 2400/site",
-                   vs_gpu_fp64_dslash=round(kernels['double']['gbs'] / gbs_cpu, 1))
+                   vs_gpu_fp64_dslash=round(kernels["double"]["gbs"] / gbs_cpu, 1))
         del fat_h, lng_h, full
 
     line = {
@@ -291,7 +303,8 @@ def main():
         "data": "synthetic (seeded near-unit SU(3) links exp(0.3iH), Gaussian source)",
         "config": {"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "lattice": list(dims),
                    "mass": args.mass, "shifts": [float(f"{s:.4g}") for s in shifts], "tol": args.tol,
-                   "ms_triplet": repr(fms), "refine_triplet": repr(fref), "parallelism": "single GPU"},
+                   "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
+                   "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],
                        "resid_after_ms": [float(f"{r:.3g}") for r in last["shift_resid_ms"]],

@@ -189,6 +189,8 @@ typedef struct {
     double shift_floor;  /* multi-shift: a shifted system stops updating once its iterated residual is below
                             max(tol_i, shift_floor) (Sec. 3.2: "reach the limit of the sloppy precision");
                             <= 0 selects the sloppy format's epsilon */
+    int batch_refine;    /* multi-shift: refine the shifted systems together, one Dslash per iteration shared
+                            by up to 16 of them (1), or one after another (0); the base is always refined first */
 } hisq_solver_params;
 
 typedef struct {
@@ -208,7 +210,7 @@ typedef struct {
 } hisq_solver_stats;
 
 /* Default parameters: delta 0.1, maxiter 100000, grad_buffer 4, PR beta,
- * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto). */
+ * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 1. */
 void hisq_solver_params_default(hisq_solver_params *p);
 
 /* Workspace bytes for hisq_cg_solve on `dims` with sloppy format `sloppy`. */
@@ -244,8 +246,11 @@ size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift, hisq_fmt m
  * shift i stops updating when its iterated residual reaches
  * max(tol_i, shift_floor); the phase ends when every shift i >= 1 has
  * stopped.  Then CG refinement in the refine_fmt triplet: the base first,
- * keeping its gradient vector, then every shift in ascending order from a
- * clean restart, each to its own tol_i (true residual).
+ * keeping its gradient vector, then every shift from a clean restart, each to
+ * its own tol_i (true residual): in ascending order, or (p->batch_refine,
+ * the default, for refine triplets other than FIX32/INT30/FP32) in blocks of
+ * up to 16 independent CGs sharing every Dslash (each the iteration of a
+ * lone solve, except that a reliable update asked for by one is done for all).
  * x: (host) array of nshift (device) canonical complex128 [Vh][3] outputs.
  * shifts, tol: (host) arrays of nshift doubles, shifts strictly ascending,
  * shifts[0] >= 0 and 1 <= nshift <= HISQ_MAX_SHIFTS.
@@ -273,13 +278,28 @@ hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hi
                                   size_t ws_bytes, hisq_solver_stats *stats, void *stream);
 
 /* Launch shapes chosen by the Dslash autotuner so far (one text line per
- * triplet, lattice and right-hand-side block: right-hand sides per lane, lanes
+ * triplet, long-link storage, lattice and right-hand-side block: right-hand sides per lane, lanes
  * per site, hops per load stage, block size, measured time).  Writes at most
  * len bytes (NUL-terminated) into buf if buf is not NULL; returns the size the
  * full report needs.  The autotuner times each candidate shape with HIP events
  * on the first application of a shape key (never inside stream capture);
  * environment HISQ_TUNE=0 selects fixed defaults instead. */
 size_t hisq_tune_report(char *buf, size_t len);
+
+/* Fix the launch shape of the Dslash for triplet fmt on lattice dims with long
+ * links stored as long_recon (HISQ_RECON_18 or HISQ_RECON_12) and a block of
+ * rhs_block right-hand sides (1, 2, 4, 8 or 16), replacing what the
+ * autotuner chose or would choose: nr right-hand sides per lane and rg lanes
+ * per site (nr * rg == rhs_block, both powers of two), stage hops per load
+ * stage (1, 2, 4 or 8 when nr == 1; 1 otherwise), block threads (128 or 256)
+ * and grid blocks (0: one tile of lanes per block; otherwise a multiple of 8,
+ * a persistent grid when smaller than the tile count).  For reproducible
+ * launch shapes and for tests.  HISQ_EINVAL for an unsupported shape. */
+hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
+                          int stage, int block, int grid);
+
+/* Forget every tuned or fixed launch shape (the next application tunes again). */
+void hisq_tune_clear(void);
 
 /* Thread-local message of the calling thread's last non-OK status. */
 const char *hisq_last_error(void);

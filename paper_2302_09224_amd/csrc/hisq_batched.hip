@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "hisq_internal.h"
 
@@ -102,7 +103,7 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
         c->bpb[j] = beta;
         c->brmax2[j] = fmax(c->brmax2[j], rn);
         if (c->delta2 > 0.0 && rn < c->delta2 * c->brmax2[j]) reason = reason ? reason : STOP_RU;
-        if (rn <= c->tol2 * c->bb2[j]) reason = reason ? reason : STOP_CONV;
+        if (rn <= c->btol2[j] * c->bb2[j]) reason = reason ? reason : STOP_CONV;
         c->brho_prev[j] = rho;
         c->brho[j] = rn;
     }
@@ -126,7 +127,7 @@ __global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, NbList nl,
         const double r2 = v[0];
         c->br2_true[j] = r2;
         if (!__builtin_isfinite(r2)) c->breakdown = 1;
-        if (c->bactive[j] && r2 <= c->tol2 * c->bb2[j]) {
+        if (c->bactive[j] && r2 <= c->btol2[j] * c->bb2[j]) {
             c->bactive[j] = 0;
             c->bdone[j] = 1;
         }
@@ -210,7 +211,6 @@ struct BRun {
     int nrhs;
     hisq_fmt fmt;
     const hisq_gauge *g64, *gs;
-    double c_;
     int nb, chunk;
     bool graph;
     BBuf *B;
@@ -233,10 +233,10 @@ struct BRun {
         nl_s.pstride = nl_64.pstride = dslash_max_blocks(g.vh);
         for (int i = 0; i < plan_s.n; i++)
             for (int j = 0; j < plan_s.tile[i].nr * plan_s.tile[i].rg; j++)
-                nl_s.nb[plan_s.rhs0[i] + j] = dslash_blocks(g.vh * plan_s.tile[i].rg, plan_s.tile[i].block);
+                nl_s.nb[plan_s.rhs0[i] + j] = dslash_tile_blocks(g.vh, plan_s.tile[i]);
         for (int i = 0; i < plan_64.n; i++)
             for (int j = 0; j < plan_64.tile[i].nr * plan_64.tile[i].rg; j++)
-                nl_64.nb[plan_64.rhs0[i] + j] = dslash_blocks(g.vh * plan_64.tile[i].rg, plan_64.tile[i].block);
+                nl_64.nb[plan_64.rhs0[i] + j] = dslash_tile_blocks(g.vh, plan_64.tile[i]);
     }
 
     ~BRun() {
@@ -270,7 +270,7 @@ struct BRun {
         DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
-        Bk.a = c_;
+        Bk.acol = c->bc;
         Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
         Bk.pstride = nl_s.pstride;
@@ -303,7 +303,7 @@ struct BRun {
         HISQ_TRY_HIP(launch_dslash(A, f64, plan_64, st, nullptr));
         DslashArgs Bk = dargs(g64, f64, B->r64, B->t64, 0);
         Bk.x = B->x64;
-        Bk.a = -c_;
+        Bk.acol = c->bnc;
         Bk.y = B->b64;
         Bk.c = 1.0;
         Bk.red = RED_NORM;
@@ -313,7 +313,7 @@ struct BRun {
         hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, nl_64, nrhs);
         HISQ_TRY_HIP(hipGetLastError());
         d64 += 2;
-        alg += 2.0 * vh * (16.0 * 144 + nrhs * 2.0 * 48) + 2.0 * vh * nrhs * 48;
+        alg += 2.0 * vh * (dslash_link_bytes(g64) + nrhs * 2.0 * 48) + 2.0 * vh * nrhs * 48;
         const Guard g0{&c->stop, 0, 0};
         HISQ_TRY_HIP(launch_bru_convert(B->rs, B->r64, fs64, mode == 1 ? nullptr : p_src, mode == 0 ? B->aps : nullptr,
                                         c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, g0, st));
@@ -366,94 +366,57 @@ BDev g_bdev[64];
 
 }  // namespace
 
-}  // namespace hisq
-
-using namespace hisq;
-
-extern "C" size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt sloppy,
-                                                  const hisq_solver_params *p) {
-    if (!dims || !dims_ok(dims) || !triplet_ok(sloppy) || nrhs < 1 || nrhs > 16) return 0;
-    hisq_solver_params q;
-    hisq_solver_params_default(&q);
-    if (p) q = *p;
-    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return 0;
-    return carve(nullptr, nullptr, make_geom(dims), nrhs, spinor_site_bytes(sloppy.spinor), q.grad_buffer);
+bool batched_fmt_ok(const hisq_fmt &f) {
+    return triplet_ok(f) && !(f.gauge == HISQ_GAUGE_FIX32 && f.compute == 32);
 }
 
-extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hisq_gauge *g64,
-                                             const hisq_gauge *gs, double mass, double shift, double tol,
-                                             hisq_fmt sloppy, const hisq_solver_params *p, void *ws, size_t ws_bytes,
-                                             hisq_solver_stats *stats, void *stream) {
-    auto t0 = std::chrono::steady_clock::now();
-    hisq_solver_stats tmp;
-    hisq_solver_stats *st = stats ? stats : &tmp;
-    memset(st, 0, sizeof(*st));
-    st->status = HISQ_EINVAL;
-    if (!x || !b || !g64 || !gs || !ws) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: null argument");
-    if (nrhs < 1 || nrhs > 16) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: nrhs must be in [1,16]");
-    if (!aligned16(x) || !aligned16(b) || !aligned16(ws)) return set_error(HISQ_EALIGN, "unaligned pointer");
-    if (!triplet_ok(sloppy) || (sloppy.gauge == HISQ_GAUGE_FIX32 && sloppy.compute == 32))
-        return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: unsupported sloppy triplet");
-    if (!(tol > 0.0)) return set_error(HISQ_EINVAL, "tol must be > 0");
-    const int *dims = g64->dims;
-    if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
-    if (!gs->fat || !gs->lng || gs->fmt != sloppy.gauge || g64->fmt != HISQ_GAUGE_F64 || !g64->fat || !g64->lng)
-        return set_error(HISQ_EINVAL, "gauge format mismatch or null gauge");
-    for (int k = 0; k < 4; k++)
-        if (gs->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "gauge dims differ");
-    hisq_solver_params q;
-    hisq_solver_params_default(&q);
-    if (p) q = *p;
-    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return set_error(HISQ_EINVAL, "bad grad_buffer");
-    if (q.maxiter <= 0) q.maxiter = 100000;
-    if (q.poll_every <= 0) q.poll_every = 32;
-    const Geom g = make_geom(dims);
-    BBuf B;
-    const size_t need = carve(&B, (char *)ws, g, nrhs, spinor_site_bytes(sloppy.spinor), q.grad_buffer);
-    if (ws_bytes < need) return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+size_t batched_ws_bytes(const Geom &g, int nrhs, int sf, int nb) {
+    return carve(nullptr, nullptr, g, nrhs, spinor_site_bytes(sf), nb);
+}
 
-    int d = 0;
-    HISQ_TRY_HIP(hipGetDevice(&d));
-    BDev &dv = g_bdev[d & 63];
-    std::unique_lock<std::mutex> lk(dv.mu);
-    if (!dv.stream) {
-        HISQ_TRY_HIP(hipStreamCreateWithFlags(&dv.stream, hipStreamNonBlocking));
-        HISQ_TRY_HIP(hipEventCreateWithFlags(&dv.ev, hipEventDisableTiming));
-        HISQ_TRY_HIP(hipHostMalloc((void **)&dv.host, sizeof(SolverCtrl), hipHostMallocDefault));
-    }
-    HISQ_TRY_HIP(hipEventRecord(dv.ev, (hipStream_t)stream));
-    HISQ_TRY_HIP(hipStreamWaitEvent(dv.stream, dv.ev, 0));
-    hipStream_t s_ = dv.stream;
+hisq_status batched_run(BatchedJob &J) {
+    const int nrhs = J.nrhs;
+    const hisq_solver_params &q = J.q;
+    const Geom g = make_geom(J.g64->dims);
+    hipStream_t s_ = J.st;
+    J.iters = J.rus = J.dsl = J.d64 = 0;
+    J.alg = 0.0;
+    BBuf B;
+    const size_t need = carve(&B, (char *)J.ws, g, nrhs, spinor_site_bytes(J.fmt.spinor), q.grad_buffer);
+    if (J.ws_bytes < need) return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", J.ws_bytes, need);
 
     BRun R;
     R.g = g;
     R.vh = g.vh;
     R.nrhs = nrhs;
-    R.fmt = sloppy;
-    R.g64 = g64;
-    R.gs = gs;
-    R.c_ = 4.0 * mass * mass + shift;
+    R.fmt = J.fmt;
+    R.g64 = J.g64;
+    R.gs = J.gs;
     R.nb = q.grad_buffer;
     R.chunk = ((q.poll_every + q.grad_buffer - 1) / q.grad_buffer) * q.grad_buffer;
     R.graph = q.use_graph != 0;
     R.B = &B;
     R.st = s_;
-    R.fs = spinor_field_bytes(g.vh, sloppy.spinor);
+    R.fs = spinor_field_bytes(g.vh, J.fmt.spinor);
     R.fs64 = spinor_field_bytes(g.vh, SF_F64);
 
     for (int j = 0; j < nrhs; j++) {
-        HISQ_TRY_HIP(launch_spinor_pack(B.x64 + j * R.fs64, x + 6 * (size_t)g.vh * j, g.vh, SF_F64, s_));
-        HISQ_TRY_HIP(launch_spinor_pack(B.b64 + j * R.fs64, b + 6 * (size_t)g.vh * j, g.vh, SF_F64, s_));
+        HISQ_TRY_HIP(launch_spinor_pack(B.x64 + j * R.fs64, J.x[j], g.vh, SF_F64, s_));
+        HISQ_TRY_HIP(launch_spinor_pack(B.b64 + j * R.fs64, J.b[j], g.vh, SF_F64, s_));
     }
-    SolverCtrl *h = dv.host;
+    SolverCtrl *h = J.h;
     memset(h, 0, sizeof(*h));
     h->stop = STOP_NEVER;
     h->pr = q.pr_beta;
     h->reproject = q.reproject;
     h->maxiter = q.maxiter;
-    h->tol2 = tol * tol;
     h->delta2 = q.delta > 0 ? q.delta * q.delta : 0.0;
-    for (int j = 0; j < nrhs; j++) h->bactive[j] = 1;
+    for (int j = 0; j < nrhs; j++) {
+        h->bactive[j] = 1;
+        h->bc[j] = J.c[j];
+        h->bnc[j] = -J.c[j];
+        h->btol2[j] = J.tol[j] * J.tol[j];
+    }
     HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
     // |b_j|^2: the F64 norm kernel per right-hand side, each into its own partial column
     for (int j = 0; j < nrhs; j++) {
@@ -480,6 +443,7 @@ extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrh
     R.setup_plans();
     hisq_status status = R.enq_reliable(1, 0, nullptr);
     if (status == HISQ_OK) status = R.read_ctrl(h);
+    for (int j = 0; j < nrhs; j++) J.resid0_j[j] = h->bb2[j] > 0 ? std::sqrt(h->br2_true[j] / h->bb2[j]) : 0.0;
     long k0 = 0;
     while (status == HISQ_OK && !h->done) {
         if (h->breakdown) {
@@ -495,8 +459,13 @@ extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrh
         R.iters += dk;
         R.dsl += 2 * dk;
         {
-            const double bs = spinor_site_bytes(sloppy.spinor), bg = gauge_matrix_bytes(sloppy.gauge);
-            R.alg += dk * (double)g.vh * (2.0 * (16.0 * bg + nrhs * 2.0 * bs) + nrhs * (bs + 6.0 * bs + (R.nb * bs + 96.0) / R.nb));
+            // links once per Dslash; spinor traffic of every right-hand side in the
+            // Dslash, of the active ones in the vector updates
+            int na = 0;
+            for (int j = 0; j < nrhs; j++) na += h->bactive[j] ? 1 : 0;
+            const double bs = spinor_site_bytes(J.fmt.spinor), bl = dslash_link_bytes(J.gs);
+            R.alg += dk * (double)g.vh * (2.0 * (bl + nrhs * 2.0 * bs) + nrhs * bs
+                                          + na * (6.0 * bs + (R.nb * bs + 96.0) / R.nb));
         }
         if (h->stop == STOP_NEVER) continue;
         if (h->breakdown) {
@@ -521,21 +490,108 @@ extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrh
         }
     }
     for (int j = 0; j < nrhs; j++) {
-        hipError_t e = launch_spinor_unpack(x + 6 * (size_t)g.vh * j, B.x64 + j * R.fs64, g.vh, SF_F64, s_);
+        hipError_t e = launch_spinor_unpack(J.x[j], B.x64 + j * R.fs64, g.vh, SF_F64, s_);
         if (e != hipSuccess && status == HISQ_OK) status = set_error(HISQ_EHIP, "unpack: %s", hipGetErrorString(e));
     }
     hipError_t e = hipStreamSynchronize(s_);
     if (e != hipSuccess && status == HISQ_OK) status = set_error(HISQ_EHIP, "sync: %s", hipGetErrorString(e));
-    st->iters = (int)R.iters;
-    st->reliable_updates = (int)R.rus;
-    st->dslash_sloppy = (int)R.dsl;
-    st->dslash_f64 = (int)R.d64;
-    st->alg_bytes = R.alg;
+    J.iters = R.iters;
+    J.rus = R.rus;
+    J.dsl = R.dsl;
+    J.d64 = R.d64;
+    J.alg = R.alg;
+    for (int j = 0; j < nrhs; j++) {
+        J.resid_j[j] = h->bb2[j] > 0 ? std::sqrt(h->br2_true[j] / h->bb2[j]) : 0.0;
+        J.iters_j[j] = h->bk[j];
+    }
+    return status;
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt sloppy,
+                                                  const hisq_solver_params *p) {
+    if (!dims || !dims_ok(dims) || !triplet_ok(sloppy) || nrhs < 1 || nrhs > 16) return 0;
+    hisq_solver_params q;
+    hisq_solver_params_default(&q);
+    if (p) q = *p;
+    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return 0;
+    return batched_ws_bytes(make_geom(dims), nrhs, sloppy.spinor, q.grad_buffer);
+}
+
+extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hisq_gauge *g64,
+                                             const hisq_gauge *gs, double mass, double shift, double tol,
+                                             hisq_fmt sloppy, const hisq_solver_params *p, void *ws, size_t ws_bytes,
+                                             hisq_solver_stats *stats, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    hisq_solver_stats tmp;
+    hisq_solver_stats *st = stats ? stats : &tmp;
+    memset(st, 0, sizeof(*st));
+    st->status = HISQ_EINVAL;
+    if (!x || !b || !g64 || !gs || !ws) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: null argument");
+    if (nrhs < 1 || nrhs > 16) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: nrhs must be in [1,16]");
+    if (!aligned16(x) || !aligned16(b) || !aligned16(ws)) return set_error(HISQ_EALIGN, "unaligned pointer");
+    if (!batched_fmt_ok(sloppy)) return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: unsupported sloppy triplet");
+    if (!(tol > 0.0)) return set_error(HISQ_EINVAL, "tol must be > 0");
+    const int *dims = g64->dims;
+    if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
+    if (!gs->fat || !gs->lng || gs->fmt != sloppy.gauge || g64->fmt != HISQ_GAUGE_F64 || !g64->fat || !g64->lng)
+        return set_error(HISQ_EINVAL, "gauge format mismatch or null gauge");
+    for (int k = 0; k < 4; k++)
+        if (gs->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "gauge dims differ");
+    hisq_solver_params q;
+    hisq_solver_params_default(&q);
+    if (p) q = *p;
+    if (q.grad_buffer < 1 || q.grad_buffer > HISQ_MAX_GRAD_BUFFER) return set_error(HISQ_EINVAL, "bad grad_buffer");
+    if (q.maxiter <= 0) q.maxiter = 100000;
+    if (q.poll_every <= 0) q.poll_every = 32;
+    const Geom g = make_geom(dims);
+    const size_t need = batched_ws_bytes(g, nrhs, sloppy.spinor, q.grad_buffer);
+    if (ws_bytes < need) return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+
+    int d = 0;
+    HISQ_TRY_HIP(hipGetDevice(&d));
+    BDev &dv = g_bdev[d & 63];
+    std::unique_lock<std::mutex> lk(dv.mu);
+    if (!dv.stream) {
+        HISQ_TRY_HIP(hipStreamCreateWithFlags(&dv.stream, hipStreamNonBlocking));
+        HISQ_TRY_HIP(hipEventCreateWithFlags(&dv.ev, hipEventDisableTiming));
+        HISQ_TRY_HIP(hipHostMalloc((void **)&dv.host, sizeof(SolverCtrl), hipHostMallocDefault));
+    }
+    HISQ_TRY_HIP(hipEventRecord(dv.ev, (hipStream_t)stream));
+    HISQ_TRY_HIP(hipStreamWaitEvent(dv.stream, dv.ev, 0));
+
+    BatchedJob J;
+    memset(&J, 0, sizeof(J));
+    J.nrhs = nrhs;
+    for (int j = 0; j < nrhs; j++) {
+        J.x[j] = x + 6 * (size_t)g.vh * j;
+        J.b[j] = b + 6 * (size_t)g.vh * j;
+        J.c[j] = 4.0 * mass * mass + shift;
+        J.tol[j] = tol;
+    }
+    J.g64 = g64;
+    J.gs = gs;
+    J.fmt = sloppy;
+    J.q = q;
+    J.ws = ws;
+    J.ws_bytes = ws_bytes;
+    J.st = dv.stream;
+    J.h = dv.host;
+    hisq_status status = batched_run(J);
+    st->iters = (int)J.iters;
+    st->reliable_updates = (int)J.rus;
+    st->dslash_sloppy = (int)J.dsl;
+    st->dslash_f64 = (int)J.d64;
+    st->alg_bytes = J.alg;
     st->nshift = nrhs;
     double worst = 0.0;
     for (int j = 0; j < nrhs; j++) {
-        st->shift_resid[j] = h->bb2[j] > 0 ? std::sqrt(h->br2_true[j] / h->bb2[j]) : 0.0;
-        st->refine_iters[j] = h->bk[j];
+        st->shift_resid_ms[j] = J.resid0_j[j];
+        st->shift_resid[j] = J.resid_j[j];
+        st->refine_iters[j] = J.iters_j[j];
         worst = std::max(worst, st->shift_resid[j]);
     }
     st->true_resid = worst;

@@ -568,6 +568,8 @@ __global__ void k_bflush_x(char *x64, size_t fs64, SpinorList p, int count, cons
                            int nrhs, Guard gd) {
     if (!gd.pass()) return;
     for (int j = 0; j < nrhs; j++) {
+        // a stopped system's buffered gradients were flushed before it stopped
+        if (!ctrl->bactive[j]) continue;
         char *xj = x64 + j * fs64;
         for (size_t s = gtid(); s < n; s += gstride()) {
             CVec<double> x = SpinorIO<SF_F64, double>::load(xj, n, s);

@@ -41,7 +41,9 @@ hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const Ds
     }
 }
 
-typedef std::tuple<int, int, int, int, int, int> TuneKey;  // triplet, X, Y, Z, T, rhs block
+typedef std::tuple<int, int, int, int, int, int> TuneKey;  // triplet + long-link storage, X, Y, Z, T, rhs block
+
+inline int tune_id(const hisq_fmt &f, int long_recon) { return triplet_key(f) * 100 + (long_recon == 12 ? 12 : 18); }
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<DslashTile, float>> g_tuned;
 
@@ -103,7 +105,7 @@ float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t,
 }
 
 DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *probe, hipStream_t st) {
-    const TuneKey key{triplet_key(f), g.X, g.Y, g.Z, g.T, c};
+    const TuneKey key{tune_id(f, probe ? probe->long_recon : 18), g.X, g.Y, g.Z, g.T, c};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second.first;
@@ -167,6 +169,33 @@ hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPla
 
 }  // namespace hisq
 
+extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
+                                     int stage, int block, int grid) {
+    using namespace hisq;
+    if (!dims || !dims_ok(dims) || !triplet_ok(fmt)) return set_error(HISQ_EINVAL, "hisq_tune_set: bad dims or triplet");
+    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
+        return set_error(HISQ_EINVAL, "hisq_tune_set: long_recon must be 18 or 12");
+    const bool pow2 = rhs_block >= 1 && rhs_block <= 16 && (rhs_block & (rhs_block - 1)) == 0;
+    if (!pow2) return set_error(HISQ_EINVAL, "hisq_tune_set: rhs_block must be 1, 2, 4, 8 or 16");
+    if (rhs_block > 1 && fmt.gauge == HISQ_GAUGE_FIX32 && fmt.compute == 32)
+        return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
+    bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
+    ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0;
+    ok = ok && (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8) : stage == 1);
+    if (!ok)
+        return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d", nr, rg,
+                         stage, block, grid);
+    const TuneKey key{tune_id(fmt, long_recon), dims[0], dims[1], dims[2], dims[3], rhs_block};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid}, -1.f);
+    return HISQ_OK;
+}
+
+extern "C" void hisq_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
+    hisq::g_tuned.clear();
+}
+
 extern "C" size_t hisq_tune_report(char *buf, size_t len) {
     std::string s;
     {
@@ -176,8 +205,10 @@ extern "C" size_t hisq_tune_report(char *buf, size_t len) {
             const auto &k = kv.first;
             const auto &t = kv.second.first;
             snprintf(line, sizeof(line),
-                     "triplet %03d lattice %dx%dx%dx%d rhs-block %d: nr %d rg %d stage %d block %d grid %d (%.1f us)\n",
-                     std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                     "triplet %03d recon %d lattice %dx%dx%dx%d rhs-block %d: nr %d rg %d stage %d block %d grid %d "
+                     "(%.1f us)\n",
+                     std::get<0>(k) / 100, std::get<0>(k) % 100, std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                     std::get<4>(k), std::get<5>(k),
                      t.nr, t.rg, t.stage, t.block, t.grid, kv.second.second * 1e3);
             s += line;
         }

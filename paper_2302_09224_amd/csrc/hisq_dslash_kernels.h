@@ -387,6 +387,16 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     double red[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) red[j] = 0.0;
+    // xpay coefficient of each of the lane's right-hand sides (rg divides
+    // blockDim, so a lane keeps its group in every tile); read once, up front
+    R acoef[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) acoef[j] = (R)A.a;
+    if (A.acol) {
+        const int rc = rhs0 + (int)(threadIdx.x & (unsigned)(rg - 1)) * NR;
+#pragma unroll
+        for (int j = 0; j < NR; j++) acoef[j] = (R)A.acol[rc + j];
+    }
     // Tiles of blockDim lanes; XCD k (blocks b with b % 8 == k) sweeps the
     // contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
     // gridDim/8 blocks taking every (gridDim/8)-th tile: one tile per block when
@@ -478,10 +488,11 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                 }
             }
         }
-        const R b = (R)A.b, a = (R)A.a, cc = (R)A.c;
+        const R b = (R)A.b, cc = (R)A.c;
 #pragma unroll
         for (int j = 0; j < NR; j++) {
             const size_t off = (size_t)(r0 + j) * fs;
+            const R a = acoef[j];
             CVec<R> xv;
             cvec_zero(xv);
 #pragma unroll
@@ -550,8 +561,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 
 template <int GF, int SF, class R, int NR, int STAGE>
 hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, hipStream_t st, int *nblocks) {
-    int nb = dslash_blocks(a.g.vh * rg, block);
-    if (grid > 0 && grid < nb) nb = grid;
+    const int nb = dslash_tile_blocks(a.g.vh, DslashTile{NR, rg, STAGE, block, grid});
     if (nblocks) *nblocks = nb;
     const FastDiv drg = make_fastdiv((unsigned)rg);
     if (a.long_recon == 12) {

@@ -67,6 +67,7 @@ struct DslashArgs {
     size_t pstride;       // partial of right-hand side j, block b at partial[j*pstride + b]
     int long_recon;       // 18: long links stored in full; 12: two rows, L = lcoef * phase * SU(3)
     double lcoef;
+    const double *acol;   // optional (device): coefficient a of right-hand side j is acol[j]
 };
 
 // Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
@@ -87,9 +88,20 @@ struct DslashPlan {
 
 // link pointers, fixed-point steps and long-link storage of a packed gauge
 void gauge_args(DslashArgs &a, const hisq_gauge *g);
+// link bytes one output site of a Dslash reads (8 fat + 8 long matrices)
+inline double dslash_link_bytes(const hisq_gauge *g) {
+    const int b18 = gauge_matrix_bytes(g->fmt);
+    return 8.0 * b18 + 8.0 * (g->long_recon == HISQ_RECON_12 ? gauge_matrix_bytes12(g->fmt) : b18);
+}
 
 // blocks of a Dslash launch over n lanes (multiple of 8 for the XCD order)
 int dslash_blocks(int n, int block);
+// blocks a launch of tile t really uses on vh sites (a persistent grid smaller
+// than the tile count is used as is): the number of per-block partials it writes
+inline int dslash_tile_blocks(int vh, const DslashTile &t) {
+    const int nb = dslash_blocks(vh * t.rg, t.block);
+    return (t.grid > 0 && t.grid < nb) ? t.grid : nb;
+}
 // largest block count any plan for (vh, nrhs) can use, per right-hand side
 size_t dslash_max_blocks(int vh);
 // plan (autotuned on first use when a probe is given and the stream is not capturing)
@@ -154,6 +166,8 @@ struct SolverCtrl {
     double brho[16], brho_prev[16], brho_new[16], bgamma[16], bpi[16], balpha[16], bbeta[16];
     double bpa_re[16], bpa_im[16], bpb[16], brmax2[16], bb2[16], br2_true[16];
     double balpha_buf[HISQ_MAX_GRAD_BUFFER][16];
+    double bc[16], bnc[16];  // 4m^2 + shift of system j, and its negative
+    double btol2[16];        // tol_j^2
     int bactive[16];   // 1 while right-hand side j is still iterating
     int bdone[16];
     int bk[16];
@@ -198,6 +212,32 @@ hipError_t launch_bflush_x(char *x64, size_t stride64, const SpinorList &p, int 
 hipError_t launch_bru_convert(char *r_s, const char *r64, size_t stride64, const char *p, const char *ap,
                               const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs, int sf, int compute,
                               double *partial, Guard gd, hipStream_t st);
+
+// A block of independent CG solves (A + c_j) x_j = b_j sharing every Dslash
+// (at most 16).  x_j, b_j: canonical FP64 [vh][3] device fields (b_j may
+// repeat); x_j holds the initial guess on entry and the solution on exit.
+struct BatchedJob {
+    int nrhs;
+    double *x[16];
+    const double *b[16];
+    double c[16];
+    double tol[16];
+    const hisq_gauge *g64, *gs;
+    hisq_fmt fmt;
+    hisq_solver_params q;   // validated
+    void *ws;
+    size_t ws_bytes;
+    hipStream_t st;
+    SolverCtrl *h;          // pinned host copy of the control block
+    // results
+    long iters, rus, dsl, d64;
+    double alg;
+    int iters_j[16];
+    double resid0_j[16], resid_j[16];
+};
+bool batched_fmt_ok(const hisq_fmt &f);
+size_t batched_ws_bytes(const Geom &g, int nrhs, int sf, int nb);
+hisq_status batched_run(BatchedJob &J);
 
 // ---------------------------------------------------------------------------
 // library-owned per-device scratch for one-shot calls (reductions)

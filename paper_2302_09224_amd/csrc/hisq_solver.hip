@@ -326,10 +326,10 @@ struct Run {
         const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
         DslashArgs ps = dargs(gs, B->ts, B->rs, 1);
         plan_s = dslash_plan(fmt, g, 1, &ps, st);
-        nb_s = dslash_blocks(g.vh * plan_s.tile[0].rg, plan_s.tile[0].block);
+        nb_s = dslash_tile_blocks(g.vh, plan_s.tile[0]);
         DslashArgs p64 = dargs(g64, B->t64, B->x64, 1);
         plan_64 = dslash_plan(f64, g, 1, &p64, st);
-        nb_64 = dslash_blocks(g.vh * plan_64.tile[0].rg, plan_64.tile[0].block);
+        nb_64 = dslash_tile_blocks(g.vh, plan_64.tile[0]);
     }
 
     DslashArgs dargs(const hisq_gauge *gg, char *out, const char *in, int parity) const {
@@ -423,7 +423,7 @@ struct Run {
                            nb_64);
         HISQ_TRY_HIP(hipGetLastError());
         dslash_f64 += 2;
-        alg_bytes += 2.0 * vh * (16.0 * 144 + 2 * 48) + 2.0 * vh * 48;
+        alg_bytes += 2.0 * vh * (dslash_link_bytes(g64) + 2 * 48) + 2.0 * vh * 48;
         return HISQ_OK;
     }
 
@@ -480,8 +480,8 @@ struct Run {
     }
 
     double iter_bytes() const {
-        const double bs = spinor_site_bytes(fmt.spinor), bg = gauge_matrix_bytes(fmt.gauge);
-        double it = 2.0 * (16.0 * bg + 2.0 * bs) + bs  // two Dslash + xpay operand
+        const double bs = spinor_site_bytes(fmt.spinor), bl = dslash_link_bytes(gs);
+        double it = 2.0 * (bl + 2.0 * bs) + bs         // two Dslash + xpay operand
                     + 3.0 * bs                           // r update
                     + 3.0 * bs                           // p update
                     + (nb * bs + 96.0) / nb;             // buffered FP64 solution update
@@ -564,7 +564,25 @@ hisq_status check_params(const hisq_solver_params *p, hisq_solver_params *out) {
     if (out->grad_buffer < 1 || out->grad_buffer > HISQ_MAX_GRAD_BUFFER)
         return set_error(HISQ_EINVAL, "grad_buffer must be in [1,%d]", HISQ_MAX_GRAD_BUFFER);
     if (out->poll_every <= 0) out->poll_every = d.poll_every;
+    if (out->batch_refine != 0 && out->batch_refine != 1) return set_error(HISQ_EINVAL, "batch_refine must be 0 or 1");
     return HISQ_OK;
+}
+
+// multi-shift workspace: the solver buffers, then (batched refinement) the
+// buffers of a block of min(16, nshift-1) shifted systems
+struct MsLayout {
+    size_t solver, batched;
+    bool batch;
+};
+MsLayout ms_layout(const Geom &g, int nshift, const hisq_fmt &ms_fmt, const hisq_fmt &refine_fmt,
+                   const hisq_solver_params &q) {
+    MsLayout L;
+    const int bs = std::max(spinor_site_bytes(ms_fmt.spinor), spinor_site_bytes(refine_fmt.spinor));
+    L.solver = (carve_cg(nullptr, nullptr, g, bs, q.grad_buffer, nshift, spinor_site_bytes(ms_fmt.spinor),
+                         spinor_site_bytes(refine_fmt.spinor)) + 255) & ~(size_t)255;
+    L.batch = q.batch_refine && nshift > 1 && batched_fmt_ok(refine_fmt);
+    L.batched = L.batch ? batched_ws_bytes(g, std::min(16, nshift - 1), refine_fmt.spinor, q.grad_buffer) : 0;
+    return L;
 }
 
 int chunk_of(const hisq_solver_params &p) {
@@ -650,6 +668,7 @@ extern "C" void hisq_solver_params_default(hisq_solver_params *p) {
     p->poll_every = 32;
     p->use_graph = 1;
     p->shift_floor = 0.0;
+    p->batch_refine = 1;
 }
 
 extern "C" size_t hisq_cg_workspace_bytes(const int dims[4], hisq_fmt sloppy, const hisq_solver_params *p) {
@@ -725,10 +744,8 @@ extern "C" size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift,
     if (nshift < 1 || nshift > HISQ_MAX_SHIFTS) return 0;
     hisq_solver_params q;
     if (check_params(p, &q) != HISQ_OK) return 0;
-    const Geom g = make_geom(dims);
-    const int bs = std::max(spinor_site_bytes(ms_fmt.spinor), spinor_site_bytes(refine_fmt.spinor));
-    return carve_cg(nullptr, nullptr, g, bs, q.grad_buffer, nshift, spinor_site_bytes(ms_fmt.spinor),
-                    spinor_site_bytes(refine_fmt.spinor));
+    const MsLayout L = ms_layout(make_geom(dims), nshift, ms_fmt, refine_fmt, q);
+    return L.solver + L.batched;
 }
 
 extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *b, const double *shifts, int nshift,
@@ -762,10 +779,12 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
     HISQ_TRY(check_params(p, &q));
     const Geom g = make_geom(dims);
     const int bs = std::max(spinor_site_bytes(ms_fmt.spinor), spinor_site_bytes(refine_fmt.spinor));
+    const MsLayout L = ms_layout(g, nshift, ms_fmt, refine_fmt, q);
+    if (ws_bytes < L.solver + L.batched)
+        return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.solver + L.batched);
     CgBuffers B;
-    const size_t need = carve_cg(&B, (char *)ws, g, bs, q.grad_buffer, nshift, spinor_site_bytes(ms_fmt.spinor),
-                                 spinor_site_bytes(refine_fmt.spinor));
-    if (ws_bytes < need) return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    carve_cg(&B, (char *)ws, g, bs, q.grad_buffer, nshift, spinor_site_bytes(ms_fmt.spinor),
+             spinor_site_bytes(refine_fmt.spinor));
     Entry E;
     HISQ_TRY(E.begin(stream));
     hipStream_t s_ = E.ds->stream;
@@ -840,7 +859,8 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
     }
 
     // ---- refinement (refine_fmt): base first keeping its gradient vector, then each shift ----
-    for (int i = 0; i < nshift && status == HISQ_OK; i++) {
+    // (batched: the shifted systems together, every Dslash shared by up to 16 of them)
+    for (int i = 0; i < (L.batch ? 1 : nshift) && status == HISQ_OK; i++) {
         Run R;
         R.g = g;
         R.vh = g.vh;
@@ -875,6 +895,39 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         st->dslash_f64 += (int)R.dslash_f64;
         st->alg_bytes += R.alg_bytes;
         HISQ_TRY_HIP(launch_spinor_unpack(x[i], Bi.x64, g.vh, SF_F64, s_));
+    }
+    if (L.batch && status == HISQ_OK) {
+        // the multi-shift solutions are the initial guesses (clean restarts from them)
+        for (int i = 1; i < nshift; i++) HISQ_TRY_HIP(launch_spinor_unpack(x[i], B.xs[i], g.vh, SF_F64, s_));
+        for (int i0 = 1; i0 < nshift && status == HISQ_OK; i0 += 16) {
+            BatchedJob J;
+            memset(&J, 0, sizeof(J));
+            J.nrhs = std::min(16, nshift - i0);
+            for (int j = 0; j < J.nrhs; j++) {
+                J.x[j] = x[i0 + j];
+                J.b[j] = b;
+                J.c[j] = m2 + shifts[i0 + j];
+                J.tol[j] = tol[i0 + j];
+            }
+            J.g64 = g64;
+            J.gs = g_ref;
+            J.fmt = refine_fmt;
+            J.q = q;
+            J.ws = (char *)ws + L.solver;
+            J.ws_bytes = L.batched;
+            J.st = s_;
+            J.h = h;
+            status = batched_run(J);
+            for (int j = 0; j < J.nrhs; j++) {
+                st->shift_resid_ms[i0 + j] = J.resid0_j[j];
+                st->refine_iters[i0 + j] = J.iters_j[j];
+                st->shift_resid[i0 + j] = J.resid_j[j];
+            }
+            st->reliable_updates += (int)J.rus;
+            st->dslash_sloppy += (int)J.dsl;
+            st->dslash_f64 += (int)J.d64;
+            st->alg_bytes += J.alg;
+        }
     }
     hisq_status s2 = E.end();
     if (status == HISQ_OK) status = s2;

@@ -54,7 +54,7 @@ RECON_18, RECON_12 = 18, 12
 class hisq_solver_params(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("maxiter", ctypes.c_int), ("grad_buffer", ctypes.c_int),
                 ("pr_beta", ctypes.c_int), ("reproject", ctypes.c_int), ("poll_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("shift_floor", ctypes.c_double)]
+                ("use_graph", ctypes.c_int), ("shift_floor", ctypes.c_double), ("batch_refine", ctypes.c_int)]
 
 
 class hisq_solver_stats(ctypes.Structure):
@@ -137,6 +137,8 @@ def load():
         "hisq_last_error": (ctypes.c_char_p, []),
         "hisq_version": (ctypes.c_char_p, []),
         "hisq_tune_report": (sz, [ctypes.c_char_p, sz]),
+        "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i]),
+        "hisq_tune_clear": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -289,6 +291,16 @@ def hisq_last_error():
     return load().hisq_last_error().decode()
 
 
+def hisq_tune_set(f, dims, rhs_block, nr, rg, stage, block, grid, long_recon=RECON_18):
+    f = fmt(f) if isinstance(f, (str, tuple)) else f
+    _check(load().hisq_tune_set(f, _dims(dims), int(long_recon), int(rhs_block), int(nr), int(rg), int(stage),
+                                int(block), int(grid)), "hisq_tune_set")
+
+
+def hisq_tune_clear():
+    load().hisq_tune_clear()
+
+
 def hisq_tune_report():
     lib = load()
     n = lib.hisq_tune_report(None, 0)
@@ -353,7 +365,10 @@ def dslash(packed_in, gauge: PackedGauge, parity, f, stream=None):
 
 def _solver_params(**kw):
     p = hisq_solver_params_default()
+    names = {f[0] for f in hisq_solver_params._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver parameter {k!r}")
         setattr(p, k, v)
     return p
 

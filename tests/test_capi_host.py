@@ -54,6 +54,18 @@ def test_sizes(hisq):
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("half"), p) > 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(2, 1, 32), p) == 0   # unsupported triplet
     assert hisq.hisq_multishift_workspace_bytes(dims, 33, hisq.fmt("single"), hisq.fmt("half"), p) == 0
+    assert p.batch_refine == 1
+    wb = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
+    p.batch_refine = 0
+    ws = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
+    assert wb > ws > 0                                           # room for a block of 11 shifted systems
+    # refinement in FIX32/INT30/FP32 has no batched form: no extra room
+    p.batch_refine = 1
+    a = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
+    p.batch_refine = 0
+    assert a == hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
+    p.batch_refine = 2
+    assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == 0
 
 
 def test_argument_errors(hisq):
@@ -81,3 +93,28 @@ def test_argument_errors(hisq):
     assert lib.hisq_gauge_pack(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, None) == -1
     dims = (ctypes.c_int * 4)(4, 4, 4, 4)
     assert lib.hisq_gauge_pack_recon(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, 9, None) == -1
+
+
+def test_tune_set_validation(hisq):
+    dims = (8, 8, 8, 16)
+    hisq.hisq_tune_clear()
+    hisq.hisq_tune_set("half", dims, 1, 1, 1, 4, 128, 0)
+    hisq.hisq_tune_set("half", dims, 1, 1, 1, 2, 128, 0, long_recon=12)
+    hisq.hisq_tune_set("double", dims, 4, 2, 2, 1, 256, 2048)
+    rep = hisq.hisq_tune_report()
+    assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048" in rep
+    assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0" in rep
+    bad = [("half", dims, 3, 1, 3, 1, 256, 0),          # block of 3 right-hand sides
+           ("half", dims, 4, 2, 1, 1, 256, 0),          # nr*rg != block
+           ("half", dims, 1, 1, 1, 3, 256, 0),          # stage
+           ("half", dims, 2, 2, 1, 2, 256, 0),          # stages only with one right-hand side per lane
+           ("half", dims, 1, 1, 1, 1, 192, 0),          # block size
+           ("half", dims, 1, 1, 1, 1, 256, 12),         # grid not a multiple of 8
+           ("int30_fp32", dims, 2, 1, 2, 1, 256, 0),    # no batched form
+           ("half", (8, 8, 8, 7), 1, 1, 1, 1, 256, 0),  # odd extent
+           ("half", dims, 1, 1, 1, 1, 256, 0, 9)]       # long-link storage
+    for args in bad:
+        with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
+            hisq.hisq_tune_set(*args)
+    hisq.hisq_tune_clear()
+    assert hisq.hisq_tune_report() == ""

@@ -32,6 +32,35 @@ HBM_PEAK_GBS = 8000.0
 FLOP_PER_SITE = 1146
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_int30_r12_48x48x48x96_counters.txt")
+COUNTER_SOURCES = ["hisq_dslash_kernels.h", "hisq_device.h", "hisq_dslash_t_int30.hip"]
+
+
+def counter_traffic(kernel, dims, recon):
+    """HBM bytes per launch of the dominant Dslash from the committed rocprofv3
+    counter passes (FETCH_SIZE + WRITE_SIZE, calibrated with a 1 GiB copy), or
+    None when that file covers another kernel or its sources have changed."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    want = f"{kernel} long_recon {recon} lattice {'x'.join(map(str, dims))}"
+    if kv.get("kernel") != want:
+        return None
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_09224_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != kv.get("kernel_sha256"):
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -93,7 +122,10 @@ def main():
     ap.add_argument("--ref", type=str, default="int20")
     ap.add_argument("--recon", type=int, default=12, choices=(12, 18),
                     help="long-link storage of the solver's low-precision operators (12: two rows)")
+    ap.add_argument("--batch-refine", type=int, default=1, choices=(0, 1),
+                    help="refine the shifted systems together (1) or one after another (0)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-alt", action="store_true", help="skip the double-single-half mixed solve")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
@@ -179,23 +211,38 @@ def main():
     batched = None
     if args.batched:
         batched = bench_batched(args, hisq, inputs, torch, dev)
-    tuning = hisq.hisq_tune_report().strip().splitlines()
-    for line in tuning:
-        log(f"[bench] tuned: {line}")
     if args.kernels_only:
-        print(json.dumps(dict(kernels=kernels, batched=batched, tuning=tuning)))
+        tuning = hisq.hisq_tune_report().strip().splitlines()
+        print(json.dumps(dict(kernels=kernels, batched=batched, tuning=tuning, config={"lattice": list(dims)})))
         return
     gauges.clear()
     torch.cuda.empty_cache()
 
     # ---------------- the timed step ----------------
-    def step():
+    def solve_once(ms, ref, **kw):
+        """pack the links the solve needs (FP64 + its two triplets) and run it"""
+        f_ms, f_ref = hisq.fmt(ms), hisq.fmt(ref)
         g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
-        gms = hisq.pack_gauge(fat, lng, dims, fms.gauge, long_recon=args.recon)
-        gref = gms if fref.gauge == fms.gauge else hisq.pack_gauge(fat, lng, dims, fref.gauge, long_recon=args.recon)
-        xs, st = hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=args.ms,
-                                          ref_fmt=args.ref)
-        return xs, st
+        gms = hisq.pack_gauge(fat, lng, dims, f_ms.gauge, long_recon=args.recon)
+        gref = gms if f_ref.gauge == f_ms.gauge else hisq.pack_gauge(fat, lng, dims, f_ref.gauge,
+                                                                     long_recon=args.recon)
+        return hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=ms, ref_fmt=ref, **kw)
+
+    def step():
+        return solve_once(args.ms, args.ref, batch_refine=args.batch_refine)
+
+    def timed_once(ms, ref, **kw):
+        """one warm-up solve (launch shapes of new keys are tuned there), then one timed"""
+        xw, _ = solve_once(ms, ref, **kw)
+        del xw
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xw, sw = solve_once(ms, ref, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        del xw
+        torch.cuda.empty_cache()
+        return dt, sw
 
     for w in range(args.warmup):
         log(f"[bench] warmup {w + 1}/{args.warmup}")
@@ -228,31 +275,36 @@ def main():
     last = stats[-1]
     resid_ok = all(r <= t * (1 + 1e-6) for r, t in zip(last["shift_resid"], tols))
 
+    tuning = hisq.hisq_tune_report().strip().splitlines()
+    for line in tuning:
+        log(f"[bench] tuned: {line}")
+
     # ---------------- FP64 GPU multi-shift comparator ----------------
     fp64 = None
     if not args.no_fp64:
-        log("[bench] FP64 multi-shift comparator")
+        log("[bench] FP64 multi-shift comparator (all-FP64 multi-shift CG, no reliable updates)")
         del xs
         torch.cuda.empty_cache()
-        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
-        g64s = g64 if args.recon == 18 else hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=args.recon)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        xs64, st64 = hisq.multishift_cg_solve(b, shifts, tols, g64, g64s, g64s, args.mass, ms_fmt="double",
-                                              ref_fmt="double", delta=0.0)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
+        t64, st64 = timed_once("double", "double", delta=0.0)
         fp64 = dict(seconds=round(t64, 3), iters=st64["iters"], refine_iters=st64["refine_iters"],
                     resid_max=max(st64["shift_resid"]), speedup_mixed=round(t64 / (ms_per_step / 1e3), 3))
         log(f"[bench]   FP64: {t64:.2f}s, iters {st64['iters']}, refine {st64['refine_iters']}")
-        del xs64, g64, g64s
-        torch.cuda.empty_cache()
+    alt = None
+    if not args.no_alt:
+        log("[bench] mixed double-single-half multi-shift")
+        ta, sa = timed_once("single", "half", batch_refine=args.batch_refine)
+        alt = dict(ms_triplet="f32/f32/fp32", refine_triplet="fix16/half16/fp32", seconds=round(ta, 3),
+                   ms_iters=sa["iters"], refine_iters=sa["refine_iters"], resid_max=max(sa["shift_resid"]),
+                   resid_after_ms=[float(f"{r:.3g}") for r in sa["shift_resid_ms"]])
+        log(f"[bench]   double-single-half: {ta:.2f}s, ms iters {sa['iters']}, refine {sa['refine_iters']}")
 
     # ---------------- roofline of the dominant kernel ----------------
     dom = args.ms if args.recon == 18 else f"{args.ms}_r12"
     kd = kernels[dom]
+    traffic = counter_traffic(f"k_dslash<{kd['triplet']}>", dims, args.recon)
     roofline = dict(bound="hbm", achieved=kd["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(kd["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(kd["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                    traffic_over_alg=round(traffic / kd["alg_bytes"], 3) if traffic else None,
                     kernel=f"k_dslash<{kd['triplet']}>", alg_bytes_per_launch=kd["alg_bytes"],
                     us_per_launch=kd["us"])
 
@@ -304,14 +356,16 @@ def main():
         "config": {"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "lattice": list(dims),
                    "mass": args.mass, "shifts": [float(f"{s:.4g}") for s in shifts], "tol": args.tol,
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
+                   "batch_refine": args.batch_refine,
                    "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],
                        "resid_after_ms": [float(f"{r:.3g}") for r in last["shift_resid_ms"]],
                        "resid": [float(f"{r:.3g}") for r in last["shift_resid"]], "all_converged": resid_ok,
-                       "step_alg_bytes": step_bytes, "fp64_gpu": fp64},
+                       "step_alg_bytes": step_bytes, "fp64_gpu": fp64, "double_single_half": alt},
         "kernels": kernels,
         "batched": batched,
+        "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

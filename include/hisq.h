@@ -291,12 +291,15 @@ size_t hisq_tune_report(char *buf, size_t len);
  * rhs_block right-hand sides (1, 2, 4, 8 or 16), replacing what the
  * autotuner chose or would choose: nr right-hand sides per lane and rg lanes
  * per site (nr * rg == rhs_block, both powers of two), stage hops per load
- * stage (1, 2, 4 or 8 when nr == 1; 1 otherwise), block threads (128 or 256)
- * and grid blocks (0: one tile of lanes per block; otherwise a multiple of 8,
- * a persistent grid when smaller than the tile count).  For reproducible
- * launch shapes and for tests.  HISQ_EINVAL for an unsupported shape. */
+ * stage (1, 2, 4 or 8 when nr == 1; 1 otherwise), block threads (128 or 256),
+ * grid blocks (0: one tile of lanes per block; otherwise a multiple of 8,
+ * a persistent grid when smaller than the tile count) and sweep, the order in
+ * which the blocks take the tiles of lanes (0: the blocks of XCD k, b % 8 ==
+ * k, take the k-th eighth of the lattice; 1: consecutive tiles on consecutive
+ * blocks, so all XCDs work on neighbouring sites).  For reproducible launch
+ * shapes and for tests.  HISQ_EINVAL for an unsupported shape. */
 hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
-                          int stage, int block, int grid);
+                          int stage, int block, int grid, int sweep);
 
 /* Forget every tuned or fixed launch shape (the next application tunes again). */
 void hisq_tune_clear(void);

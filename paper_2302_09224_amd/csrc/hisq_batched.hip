@@ -266,11 +266,13 @@ struct BRun {
         const Guard gns{&c->stop, j, 0}, gsn{&c->stop, j, 1};
         DslashArgs A = dargs(gs, fmt, B->ts, B->p[jb], 1);
         A.guard = gns;
+        A.cactive = c->bactive;   // stopped systems cost no Dslash work
         HISQ_TRY_HIP(launch_dslash(A, fmt, plan_s, st, nullptr));
         DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
         Bk.acol = c->bc;
+        Bk.cactive = c->bactive;
         Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
         Bk.pstride = nl_s.pstride;

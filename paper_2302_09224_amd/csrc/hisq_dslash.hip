@@ -3,6 +3,7 @@
 // are instantiated in hisq_dslash_t_*.hip (one translation unit per triplet).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -59,24 +60,26 @@ std::vector<DslashTile> candidates(int c, bool batched_ok) {
     if (c == 1) {
         for (int st : {1, 2, 4, 8})
             for (int blk : {128, 256})
-                for (int per_cu : {0, 4, 8}) v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk)});
+                for (int per_cu : {0, 4, 8})
+                    for (int sw : {0, 1}) v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk), sw});
         return v;
     }
     if (!batched_ok) return v;
     for (int nr : {1, 2, 4, 8, 16}) {
         if (nr > c) break;
         const int rg = c / nr;
-        for (int grid : {0, 2048}) {
-            v.push_back(DslashTile{nr, rg, 1, 256, grid});
-            if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid});
-        }
+        for (int grid : {0, 2048})
+            for (int sw : {0, 1}) {
+                v.push_back(DslashTile{nr, rg, 1, 256, grid, sw});
+                if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid, sw});
+            }
     }
     return v;
 }
 
 DslashTile default_tile(int c) {
-    if (c == 1) return DslashTile{1, 1, 8, 256, 0};
-    return DslashTile{1, c, 1, 256, 0};
+    if (c == 1) return DslashTile{1, 1, 8, 256, 0, 0};
+    return DslashTile{1, c, 1, 256, 0, 0};
 }
 
 // time one shape on the probe arguments (pure Dslash, idempotent: no xpay, no reduction)
@@ -118,7 +121,7 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     p.x = p.y = nullptr;
     p.red = RED_NONE;
     p.guard = Guard{nullptr, 0, 0};
-    p.nrhs = c;
+    p.nrhs = std::max(1, std::min(c, probe->nrhs));   // only the columns the probe's buffers hold
     float tbest = -1.f;
     for (const DslashTile &t : candidates(c, batched_ok)) {
         const float ms = time_tile(p, f, t, st);
@@ -141,17 +144,14 @@ int dslash_blocks(int n, int block) {
 size_t dslash_max_blocks(int vh) { return (size_t)dslash_blocks(vh * 16, 128); }
 
 DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st) {
+    // one launch: the block of right-hand sides padded to a power of two (the
+    // padding columns are masked in the kernel), so every link is read once
     DslashPlan plan;
-    plan.n = 0;
-    int done = 0;
-    while (done < nrhs && plan.n < 5) {
-        int c = 16;
-        while (c > nrhs - done) c >>= 1;
-        plan.rhs0[plan.n] = done;
-        plan.tile[plan.n] = tile_for(f, g, c, probe, st);
-        plan.n++;
-        done += c;
-    }
+    int c = 1;
+    while (c < nrhs && c < 16) c <<= 1;
+    plan.n = 1;
+    plan.rhs0[0] = 0;
+    plan.tile[0] = tile_for(f, g, c, probe, st);
     return plan;
 }
 
@@ -170,7 +170,7 @@ hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPla
 }  // namespace hisq
 
 extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
-                                     int stage, int block, int grid) {
+                                     int stage, int block, int grid, int sweep) {
     using namespace hisq;
     if (!dims || !dims_ok(dims) || !triplet_ok(fmt)) return set_error(HISQ_EINVAL, "hisq_tune_set: bad dims or triplet");
     if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
@@ -180,14 +180,14 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
     if (rhs_block > 1 && fmt.gauge == HISQ_GAUGE_FIX32 && fmt.compute == 32)
         return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
     bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
-    ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0;
+    ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);
     ok = ok && (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8) : stage == 1);
     if (!ok)
-        return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d", nr, rg,
-                         stage, block, grid);
+        return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d",
+                         nr, rg, stage, block, grid, sweep);
     const TuneKey key{tune_id(fmt, long_recon), dims[0], dims[1], dims[2], dims[3], rhs_block};
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid}, -1.f);
+    g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid, sweep}, -1.f);
     return HISQ_OK;
 }
 
@@ -206,10 +206,10 @@ extern "C" size_t hisq_tune_report(char *buf, size_t len) {
             const auto &t = kv.second.first;
             snprintf(line, sizeof(line),
                      "triplet %03d recon %d lattice %dx%dx%dx%d rhs-block %d: nr %d rg %d stage %d block %d grid %d "
-                     "(%.1f us)\n",
+                     "sweep %d (%.1f us)\n",
                      std::get<0>(k) / 100, std::get<0>(k) % 100, std::get<1>(k), std::get<2>(k), std::get<3>(k),
                      std::get<4>(k), std::get<5>(k),
-                     t.nr, t.rg, t.stage, t.block, t.grid, kv.second.second * 1e3);
+                     t.nr, t.rg, t.stage, t.block, t.grid, t.sweep, kv.second.second * 1e3);
             s += line;
         }
     }

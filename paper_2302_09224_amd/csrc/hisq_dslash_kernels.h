@@ -379,7 +379,7 @@ __device__ __forceinline__ int hop_site_rt(const Geom &g, const Coords &c, int s
 // standalone applications use the unguarded instantiation.
 // LR: 18 = long links stored in full, 12 = two rows + reconstruction
 template <int GF, int SF, class R, int NR, int STAGE, bool RED, bool GUARD, int LR>
-__global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, FastDiv drg) {
+__global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, FastDiv drg, int sweep) {
     __shared__ double lds[64];
     if (GUARD && !A.guard.pass()) return;
     const Geom g = A.g;
@@ -389,27 +389,42 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     for (int j = 0; j < NR; j++) red[j] = 0.0;
     // xpay coefficient of each of the lane's right-hand sides (rg divides
     // blockDim, so a lane keeps its group in every tile); read once, up front
+    // The lane's right-hand sides rc..rc+NR-1 (rg divides blockDim, so a lane
+    // keeps its group in every tile).  Those at or beyond ncol (a block padded
+    // to a power of two) and those marked inactive are neither read nor written.
+    const int ncol = A.nrhs > 1 ? A.nrhs : 1;
+    const int rc = rhs0 + (int)(threadIdx.x & (unsigned)(rg - 1)) * NR;
+    unsigned live = 0;
+#pragma unroll
+    for (int j = 0; j < NR; j++)
+        if (rc + j < ncol && (!A.cactive || A.cactive[rc + j])) live |= 1u << j;
+    // xpay coefficient of each of the lane's right-hand sides, read once
     R acoef[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) acoef[j] = (R)A.a;
-    if (A.acol) {
-        const int rc = rhs0 + (int)(threadIdx.x & (unsigned)(rg - 1)) * NR;
-#pragma unroll
-        for (int j = 0; j < NR; j++) acoef[j] = (R)A.acol[rc + j];
-    }
-    // Tiles of blockDim lanes; XCD k (blocks b with b % 8 == k) sweeps the
-    // contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
-    // gridDim/8 blocks taking every (gridDim/8)-th tile: one tile per block when
-    // the grid covers the lattice, a persistent grid-stride sweep otherwise.
+    for (int j = 0; j < NR; j++) acoef[j] = (A.acol && ((live >> j) & 1u)) ? (R)A.acol[rc + j] : (R)A.a;
+    // Tiles of blockDim lanes.  sweep 0: XCD k (blocks b with b % 8 == k) sweeps
+    // the contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
+    // gridDim/8 blocks taking every (gridDim/8)-th tile.  sweep 1: block b takes
+    // tiles b, b + gridDim, ...  One tile per block when the grid covers the
+    // lattice, a persistent grid-stride sweep otherwise.
     const int ntile = (int)(((long long)g.vh * rg + blockDim.x - 1) / blockDim.x);
-    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7;
-    const int tend = (int)(((long long)ntile * (xcd + 1)) >> 3);
-    for (int tile = (int)(((long long)ntile * xcd) >> 3) + (int)(blockIdx.x >> 3); tile < tend; tile += per) {
+    int tile0, tend, tstep;
+    if (sweep == 0) {
+        const int xcd = blockIdx.x & 7;
+        tile0 = (int)(((long long)ntile * xcd) >> 3) + (int)(blockIdx.x >> 3);
+        tend = (int)(((long long)ntile * (xcd + 1)) >> 3);
+        tstep = gridDim.x >> 3;
+    } else {
+        tile0 = blockIdx.x;
+        tend = ntile;
+        tstep = gridDim.x;
+    }
+    for (int tile = tile0; tile < tend; tile += tstep) {
     const int tid = tile * blockDim.x + threadIdx.x;
     const int s = rg == 1 ? tid : fdiv(tid, drg);
     const int grp = tid - s * rg;
-    const int r0 = rhs0 + grp * NR;
-    if (s < g.vh) {
+    const int r0 = rhs0 + grp * NR;   // == rc
+    if (s < g.vh && live) {
         const size_t vh = (size_t)g.vh;
         const int p = A.parity, q = 1 - p;
         const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
@@ -419,7 +434,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         CVec<R> acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
-        if (NR > 1) {
+        if (NR > 1 && STAGE == 1) {
             // several right-hand sides per lane: one hop at a time (bounded registers)
             const Coords c = coords_of(g, s, p);
 #pragma unroll 1
@@ -434,27 +449,29 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                     const int tl = (mu == 3 && (h & 1)) ? wrap_add(c.t, -3, g.T) : c.t;
                     const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
 #pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
+                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
                     U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
                 } else {
                     const char *field = (h & 2) ? A.lng : A.fat;
                     const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = spin_load<SF>(in + j * fs, vh, ss);
+                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
                     U = link_decode<R>(Lr, (h & 2) ? gl : gf);
                 }
                 if (h & 1) {
 #pragma unroll
-                    for (int j = 0; j < NR; j++) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
+                    for (int j = 0; j < NR; j++)
+                        if ((live >> j) & 1u) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
                 } else {
 #pragma unroll
-                    for (int j = 0; j < NR; j++) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
+                    for (int j = 0; j < NR; j++)
+                        if ((live >> j) & 1u) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
                 }
             }
         }
         const Nbrs n = neighbours(g, s, p);
 #pragma unroll
-        for (int h0 = 0; h0 < (NR > 1 ? 0 : 16); h0 += STAGE) {
+        for (int h0 = 0; h0 < ((NR > 1 && STAGE == 1) ? 0 : 16); h0 += STAGE) {
             LinkRaw<GF> L[STAGE];
             LinkRaw12<GF> L12[STAGE];
             SpinRaw<SF> P[STAGE][NR];
@@ -469,7 +486,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                 else
                     L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-                for (int j = 0; j < NR; j++) P[i][j] = spin_load<SF>(in + j * fs, vh, ss);
+                for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -480,6 +497,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                                      : link_decode<R>(L[i], (h & 2) ? gl : gf);
 #pragma unroll
                 for (int j = 0; j < NR; j++) {
+                    if (NR > 1 && !((live >> j) & 1u)) continue;
                     const CVec<R> v = spin_decode<R>(P[i][j]);
                     if (h & 1)
                         mdv_sub(acc[j], U, v);
@@ -491,6 +509,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         const R b = (R)A.b, cc = (R)A.c;
 #pragma unroll
         for (int j = 0; j < NR; j++) {
+            if (!((live >> j) & 1u)) continue;
             const size_t off = (size_t)(r0 + j) * fs;
             const R a = acoef[j];
             CVec<R> xv;
@@ -547,7 +566,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         }
         __syncthreads();
         const int k = threadIdx.x;
-        if (k < rg * NR) {
+        if (k < rg * NR && rhs0 + k < ncol) {
             double v = 0.0;
             for (int ww = 0; ww < nw; ww++) v += lds[ww * rg * NR + k];
             A.partial[(size_t)(rhs0 + k) * A.pstride + blockIdx.x] = v;
@@ -560,24 +579,25 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 // ---------------------------------------------------------------------------
 
 template <int GF, int SF, class R, int NR, int STAGE>
-hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, hipStream_t st, int *nblocks) {
-    const int nb = dslash_tile_blocks(a.g.vh, DslashTile{NR, rg, STAGE, block, grid});
+hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, int sweep, hipStream_t st,
+                      int *nblocks) {
+    const int nb = dslash_tile_blocks(a.g.vh, DslashTile{NR, rg, STAGE, block, grid, sweep});
     if (nblocks) *nblocks = nb;
     const FastDiv drg = make_fastdiv((unsigned)rg);
     if (a.long_recon == 12) {
         if (a.red != RED_NONE)
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
         else if (a.guard.stop)
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
         else
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
     } else {
         if (a.red != RED_NONE)
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
         else if (a.guard.stop)
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
         else
-            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg);
+            hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 18>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
     }
     return hipGetLastError();
 }
@@ -587,21 +607,21 @@ hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid
 template <int GF, int SF, class R, bool BATCHED>
 hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nblocks) {
     if (t.rg < 1 || t.rg > 16 || (t.rg & (t.rg - 1)) || t.nr * t.rg > 16 || (t.block != 128 && t.block != 256) ||
-        t.grid < 0 || (t.grid & 7))
+        t.grid < 0 || (t.grid & 7) || (t.sweep != 0 && t.sweep != 1))
         return hipErrorInvalidValue;
     switch (t.nr * 100 + t.stage) {
-    case 101: return launch_cfg<GF, SF, R, 1, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-    case 102: return launch_cfg<GF, SF, R, 1, 2>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-    case 104: return launch_cfg<GF, SF, R, 1, 4>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-    case 108: return launch_cfg<GF, SF, R, 1, 8>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+    case 101: return launch_cfg<GF, SF, R, 1, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+    case 102: return launch_cfg<GF, SF, R, 1, 2>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+    case 104: return launch_cfg<GF, SF, R, 1, 4>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+    case 108: return launch_cfg<GF, SF, R, 1, 8>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     default: break;
     }
     if (BATCHED) {
         switch (t.nr * 100 + t.stage) {
-        case 201: return launch_cfg<GF, SF, R, 2, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-        case 401: return launch_cfg<GF, SF, R, 4, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-        case 801: return launch_cfg<GF, SF, R, 8, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
-        case 1601: return launch_cfg<GF, SF, R, 16, 1>(a, rhs0, t.rg, t.block, t.grid, st, nblocks);
+        case 201: return launch_cfg<GF, SF, R, 2, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 401: return launch_cfg<GF, SF, R, 4, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 801: return launch_cfg<GF, SF, R, 8, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 1601: return launch_cfg<GF, SF, R, 16, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
         default: break;
         }
     }

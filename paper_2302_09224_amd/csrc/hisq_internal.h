@@ -68,15 +68,19 @@ struct DslashArgs {
     int long_recon;       // 18: long links stored in full; 12: two rows, L = lcoef * phase * SU(3)
     double lcoef;
     const double *acol;   // optional (device): coefficient a of right-hand side j is acol[j]
+    const int *cactive;   // optional (device): right-hand side j is skipped (not read, not written) if !cactive[j]
 };
 
 // Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
 // sides of one site, `rg` adjacent lanes share a site (nr*rg right-hand sides
 // per launch), the 16 hops are loaded in stages of `stage`, `block` threads,
 // `grid` blocks (0: one tile of lanes per block; otherwise a persistent grid,
-// a multiple of 8, sweeping the tiles).
+// a multiple of 8, sweeping the tiles), `sweep` the order of the tiles: 0 =
+// XCD k (blocks b with b % 8 == k) takes the k-th eighth of the lattice, 1 =
+// consecutive tiles on consecutive blocks (the eight XCDs advance together,
+// sharing the neighbours they read in the memory-side cache).
 struct DslashTile {
-    int nr, rg, stage, block, grid;
+    int nr, rg, stage, block, grid, sweep;
 };
 
 // A whole application: launches covering right-hand sides [rhs0[i], rhs0[i]+nr*rg)

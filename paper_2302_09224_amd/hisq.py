@@ -137,7 +137,7 @@ def load():
         "hisq_last_error": (ctypes.c_char_p, []),
         "hisq_version": (ctypes.c_char_p, []),
         "hisq_tune_report": (sz, [ctypes.c_char_p, sz]),
-        "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i]),
+        "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
         "hisq_tune_clear": (None, []),
     }
     for name, (res, args) in sig.items():
@@ -291,10 +291,10 @@ def hisq_last_error():
     return load().hisq_last_error().decode()
 
 
-def hisq_tune_set(f, dims, rhs_block, nr, rg, stage, block, grid, long_recon=RECON_18):
+def hisq_tune_set(f, dims, rhs_block, nr, rg, stage, block, grid, sweep=0, long_recon=RECON_18):
     f = fmt(f) if isinstance(f, (str, tuple)) else f
     _check(load().hisq_tune_set(f, _dims(dims), int(long_recon), int(rhs_block), int(nr), int(rg), int(stage),
-                                int(block), int(grid)), "hisq_tune_set")
+                                int(block), int(grid), int(sweep)), "hisq_tune_set")
 
 
 def hisq_tune_clear():

@@ -100,10 +100,10 @@ def test_tune_set_validation(hisq):
     hisq.hisq_tune_clear()
     hisq.hisq_tune_set("half", dims, 1, 1, 1, 4, 128, 0)
     hisq.hisq_tune_set("half", dims, 1, 1, 1, 2, 128, 0, long_recon=12)
-    hisq.hisq_tune_set("double", dims, 4, 2, 2, 1, 256, 2048)
+    hisq.hisq_tune_set("double", dims, 4, 2, 2, 1, 256, 2048, sweep=1)
     rep = hisq.hisq_tune_report()
-    assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048" in rep
-    assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0" in rep
+    assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
+    assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0 sweep 0" in rep
     bad = [("half", dims, 3, 1, 3, 1, 256, 0),          # block of 3 right-hand sides
            ("half", dims, 4, 2, 1, 1, 256, 0),          # nr*rg != block
            ("half", dims, 1, 1, 1, 3, 256, 0),          # stage
@@ -112,7 +112,8 @@ def test_tune_set_validation(hisq):
            ("half", dims, 1, 1, 1, 1, 256, 12),         # grid not a multiple of 8
            ("int30_fp32", dims, 2, 1, 2, 1, 256, 0),    # no batched form
            ("half", (8, 8, 8, 7), 1, 1, 1, 1, 256, 0),  # odd extent
-           ("half", dims, 1, 1, 1, 1, 256, 0, 9)]       # long-link storage
+           ("half", dims, 1, 1, 1, 1, 256, 0, 2),       # sweep order
+           ("half", dims, 1, 1, 1, 1, 256, 0, 0, 9)]    # long-link storage
     for args in bad:
         with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
             hisq.hisq_tune_set(*args)

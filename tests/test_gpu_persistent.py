@@ -22,9 +22,9 @@ def persistent():
     hisq.hisq_tune_clear()
     for name in ("double", "single", "half", "int20", "int30"):
         for recon in (18, 12):
-            hisq.hisq_tune_set(name, DIMS, 1, 1, 1, 8, 256, 8, long_recon=recon)
+            hisq.hisq_tune_set(name, DIMS, 1, 1, 1, 8, 256, 8, sweep=recon % 2, long_recon=recon)
             for c in (2, 4, 8, 16):
-                hisq.hisq_tune_set(name, DIMS, c, 1, c, 1, 256, 8, long_recon=recon)
+                hisq.hisq_tune_set(name, DIMS, c, 1, c, 1, 256, 8, sweep=c % 3 % 2, long_recon=recon)
     yield hisq
     hisq.hisq_tune_clear()
 
@@ -50,9 +50,10 @@ def test_persistent_dslash_matches_tiled(persistent):
         pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), DIMS, f.gauge)
         pin = hisq.pack_spinor(torch.from_numpy(psi).cuda(), f.spinor)
         yp = hisq.dslash(pin, pg, 1, f).clone()
-        hisq.hisq_tune_set(name, DIMS, 1, 1, 1, 8, 256, 0)
-        yt = hisq.dslash(pin, pg, 1, f)
-        assert torch.equal(yp, yt), name           # same arithmetic per site, only the schedule differs
+        for grid, sweep in ((0, 0), (0, 1), (8, 1)):
+            hisq.hisq_tune_set(name, DIMS, 1, 1, 1, 8, 256, grid, sweep=sweep)
+            yt = hisq.dslash(pin, pg, 1, f)
+            assert torch.equal(yp, yt), (name, grid, sweep)   # same arithmetic per site, only the schedule differs
         hisq.hisq_tune_set(name, DIMS, 1, 1, 1, 8, 256, 8)
 
 

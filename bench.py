@@ -256,8 +256,9 @@ def main():
     for k in range(args.steps):
         xs, st = step()
         stats.append(st)
-        log(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.2f}s, ms iters {st['iters']}, "
-            f"refine {st['refine_iters']}, resid max {max(st['shift_resid']):.2e}")
+        log(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.2f}s (multi-shift {st['phase_seconds'][0]:.2f}, "
+            f"base refinement {st['phase_seconds'][1]:.2f}, shifted refinement {st['phase_seconds'][2]:.2f}), "
+            f"ms iters {st['iters']}, refine {st['refine_iters']}, resid max {max(st['shift_resid']):.2e}")
         if k + 1 < args.steps:
             del xs
     torch.cuda.synchronize()
@@ -287,6 +288,7 @@ def main():
         torch.cuda.empty_cache()
         t64, st64 = timed_once("double", "double", delta=0.0)
         fp64 = dict(seconds=round(t64, 3), iters=st64["iters"], refine_iters=st64["refine_iters"],
+                    phase_seconds=[round(v, 3) for v in st64["phase_seconds"]],
                     resid_max=max(st64["shift_resid"]), speedup_mixed=round(t64 / (ms_per_step / 1e3), 3))
         log(f"[bench]   FP64: {t64:.2f}s, iters {st64['iters']}, refine {st64['refine_iters']}")
     alt = None
@@ -294,6 +296,7 @@ def main():
         log("[bench] mixed double-single-half multi-shift")
         ta, sa = timed_once("single", "half", batch_refine=args.batch_refine)
         alt = dict(ms_triplet="f32/f32/fp32", refine_triplet="fix16/half16/fp32", seconds=round(ta, 3),
+                   phase_seconds=[round(v, 3) for v in sa["phase_seconds"]],
                    ms_iters=sa["iters"], refine_iters=sa["refine_iters"], resid_max=max(sa["shift_resid"]),
                    resid_after_ms=[float(f"{r:.3g}") for r in sa["shift_resid_ms"]])
         log(f"[bench]   double-single-half: {ta:.2f}s, ms iters {sa['iters']}, refine {sa['refine_iters']}")
@@ -359,6 +362,7 @@ def main():
                    "batch_refine": args.batch_refine,
                    "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
+                       "phase_seconds": [round(v, 3) for v in last["phase_seconds"]],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],
                        "resid_after_ms": [float(f"{r:.3g}") for r in last["shift_resid_ms"]],
                        "resid": [float(f"{r:.3g}") for r in last["shift_resid"]], "all_converged": resid_ok,

@@ -207,6 +207,8 @@ typedef struct {
     double shift_resid_ms[HISQ_MAX_SHIFTS];  /* true residual of shift i after the multi-shift phase */
     int refine_iters[HISQ_MAX_SHIFTS];       /* refinement CG iterations of shift i */
     double shift_resid[HISQ_MAX_SHIFTS];     /* final true residual of shift i */
+    double phase_seconds[3];                 /* multi-shift: wall time of the multi-shift phase, of the base's
+                                                refinement and of the shifted systems' refinement */
 } hisq_solver_stats;
 
 /* Default parameters: delta 0.1, maxiter 100000, grad_buffer 4, PR beta,
@@ -250,7 +252,7 @@ size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift, hisq_fmt m
  * its own tol_i (true residual): in ascending order, or (p->batch_refine,
  * the default, for refine triplets other than FIX32/INT30/FP32) in blocks of
  * up to 16 independent CGs sharing every Dslash (each the iteration of a
- * lone solve, except that a reliable update asked for by one is done for all).
+ * lone solve, with its own reliable updates).
  * x: (host) array of nshift (device) canonical complex128 [Vh][3] outputs.
  * shifts, tol: (host) arrays of nshift doubles, shifts strictly ascending,
  * shifts[0] >= 0 and 1 <= nshift <= HISQ_MAX_SHIFTS.
@@ -271,7 +273,9 @@ size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt slo
  * sides) that share every Dslash launch, so each link is loaded once per
  * application for the whole block (Sec. 1 "Block solvers").  x, b: (device)
  * nrhs consecutive canonical complex128 [Vh][3] fields.  Each right-hand side
- * converges to tol on its own; stats describe the slowest one.  1 <= nrhs <= 16. */
+ * converges to tol on its own, with its own reliable updates, and stops
+ * costing Dslash work once converged; stats describe the slowest one
+ * (shift_resid[j], refine_iters[j]: right-hand side j).  1 <= nrhs <= 16. */
 hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hisq_gauge *g64,
                                   const hisq_gauge *gs, double mass, double shift, double tol,
                                   hisq_fmt sloppy, const hisq_solver_params *p, void *ws,

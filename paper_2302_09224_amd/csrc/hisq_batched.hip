@@ -6,9 +6,12 @@
 // in the control block; the Dslash applies one load of each link matrix to all
 // nrhs spinors.  The iteration is the single-system one of hisq_solver.hip
 // (buffered FP64 solution, Polak-Ribiere beta, reliable updates with
-// re-projection) done for every j at once; a reliable update requested by any
-// right-hand side is performed for all of them (it is never harmful), and a
-// right-hand side whose true residual meets tol stops updating.
+// re-projection) done for every j at once.  When a right-hand side asks for a
+// reliable update (or its iterated residual meets tol) the block stops; only
+// the right-hand sides that asked compute their true residual (the FP64 Dslash
+// skips the others), replace r and re-project p, while the others take their
+// ordinary CG step; every buffered gradient is flushed.  A right-hand side
+// whose true residual meets tol stops updating and costs no more Dslash work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -102,15 +105,21 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
         c->bpa_im[j] = 0.0;
         c->bpb[j] = beta;
         c->brmax2[j] = fmax(c->brmax2[j], rn);
-        if (c->delta2 > 0.0 && rn < c->delta2 * c->brmax2[j]) reason = reason ? reason : STOP_RU;
-        if (rn <= c->btol2[j] * c->bb2[j]) reason = reason ? reason : STOP_CONV;
+        const bool ru = c->delta2 > 0.0 && rn < c->delta2 * c->brmax2[j];
+        const bool conv = rn <= c->btol2[j] * c->bb2[j];
+        if (ru) reason = reason ? reason : STOP_RU;
+        if (conv) reason = reason ? reason : STOP_CONV;
+        if (ru || conv) c->bru[j] = 1;
         c->brho_prev[j] = rho;
         c->brho[j] = rn;
     }
     if (threadIdx.x) return;
     const int k = c->k + 1;
     c->k = k;
-    if (reason == STOP_NONE && k >= c->maxiter) reason = STOP_MAXITER;
+    if (reason == STOP_NONE && k >= c->maxiter) {
+        reason = STOP_MAXITER;
+        for (int j = 0; j < nrhs; j++) c->bru[j] = c->bactive[j];   // report every true residual
+    }
     if (reason != STOP_NONE) {
         c->reason = reason;
         c->stop = gd.j;
@@ -124,12 +133,14 @@ __global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, NbList nl,
         double v[1];
         csum(partial + (size_t)j * nl.pstride, nl.nb[j], v, lds);
         if (threadIdx.x) continue;
-        const double r2 = v[0];
-        c->br2_true[j] = r2;
-        if (!__builtin_isfinite(r2)) c->breakdown = 1;
-        if (c->bactive[j] && r2 <= c->btol2[j] * c->bb2[j]) {
-            c->bactive[j] = 0;
-            c->bdone[j] = 1;
+        if (c->bru[j] && c->bactive[j]) {
+            const double r2 = v[0];
+            c->br2_true[j] = r2;
+            if (!__builtin_isfinite(r2)) c->breakdown = 1;
+            if (r2 <= c->btol2[j] * c->bb2[j]) {
+                c->bactive[j] = 0;
+                c->bdone[j] = 1;
+            }
         }
         all &= !c->bactive[j];
     }
@@ -144,7 +155,7 @@ __global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, i
     for (int j = 0; j < nrhs; j++) {
         double v[4];
         bsum<4>(partial, nb, nrhs, j, v, lds);
-        if (threadIdx.x || !c->bactive[j]) continue;
+        if (threadIdx.x || !c->bactive[j] || !c->bru[j]) continue;   // the others keep their CG step
         const double rho = v[0];
         double beta = 0.0, cr = 0.0, ci = 0.0;
         if (mode != 1) {
@@ -162,6 +173,7 @@ __global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, i
         c->brmax2[j] = rho;
     }
     if (threadIdx.x) return;
+    for (int j = 0; j < nrhs; j++) c->bru[j] = 0;
     c->reason = STOP_NONE;
     c->stop = STOP_NEVER;
 }
@@ -219,24 +231,64 @@ struct BRun {
     long iters = 0, rus = 0, dsl = 0, d64 = 0;
     double alg = 0.0;
     hipGraphExec_t exec = nullptr;
-    DslashPlan plan_s{}, plan_64{};
-    NbList nl_s{}, nl_64{};
+    // A Dslash launch over a set of field columns: the plan for the block padded
+    // to a power of two and the column map that deals the columns round-robin
+    // over the lane groups (column i of the set -> group i % rg, slot i / rg),
+    // so that the lanes of a site share the work of the longest-running systems.
+    struct Mapped {
+        DslashPlan plan{};
+        unsigned mask = 0;            // field columns in the launch
+        unsigned cvalid = 0;
+        unsigned long long cmap = 0;
+        NbList nl{};
+    };
+    Mapped ms_{}, m64_{};
 
-    // launch shapes (autotuned on first use, outside capture) and the block
-    // count each right-hand side's Dslash partials use
-    void setup_plans() {
-        const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
-        DslashArgs ps = dargs(gs, fmt, B->ts, B->rs, 1);
-        plan_s = dslash_plan(fmt, g, nrhs, &ps, st);
-        DslashArgs p64 = dargs(g64, f64, B->t64, B->x64, 1);
-        plan_64 = dslash_plan(f64, g, nrhs, &p64, st);
-        nl_s.pstride = nl_64.pstride = dslash_max_blocks(g.vh);
-        for (int i = 0; i < plan_s.n; i++)
-            for (int j = 0; j < plan_s.tile[i].nr * plan_s.tile[i].rg; j++)
-                nl_s.nb[plan_s.rhs0[i] + j] = dslash_tile_blocks(g.vh, plan_s.tile[i]);
-        for (int i = 0; i < plan_64.n; i++)
-            for (int j = 0; j < plan_64.tile[i].nr * plan_64.tile[i].rg; j++)
-                nl_64.nb[plan_64.rhs0[i] + j] = dslash_tile_blocks(g.vh, plan_64.tile[i]);
+    Mapped map_columns(const hisq_fmt &f, const hisq_gauge *gg, char *out, const char *in, unsigned mask) {
+        Mapped m;
+        m.mask = mask;
+        int cols[16], n = 0;
+        for (int j = 0; j < nrhs; j++)
+            if ((mask >> j) & 1u) cols[n++] = j;
+        // tune (first use of a key) on a dense map of the same columns
+        DslashArgs probe = dargs(gg, f, out, in, 1);
+        probe.nrhs = n;
+        probe.cmapped = 1;
+        probe.cvalid = n >= 16 ? 0xffffu : ((1u << n) - 1u);
+        probe.cmap = 0;
+        for (int k = 0; k < n; k++) probe.cmap |= (unsigned long long)cols[k] << (4 * k);
+        m.plan = dslash_plan(f, g, n, &probe, st);
+        const DslashTile &t = m.plan.tile[0];
+        for (int i = 0; i < n; i++) {
+            const int k = (i % t.rg) * t.nr + i / t.rg;
+            m.cmap |= (unsigned long long)cols[i] << (4 * k);
+            m.cvalid |= 1u << k;
+        }
+        m.nl.pstride = dslash_max_blocks(g.vh);
+        for (int j = 0; j < 16; j++) m.nl.nb[j] = dslash_tile_blocks(g.vh, t);
+        return m;
+    }
+
+    void apply(DslashArgs &a, const Mapped &m) const {
+        a.nrhs = __builtin_popcount(m.mask);
+        a.cmapped = 1;
+        a.cvalid = m.cvalid;
+        a.cmap = m.cmap;
+    }
+
+    // the sloppy launches cover the systems still iterating; a change of that set
+    // re-plans them and drops the captured block of iterations
+    hisq_status remap_sloppy(const SolverCtrl *h) {
+        unsigned mask = 0;
+        for (int j = 0; j < nrhs; j++)
+            if (h->bactive[j]) mask |= 1u << j;
+        if (mask == 0 || mask == ms_.mask) return HISQ_OK;
+        ms_ = map_columns(fmt, gs, B->ts, B->rs, mask);
+        if (exec) {
+            HISQ_TRY_HIP(hipGraphExecDestroy(exec));
+            exec = nullptr;
+        }
+        return HISQ_OK;
     }
 
     ~BRun() {
@@ -265,20 +317,22 @@ struct BRun {
         SolverCtrl *c = B->ctrl;
         const Guard gns{&c->stop, j, 0}, gsn{&c->stop, j, 1};
         DslashArgs A = dargs(gs, fmt, B->ts, B->p[jb], 1);
+        apply(A, ms_);
         A.guard = gns;
         A.cactive = c->bactive;   // stopped systems cost no Dslash work
-        HISQ_TRY_HIP(launch_dslash(A, fmt, plan_s, st, nullptr));
+        HISQ_TRY_HIP(launch_dslash(A, fmt, ms_.plan, st, nullptr));
         DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
+        apply(Bk, ms_);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
         Bk.acol = c->bc;
         Bk.cactive = c->bactive;
         Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
-        Bk.pstride = nl_s.pstride;
+        Bk.pstride = ms_.nl.pstride;
         Bk.guard = gns;
-        HISQ_TRY_HIP(launch_dslash(Bk, fmt, plan_s, st, nullptr));
-        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, nl_s, nrhs, jb, gns);
+        HISQ_TRY_HIP(launch_dslash(Bk, fmt, ms_.plan, st, nullptr));
+        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, ms_.nl, nrhs, jb, gns);
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_bcg_axpy(B->rs, B->aps, c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_bfin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs, gns);
@@ -292,30 +346,38 @@ struct BRun {
         return HISQ_OK;
     }
 
-    hisq_status enq_reliable(int mode, int count, const char *p_src) {
+    // ru_mask: the systems taking part (the FP64 launches cover those only)
+    hisq_status enq_reliable(int mode, int count, const char *p_src, unsigned ru_mask) {
         SolverCtrl *c = B->ctrl;
         const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
+        const int nru = __builtin_popcount(ru_mask);
+        if (ru_mask != m64_.mask) m64_ = map_columns(f64, g64, B->t64, B->x64, ru_mask);
         if (count > 0) {
             SpinorList pl;
             for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;
             HISQ_TRY_HIP(launch_bflush_x(B->x64, fs64, pl, count, c, vh, fs, nrhs, fmt.spinor, fmt.compute,
                                          Guard{nullptr, 0, 0}, st));
         }
+        // true residuals of the systems taking part (c->bru) only
         DslashArgs A = dargs(g64, f64, B->t64, B->x64, 1);
-        HISQ_TRY_HIP(launch_dslash(A, f64, plan_64, st, nullptr));
+        apply(A, m64_);
+        A.cactive = c->bru;
+        HISQ_TRY_HIP(launch_dslash(A, f64, m64_.plan, st, nullptr));
         DslashArgs Bk = dargs(g64, f64, B->r64, B->t64, 0);
+        apply(Bk, m64_);
+        Bk.cactive = c->bru;
         Bk.x = B->x64;
         Bk.acol = c->bnc;
         Bk.y = B->b64;
         Bk.c = 1.0;
         Bk.red = RED_NORM;
         Bk.partial = B->partial;
-        Bk.pstride = nl_64.pstride;
-        HISQ_TRY_HIP(launch_dslash(Bk, f64, plan_64, st, nullptr));
-        hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, nl_64, nrhs);
+        Bk.pstride = m64_.nl.pstride;
+        HISQ_TRY_HIP(launch_dslash(Bk, f64, m64_.plan, st, nullptr));
+        hipLaunchKernelGGL(k_bfin_ru_check, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, m64_.nl, nrhs);
         HISQ_TRY_HIP(hipGetLastError());
         d64 += 2;
-        alg += 2.0 * vh * (dslash_link_bytes(g64) + nrhs * 2.0 * 48) + 2.0 * vh * nrhs * 48;
+        alg += 2.0 * vh * (dslash_link_bytes(g64) + nru * 2.0 * 48) + 2.0 * vh * nru * 48;
         const Guard g0{&c->stop, 0, 0};
         HISQ_TRY_HIP(launch_bru_convert(B->rs, B->r64, fs64, mode == 1 ? nullptr : p_src, mode == 0 ? B->aps : nullptr,
                                         c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, g0, st));
@@ -415,6 +477,7 @@ hisq_status batched_run(BatchedJob &J) {
     h->delta2 = q.delta > 0 ? q.delta * q.delta : 0.0;
     for (int j = 0; j < nrhs; j++) {
         h->bactive[j] = 1;
+        h->bru[j] = 1;   // the first reliable update computes every initial residual
         h->bc[j] = J.c[j];
         h->bnc[j] = -J.c[j];
         h->btol2[j] = J.tol[j] * J.tol[j];
@@ -435,17 +498,26 @@ hisq_status batched_run(BatchedJob &J) {
             double acc = 0.0;
             for (int k = 0; k < nbk; k++) acc += part[(size_t)j * 4096 + k];
             h->bb2[j] = acc;
-            if (acc == 0.0) {
+            if (acc == 0.0) {   // b_j = 0: x_j = 0 whatever the initial guess
                 h->bactive[j] = 0;
                 h->bdone[j] = 1;
+                HISQ_TRY_HIP(hipMemsetAsync(B.x64 + j * R.fs64, 0, R.fs64, s_));
             }
         }
         HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
     }
-    R.setup_plans();
-    hisq_status status = R.enq_reliable(1, 0, nullptr);
-    if (status == HISQ_OK) status = R.read_ctrl(h);
+    unsigned m0 = 0;   // systems with b != 0: their initial true residuals
+    for (int j = 0; j < nrhs; j++)
+        if (h->bactive[j]) m0 |= 1u << j;
+    hisq_status status = HISQ_OK;
+    if (m0) {
+        status = R.enq_reliable(1, 0, nullptr, m0);
+        if (status == HISQ_OK) status = R.read_ctrl(h);
+    } else {
+        h->done = 1;
+    }
     for (int j = 0; j < nrhs; j++) J.resid0_j[j] = h->bb2[j] > 0 ? std::sqrt(h->br2_true[j] / h->bb2[j]) : 0.0;
+    if (status == HISQ_OK && !h->done) status = R.remap_sloppy(h);
     long k0 = 0;
     while (status == HISQ_OK && !h->done) {
         if (h->breakdown) {
@@ -461,13 +533,11 @@ hisq_status batched_run(BatchedJob &J) {
         R.iters += dk;
         R.dsl += 2 * dk;
         {
-            // links once per Dslash; spinor traffic of every right-hand side in the
-            // Dslash, of the active ones in the vector updates
+            // links once per Dslash; spinor traffic of the systems still iterating
             int na = 0;
             for (int j = 0; j < nrhs; j++) na += h->bactive[j] ? 1 : 0;
             const double bs = spinor_site_bytes(J.fmt.spinor), bl = dslash_link_bytes(J.gs);
-            R.alg += dk * (double)g.vh * (2.0 * (bl + nrhs * 2.0 * bs) + nrhs * bs
-                                          + na * (6.0 * bs + (R.nb * bs + 96.0) / R.nb));
+            R.alg += dk * (double)g.vh * (2.0 * (bl + na * 2.0 * bs) + na * (7.0 * bs + (R.nb * bs + 96.0) / R.nb));
         }
         if (h->stop == STOP_NEVER) continue;
         if (h->breakdown) {
@@ -480,12 +550,19 @@ hisq_status batched_run(BatchedJob &J) {
         }
         const int jb = h->stop % R.nb;
         const int reason = h->reason;
-        status = R.enq_reliable(0, jb + 1, B.p[jb]);
+        unsigned rum = 0, act = 0;
+        for (int j = 0; j < nrhs; j++) {
+            if (h->bru[j] && h->bactive[j]) rum |= 1u << j;
+            if (h->bactive[j]) act |= 1u << j;
+        }
+        status = R.enq_reliable(0, jb + 1, B.p[jb], rum ? rum : act);
         if (status != HISQ_OK) break;
         R.rus++;
         status = R.read_ctrl(h);
         if (status != HISQ_OK) break;
         if (h->done) break;
+        status = R.remap_sloppy(h);
+        if (status != HISQ_OK) break;
         if (reason == STOP_MAXITER || h->k >= q.maxiter) {
             status = set_error(HISQ_ENOCONV, "batched CG: no convergence in %d iterations", h->k);
             break;

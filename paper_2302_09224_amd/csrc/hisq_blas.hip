@@ -597,7 +597,9 @@ __global__ void k_bru_convert(char *rs, const char *r64, size_t fs64, const char
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         const R a = (R)ctrl->balpha[j];
         char *rsj = rs + j * fs;
-        for (size_t s = gtid(); s < n; s += gstride()) {
+        // only the systems taking part in the reliable update replace their residual
+        const bool part = ctrl->bru[j] && ctrl->bactive[j];
+        for (size_t s = gtid(); part && s < n; s += gstride()) {
             CVec<double> rt = SpinorIO<SF_F64, double>::load(r64 + j * fs64, n, s);
             CVec<R> rold;
             if (ap) rold = SpinorIO<SF, R>::load(rsj, n, s);

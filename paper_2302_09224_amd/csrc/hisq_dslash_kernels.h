@@ -375,6 +375,14 @@ __device__ __forceinline__ int hop_site_rt(const Geom &g, const Coords &c, int s
 // the kernel
 // ---------------------------------------------------------------------------
 
+// field column of the launch's right-hand side k, and whether it exists
+__device__ __forceinline__ int colmap(const DslashArgs &A, int k) {
+    return A.cmapped ? (int)((A.cmap >> (4 * k)) & 15ull) : k;
+}
+__device__ __forceinline__ bool colvalid(const DslashArgs &A, int k, int ncol) {
+    return A.cmapped ? ((A.cvalid >> k) & 1u) != 0 : k < ncol;
+}
+
 // GUARD: launched inside a solver's block of iterations (may return at once);
 // standalone applications use the unguarded instantiation.
 // LR: 18 = long links stored in full, 12 = two rows + reconstruction
@@ -397,11 +405,11 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     unsigned live = 0;
 #pragma unroll
     for (int j = 0; j < NR; j++)
-        if (rc + j < ncol && (!A.cactive || A.cactive[rc + j])) live |= 1u << j;
+        if (colvalid(A, rc + j, ncol) && (!A.cactive || A.cactive[colmap(A, rc + j)])) live |= 1u << j;
     // xpay coefficient of each of the lane's right-hand sides, read once
     R acoef[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) acoef[j] = (A.acol && ((live >> j) & 1u)) ? (R)A.acol[rc + j] : (R)A.a;
+    for (int j = 0; j < NR; j++) acoef[j] = (A.acol && ((live >> j) & 1u)) ? (R)A.acol[colmap(A, rc + j)] : (R)A.a;
     // Tiles of blockDim lanes.  sweep 0: XCD k (blocks b with b % 8 == k) sweeps
     // the contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
     // gridDim/8 blocks taking every (gridDim/8)-th tile.  sweep 1: block b takes
@@ -430,7 +438,8 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
         const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
         const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
-        const char *in = A.in + (size_t)r0 * fs;
+        // input field of the lane's right-hand side j
+        auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
         CVec<R> acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
@@ -449,13 +458,13 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                     const int tl = (mu == 3 && (h & 1)) ? wrap_add(c.t, -3, g.T) : c.t;
                     const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
 #pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
+                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
                     U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
                 } else {
                     const char *field = (h & 2) ? A.lng : A.fat;
                     const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
+                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
                     U = link_decode<R>(Lr, (h & 2) ? gl : gf);
                 }
                 if (h & 1) {
@@ -486,7 +495,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
                 else
                     L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-                for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in + j * fs, vh, ss) : SpinRaw<SF>{};
+                for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -510,7 +519,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 #pragma unroll
         for (int j = 0; j < NR; j++) {
             if (!((live >> j) & 1u)) continue;
-            const size_t off = (size_t)(r0 + j) * fs;
+            const size_t off = (size_t)colmap(A, r0 + j) * fs;
             const R a = acoef[j];
             CVec<R> xv;
             cvec_zero(xv);
@@ -566,10 +575,10 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         }
         __syncthreads();
         const int k = threadIdx.x;
-        if (k < rg * NR && rhs0 + k < ncol) {
+        if (k < rg * NR && colvalid(A, rhs0 + k, ncol)) {
             double v = 0.0;
             for (int ww = 0; ww < nw; ww++) v += lds[ww * rg * NR + k];
-            A.partial[(size_t)(rhs0 + k) * A.pstride + blockIdx.x] = v;
+            A.partial[(size_t)colmap(A, rhs0 + k) * A.pstride + blockIdx.x] = v;
         }
     }
 }

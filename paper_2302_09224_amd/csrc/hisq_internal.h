@@ -69,6 +69,12 @@ struct DslashArgs {
     double lcoef;
     const double *acol;   // optional (device): coefficient a of right-hand side j is acol[j]
     const int *cactive;   // optional (device): right-hand side j is skipped (not read, not written) if !cactive[j]
+    // cmapped: the launch's right-hand side k exists if bit k of cvalid is set and is field column
+    // (cmap >> 4k) & 15 (fields, acol, cactive and partials are indexed by the field column);
+    // otherwise right-hand side k < nrhs is column k
+    int cmapped;
+    unsigned cvalid;
+    unsigned long long cmap;
 };
 
 // Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
@@ -173,6 +179,7 @@ struct SolverCtrl {
     double bc[16], bnc[16];  // 4m^2 + shift of system j, and its negative
     double btol2[16];        // tol_j^2
     int bactive[16];   // 1 while right-hand side j is still iterating
+    int bru[16];       // 1: right-hand side j takes part in the pending reliable update
     int bdone[16];
     int bk[16];
 };

@@ -850,6 +850,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         for (int i = 1; i < nshift; i++) st->shift_iters[i] = h->shift_stop_k[i] ? h->shift_stop_k[i] : h->k;
         st->shift_iters[0] = h->k;
         rho_ms = h->rho_prev;  // |r_k|^2 of the gradient vector p_k carried into the refinement
+        st->phase_seconds[0] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         base_slot = R.last_slot;
         if (status != HISQ_OK) {
             (void)E.end();
@@ -860,7 +861,13 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
 
     // ---- refinement (refine_fmt): base first keeping its gradient vector, then each shift ----
     // (batched: the shifted systems together, every Dslash shared by up to 16 of them)
+    auto t1 = std::chrono::steady_clock::now();
     for (int i = 0; i < (L.batch ? 1 : nshift) && status == HISQ_OK; i++) {
+        if (i == 1) {
+            HISQ_TRY_HIP(hipStreamSynchronize(s_));
+            t1 = std::chrono::steady_clock::now();
+            st->phase_seconds[1] = std::chrono::duration<double>(t1 - t0).count() - st->phase_seconds[0];
+        }
         Run R;
         R.g = g;
         R.vh = g.vh;
@@ -895,6 +902,11 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         st->dslash_f64 += (int)R.dslash_f64;
         st->alg_bytes += R.alg_bytes;
         HISQ_TRY_HIP(launch_spinor_unpack(x[i], Bi.x64, g.vh, SF_F64, s_));
+    }
+    if (L.batch || nshift == 1) {
+        HISQ_TRY_HIP(hipStreamSynchronize(s_));
+        t1 = std::chrono::steady_clock::now();
+        st->phase_seconds[1] = std::chrono::duration<double>(t1 - t0).count() - st->phase_seconds[0];
     }
     if (L.batch && status == HISQ_OK) {
         // the multi-shift solutions are the initial guesses (clean restarts from them)
@@ -931,6 +943,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
     }
     hisq_status s2 = E.end();
     if (status == HISQ_OK) status = s2;
+    st->phase_seconds[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
     double worst = 0.0;
     for (int i = 0; i < nshift; i++) worst = std::max(worst, st->shift_resid[i] / tol[i] * tol[0]);
     st->true_resid = worst;

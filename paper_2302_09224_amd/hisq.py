@@ -64,7 +64,8 @@ class hisq_solver_stats(ctypes.Structure):
                 ("shift_iters", ctypes.c_int * HISQ_MAX_SHIFTS),
                 ("shift_resid_ms", ctypes.c_double * HISQ_MAX_SHIFTS),
                 ("refine_iters", ctypes.c_int * HISQ_MAX_SHIFTS),
-                ("shift_resid", ctypes.c_double * HISQ_MAX_SHIFTS)]
+                ("shift_resid", ctypes.c_double * HISQ_MAX_SHIFTS),
+                ("phase_seconds", ctypes.c_double * 3)]
 
     def as_dict(self):
         n = max(1, self.nshift)
@@ -73,7 +74,8 @@ class hisq_solver_stats(ctypes.Structure):
                     dslash_f64=self.dslash_f64, true_resid=self.true_resid, seconds=self.seconds,
                     alg_bytes=self.alg_bytes, nshift=self.nshift,
                     shift_iters=list(self.shift_iters[:n]), shift_resid_ms=list(self.shift_resid_ms[:n]),
-                    refine_iters=list(self.refine_iters[:n]), shift_resid=list(self.shift_resid[:n]))
+                    refine_iters=list(self.refine_iters[:n]), shift_resid=list(self.shift_resid[:n]),
+                    phase_seconds=list(self.phase_seconds))
 
 
 # named precision triplets gauge/fermion/compute (Sec. 4)

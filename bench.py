@@ -222,7 +222,9 @@ def main():
     def solve_once(ms, ref, **kw):
         """pack the links the solve needs (FP64 + its two triplets) and run it"""
         f_ms, f_ref = hisq.fmt(ms), hisq.fmt(ref)
-        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+        # the FP64 operator of the reliable updates and true residuals: FP64 links, the
+        # long ones as two rows when --recon 12 (rebuilt to within FP64 rounding)
+        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=args.recon)
         gms = hisq.pack_gauge(fat, lng, dims, f_ms.gauge, long_recon=args.recon)
         gref = gms if f_ref.gauge == f_ms.gauge else hisq.pack_gauge(fat, lng, dims, f_ref.gauge,
                                                                      long_recon=args.recon)
@@ -268,7 +270,7 @@ def main():
     def pack_field_bytes(gf, recon):
         return 4 * V * (2 * 144 + hisq.GAUGE_BYTES[gf] + (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12
                                                            else hisq.GAUGE_BYTES[gf]))
-    pack_bytes = pack_field_bytes(hisq.GAUGE_F64, 18) + pack_field_bytes(fms.gauge, args.recon)
+    pack_bytes = pack_field_bytes(hisq.GAUGE_F64, args.recon) + pack_field_bytes(fms.gauge, args.recon)
     if fref.gauge != fms.gauge:
         pack_bytes += pack_field_bytes(fref.gauge, args.recon)
     step_bytes = float(np.mean([s["alg_bytes"] for s in stats])) + pack_bytes

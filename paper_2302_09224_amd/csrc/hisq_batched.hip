@@ -120,6 +120,12 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
         reason = STOP_MAXITER;
         for (int j = 0; j < nrhs; j++) c->bru[j] = c->bactive[j];   // report every true residual
     }
+    if (reason == STOP_RU || reason == STOP_CONV) {
+        // systems within a factor 2 of their own trigger join this reliable update
+        // (one FP64 application serves them all instead of one each shortly after)
+        for (int j = 0; j < nrhs; j++)
+            if (c->bactive[j] && c->delta2 > 0.0 && c->brho[j] < 4.0 * c->delta2 * c->brmax2[j]) c->bru[j] = 1;
+    }
     if (reason != STOP_NONE) {
         c->reason = reason;
         c->stop = gd.j;

@@ -144,3 +144,24 @@ def test_batched_cg_recon12():
         res = oracle.true_residual(fat.numpy(), lng.numpy(), _full(dims, ev, x[j]), _full(dims, ev, bs[j]),
                                    dims, mass)
         assert res <= 1e-10 * (1 + 1e-6), (j, res)
+
+
+def test_multishift_recon12_fp64_operator():
+    """the FP64 operator itself (reliable updates, true residuals) on two-row long
+    links: the solutions still meet the targets measured with the full links"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 14)
+    ev = oracle.parity_sites(dims, 0)
+    b = inputs.gaussian_spinor(ev.size, inputs.SOURCE_SEED).numpy()
+    shifts = [1e-4, 1e-2, 0.5]
+    p64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64, long_recon=hisq.RECON_12)
+    pms = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX32, long_recon=hisq.RECON_12)
+    pref = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16, long_recon=hisq.RECON_12)
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, [1e-10] * 3, p64, pms, pref, mass,
+                                      ms_fmt="int30", ref_fmt="int20")
+    assert st["status"] == "HISQ_OK", st
+    for i, s in enumerate(shifts):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), _full(dims, ev, xs[i].cpu().numpy()),
+                                   _full(dims, ev, b), dims, mass, shift=s)
+        assert res <= 1e-10 * (1 + 1e-5), (i, res, st)

@@ -109,6 +109,53 @@ def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16
     return out
 
 
+def bench_multi(hisq, inputs, torch, dev, reps=50):
+    """8^4 + 12^4 + 16^4 + 24^4 in one launch against one launch per lattice
+    (HIP events; FIX16/INT20/FP32, two-row long links)."""
+    lattices = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (24, 24, 24, 24)]
+    f = hisq.fmt("int20")
+    outs, ins, gauges, keep = [], [], [], []
+    nbytes = 0
+    for k, dims in enumerate(lattices):
+        vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+        fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 50 + k, device=dev)
+        pg = hisq.pack_gauge(fat, lng, dims, f.gauge, long_recon=12)
+        pin = hisq.pack_spinor(inputs.gaussian_spinor(vh, inputs.SOURCE_SEED + 50 + k, device=dev), f.spinor)
+        outs.append(torch.empty_like(pin))
+        ins.append(pin)
+        gauges.append(pg.desc)
+        keep.append(pg)
+        nbytes += vh * (8 * 36 + 8 * 24 + 2 * 16)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def one_launch():
+        hisq.hisq_dslash_multi(outs, ins, gauges, 0, f)
+
+    def per_lattice():
+        for o, i, g in zip(outs, ins, gauges):
+            hisq.hisq_dslash(o, i, g, 0, f)
+
+    res = {}
+    for name, fn in (("one_launch", one_launch), ("per_lattice", per_lattice)):
+        for _ in range(3):
+            fn()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps * 1e3
+    out = dict(lattices=["x".join(map(str, d)) for d in lattices], triplet="fix16/int20/fp32", long_recon=12,
+               us_one_launch=round(res["one_launch"], 1), us_per_lattice=round(res["per_lattice"], 1),
+               speedup=round(res["per_lattice"] / res["one_launch"], 2),
+               gbs_one_launch=round(nbytes / res["one_launch"] / 1e3, 1))
+    log(f"[bench] multi-lattice {out}")
+    del outs, ins, gauges, keep
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,9 +258,11 @@ def main():
     batched = None
     if args.batched:
         batched = bench_batched(args, hisq, inputs, torch, dev)
+    multi = bench_multi(hisq, inputs, torch, dev)
     if args.kernels_only:
         tuning = hisq.hisq_tune_report().strip().splitlines()
-        print(json.dumps(dict(kernels=kernels, batched=batched, tuning=tuning, config={"lattice": list(dims)})))
+        print(json.dumps(dict(kernels=kernels, batched=batched, multi_lattice=multi, tuning=tuning,
+                              config={"lattice": list(dims)})))
         return
     gauges.clear()
     torch.cuda.empty_cache()
@@ -371,6 +420,7 @@ def main():
                        "step_alg_bytes": step_bytes, "fp64_gpu": fp64, "double_single_half": alt},
         "kernels": kernels,
         "batched": batched,
+        "multi_lattice": multi,
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -169,6 +169,17 @@ hisq_status hisq_normal_op(void *out, const void *in, void *tmp, const hisq_gaug
 hisq_status hisq_dslash_batched(void *out, const void *in, const hisq_gauge *g, int parity,
                                 hisq_fmt fmt, int nrhs, void *stream);
 
+/* Several independent lattices in ONE launch (Sec. 1 "Block solvers": small
+ * problems sharing the device, e.g. 8^4 + 12^4 + 16^4 + 24^4): lattice i gets
+ * out[i] = D in[i] with its own packed links g[i] (its own dims), the same
+ * triplet, parity and long-link storage for all.  out, in: (host) arrays of n
+ * (device) packed spinors of lattice i's Vh sites; g: (host) array of n
+ * descriptors.  1 <= n <= HISQ_MAX_LATTICES; every lattice has at most 2^31
+ * sites.  Results are identical to n hisq_dslash calls. */
+#define HISQ_MAX_LATTICES 8
+hisq_status hisq_dslash_multi(int n, void *const *out, const void *const *in, const hisq_gauge *const *g,
+                              int parity, hisq_fmt fmt, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Solvers (Sec. 3)                                                          */
 /* ------------------------------------------------------------------------ */

@@ -274,6 +274,34 @@ extern "C" hisq_status hisq_dslash(void *out, const void *in, const hisq_gauge *
     return HISQ_OK;
 }
 
+extern "C" hisq_status hisq_dslash_multi(int n, void *const *out, const void *const *in, const hisq_gauge *const *g,
+                                         int parity, hisq_fmt fmt, void *stream) {
+    if (n < 1 || n > HISQ_MAX_LATTICES) return set_error(HISQ_EINVAL, "hisq_dslash_multi: n must be in [1,%d]", HISQ_MAX_LATTICES);
+    if (!out || !in || !g) return set_error(HISQ_EINVAL, "hisq_dslash_multi: null argument");
+    MultiArgs m;
+    memset(&m, 0, sizeof(m));
+    m.n = n;
+    int lr = -1;
+    long long blocks = 0;
+    for (int i = 0; i < n; i++) {
+        if (!g[i]) return set_error(HISQ_EINVAL, "hisq_dslash_multi: null gauge %d", i);
+        HISQ_TRY(dslash_common(out[i], in[i], g[i], parity, fmt, "hisq_dslash_multi"));
+        const int r = g[i]->long_recon == HISQ_RECON_12 ? 12 : 18;
+        if (lr >= 0 && r != lr) return set_error(HISQ_EINVAL, "hisq_dslash_multi: lattices differ in long-link storage");
+        lr = r;
+        for (int k = 0; k < i; k++)
+            if (out[i] == out[k] || out[i] == in[k] || in[i] == out[k])
+                return set_error(HISQ_EINVAL, "hisq_dslash_multi: lattice %d aliases lattice %d", i, k);
+        m.a[i] = base_args(g[i], out[i], in[i], parity);
+        m.boff[i] = (int)blocks;
+        blocks += (m.a[i].g.vh + MULTI_BLOCK - 1) / MULTI_BLOCK;
+        if (blocks > 0x7fffffff) return set_error(HISQ_EINVAL, "hisq_dslash_multi: too many sites");
+    }
+    m.boff[n] = (int)blocks;
+    HISQ_TRY_HIP(launch_dslash_multi(m, fmt, lr, (hipStream_t)stream));
+    return HISQ_OK;
+}
+
 extern "C" hisq_status hisq_dslash_xpay(void *out, const void *in, const hisq_gauge *g, int parity, hisq_fmt fmt,
                                         double a, const void *x, double b, void *stream) {
     HISQ_TRY(dslash_common(out, in, g, parity, fmt, "hisq_dslash_xpay"));

@@ -17,8 +17,9 @@
 
 namespace hisq {
 
-#define HISQ_DECL_TRIPLET(NAME) \
-    hipError_t dslash_launch_##NAME(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb);
+#define HISQ_DECL_TRIPLET(NAME)                                                                              \
+    hipError_t dslash_launch_##NAME(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nb); \
+    hipError_t dslash_multi_##NAME(const MultiArgs &m, int long_recon, hipStream_t st);
 HISQ_DECL_TRIPLET(double)
 HISQ_DECL_TRIPLET(single)
 HISQ_DECL_TRIPLET(half)
@@ -153,6 +154,18 @@ DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashA
     plan.rhs0[0] = 0;
     plan.tile[0] = tile_for(f, g, c, probe, st);
     return plan;
+}
+
+hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_recon, hipStream_t st) {
+    switch (triplet_key(f)) {
+    case GF_F64 * 100 + SF_F64 * 10 + 1: return dslash_multi_double(m, long_recon, st);
+    case GF_F32 * 100 + SF_F32 * 10 + 0: return dslash_multi_single(m, long_recon, st);
+    case GF_FIX16 * 100 + SF_HALF16 * 10 + 0: return dslash_multi_half(m, long_recon, st);
+    case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_multi_int20(m, long_recon, st);
+    case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_multi_int30(m, long_recon, st);
+    case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_multi_int30_fp32(m, long_recon, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPlan &plan, hipStream_t st, int *nblocks) {

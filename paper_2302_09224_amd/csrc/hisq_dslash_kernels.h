@@ -383,6 +383,140 @@ __device__ __forceinline__ bool colvalid(const DslashArgs &A, int k, int ncol) {
     return A.cmapped ? ((A.cvalid >> k) & 1u) != 0 : k < ncol;
 }
 
+// One output site s for the lane's right-hand sides r0..r0+NR-1 (those in
+// `live`): the 16 hops, the epilogue out = b*D(in) + a*x + c*y, the packed
+// store, and the optional reduction into red[].
+template <int GF, int SF, class R, int NR, int STAGE, bool RED, int LR>
+__device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, unsigned live, const R (&acoef)[NR],
+                                            double (&red)[NR]) {
+    const Geom &g = A.g;
+    const size_t fs = A.field_stride;
+    const size_t vh = (size_t)g.vh;
+    const int p = A.parity, q = 1 - p;
+    const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
+    const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
+    const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
+    // input field of the lane's right-hand side j
+    auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
+    CVec<R> acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
+    if (NR > 1 && STAGE == 1) {
+        // several right-hand sides per lane: one hop at a time (bounded registers)
+        const Coords c = coords_of(g, s, p);
+#pragma unroll 1
+        for (int h = 0; h < 16; h++) {
+            const int ss = hop_site_rt(g, c, s, h);
+            const int ls = (h & 1) ? ss : s;
+            const int lpar = (h & 1) ? q : p;
+            Mat<R> U;
+            SpinRaw<SF> Pr[NR];
+            if (LR == 12 && (h & 2)) {
+                const int mu = h >> 2;
+                const int tl = (mu == 3 && (h & 1)) ? wrap_add(c.t, -3, g.T) : c.t;
+                const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
+#pragma unroll
+                for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
+                U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
+            } else {
+                const char *field = (h & 2) ? A.lng : A.fat;
+                const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+#pragma unroll
+                for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
+                U = link_decode<R>(Lr, (h & 2) ? gl : gf);
+            }
+            if (h & 1) {
+#pragma unroll
+                for (int j = 0; j < NR; j++)
+                    if ((live >> j) & 1u) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
+            } else {
+#pragma unroll
+                for (int j = 0; j < NR; j++)
+                    if ((live >> j) & 1u) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
+            }
+        }
+    }
+    const Nbrs n = neighbours(g, s, p);
+#pragma unroll
+    for (int h0 = 0; h0 < ((NR > 1 && STAGE == 1) ? 0 : 16); h0 += STAGE) {
+        LinkRaw<GF> L[STAGE];
+        LinkRaw12<GF> L12[STAGE];
+        SpinRaw<SF> P[STAGE][NR];
+#pragma unroll
+        for (int i = 0; i < STAGE; i++) {
+            const int h = h0 + i;
+            const int ss = hop_spinor_site(n, h);
+            const int ls = (h & 1) ? ss : s;
+            const int lpar = (h & 1) ? q : p;
+            if (LR == 12 && (h & 2))
+                L12[i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
+            else
+                L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+#pragma unroll
+            for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < STAGE; i++) {
+            const int h = h0 + i;
+            const Mat<R> U = (LR == 12 && (h & 2))
+                                 ? link_decode12<R>(L12[i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
+                                 : link_decode<R>(L[i], (h & 2) ? gl : gf);
+#pragma unroll
+            for (int j = 0; j < NR; j++) {
+                if (NR > 1 && !((live >> j) & 1u)) continue;
+                const CVec<R> v = spin_decode<R>(P[i][j]);
+                if (h & 1)
+                    mdv_sub(acc[j], U, v);
+                else
+                    mv_add(acc[j], U, v);
+            }
+        }
+    }
+    const R b = (R)A.b, cc = (R)A.c;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        if (!((live >> j) & 1u)) continue;
+        const size_t off = (size_t)colmap(A, r0 + j) * fs;
+        const R a = acoef[j];
+        CVec<R> xv;
+        cvec_zero(xv);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[j].re[c] *= b;
+            acc[j].im[c] *= b;
+        }
+        if (A.x) {
+            xv = SpinorIO<SF, R>::load(A.x + off, vh, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[j].re[c] = fma(a, xv.re[c], acc[j].re[c]);
+                acc[j].im[c] = fma(a, xv.im[c], acc[j].im[c]);
+            }
+        }
+        if (A.y) {
+            const CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[j].re[c] = fma(cc, yv.re[c], acc[j].re[c]);
+                acc[j].im[c] = fma(cc, yv.im[c], acc[j].im[c]);
+            }
+        }
+        const CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
+        if (RED) {
+            if (A.red == RED_DOT_X) {
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+            }
+        }
+    }
+}
+
 // GUARD: launched inside a solver's block of iterations (may return at once);
 // standalone applications use the unguarded instantiation.
 // LR: 18 = long links stored in full, 12 = two rows + reconstruction
@@ -391,12 +525,9 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     __shared__ double lds[64];
     if (GUARD && !A.guard.pass()) return;
     const Geom g = A.g;
-    const size_t fs = A.field_stride;
     double red[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) red[j] = 0.0;
-    // xpay coefficient of each of the lane's right-hand sides (rg divides
-    // blockDim, so a lane keeps its group in every tile); read once, up front
     // The lane's right-hand sides rc..rc+NR-1 (rg divides blockDim, so a lane
     // keeps its group in every tile).  Those at or beyond ncol (a block padded
     // to a power of two) and those marked inactive are neither read nor written.
@@ -432,132 +563,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     const int s = rg == 1 ? tid : fdiv(tid, drg);
     const int grp = tid - s * rg;
     const int r0 = rhs0 + grp * NR;   // == rc
-    if (s < g.vh && live) {
-        const size_t vh = (size_t)g.vh;
-        const int p = A.parity, q = 1 - p;
-        const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
-        const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
-        const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
-        // input field of the lane's right-hand side j
-        auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
-        CVec<R> acc[NR];
-#pragma unroll
-        for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
-        if (NR > 1 && STAGE == 1) {
-            // several right-hand sides per lane: one hop at a time (bounded registers)
-            const Coords c = coords_of(g, s, p);
-#pragma unroll 1
-            for (int h = 0; h < 16; h++) {
-                const int ss = hop_site_rt(g, c, s, h);
-                const int ls = (h & 1) ? ss : s;
-                const int lpar = (h & 1) ? q : p;
-                Mat<R> U;
-                SpinRaw<SF> Pr[NR];
-                if (LR == 12 && (h & 2)) {
-                    const int mu = h >> 2;
-                    const int tl = (mu == 3 && (h & 1)) ? wrap_add(c.t, -3, g.T) : c.t;
-                    const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
-#pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
-                    U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
-                } else {
-                    const char *field = (h & 2) ? A.lng : A.fat;
-                    const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
-#pragma unroll
-                    for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
-                    U = link_decode<R>(Lr, (h & 2) ? gl : gf);
-                }
-                if (h & 1) {
-#pragma unroll
-                    for (int j = 0; j < NR; j++)
-                        if ((live >> j) & 1u) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
-                } else {
-#pragma unroll
-                    for (int j = 0; j < NR; j++)
-                        if ((live >> j) & 1u) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
-                }
-            }
-        }
-        const Nbrs n = neighbours(g, s, p);
-#pragma unroll
-        for (int h0 = 0; h0 < ((NR > 1 && STAGE == 1) ? 0 : 16); h0 += STAGE) {
-            LinkRaw<GF> L[STAGE];
-            LinkRaw12<GF> L12[STAGE];
-            SpinRaw<SF> P[STAGE][NR];
-#pragma unroll
-            for (int i = 0; i < STAGE; i++) {
-                const int h = h0 + i;
-                const int ss = hop_spinor_site(n, h);
-                const int ls = (h & 1) ? ss : s;
-                const int lpar = (h & 1) ? q : p;
-                if (LR == 12 && (h & 2))
-                    L12[i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
-                else
-                    L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
-#pragma unroll
-                for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < STAGE; i++) {
-                const int h = h0 + i;
-                const Mat<R> U = (LR == 12 && (h & 2))
-                                     ? link_decode12<R>(L12[i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
-                                     : link_decode<R>(L[i], (h & 2) ? gl : gf);
-#pragma unroll
-                for (int j = 0; j < NR; j++) {
-                    if (NR > 1 && !((live >> j) & 1u)) continue;
-                    const CVec<R> v = spin_decode<R>(P[i][j]);
-                    if (h & 1)
-                        mdv_sub(acc[j], U, v);
-                    else
-                        mv_add(acc[j], U, v);
-                }
-            }
-        }
-        const R b = (R)A.b, cc = (R)A.c;
-#pragma unroll
-        for (int j = 0; j < NR; j++) {
-            if (!((live >> j) & 1u)) continue;
-            const size_t off = (size_t)colmap(A, r0 + j) * fs;
-            const R a = acoef[j];
-            CVec<R> xv;
-            cvec_zero(xv);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc[j].re[c] *= b;
-                acc[j].im[c] *= b;
-            }
-            if (A.x) {
-                xv = SpinorIO<SF, R>::load(A.x + off, vh, s);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    acc[j].re[c] = fma(a, xv.re[c], acc[j].re[c]);
-                    acc[j].im[c] = fma(a, xv.im[c], acc[j].im[c]);
-                }
-            }
-            if (A.y) {
-                const CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    acc[j].re[c] = fma(cc, yv.re[c], acc[j].re[c]);
-                    acc[j].im[c] = fma(cc, yv.im[c], acc[j].im[c]);
-                }
-            }
-            const CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
-            if (RED) {
-                if (A.red == RED_DOT_X) {
-#pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; c++)
-                        red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
-                }
-            }
-        }
-    }
+    if (s < g.vh && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
     }
     if (RED) {
         // per right-hand side: sum over the lanes of the same group (lanes l with
@@ -583,9 +589,34 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     }
 }
 
+// Several lattices in one launch (Sec. 1 "Block solvers": small problems filling
+// the device together): block b belongs to the lattice l with boff[l] <= b <
+// boff[l+1] and covers its sites (b - boff[l]) * MULTI_BLOCK + lane.
+template <int GF, int SF, class R, int STAGE, int LR>
+__global__ void __launch_bounds__(MULTI_BLOCK) k_dslash_multi(MultiArgs M) {
+    int l = 0;
+    while (l + 1 < M.n && (int)blockIdx.x >= M.boff[l + 1]) l++;
+    const DslashArgs &A = M.a[l];
+    const int s = ((int)blockIdx.x - M.boff[l]) * MULTI_BLOCK + (int)threadIdx.x;
+    if (s >= A.g.vh) return;
+    const R acoef[1] = {(R)A.a};
+    double red[1] = {0.0};
+    dslash_site<GF, SF, R, 1, STAGE, false, LR>(A, s, 0, 1u, acoef, red);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+template <int GF, int SF, class R>
+hipError_t launch_multi(const MultiArgs &m, int long_recon, hipStream_t st) {
+    const int nb = m.boff[m.n];
+    if (long_recon == 12)
+        hipLaunchKernelGGL((k_dslash_multi<GF, SF, R, 4, 12>), dim3(nb), dim3(MULTI_BLOCK), 0, st, m);
+    else
+        hipLaunchKernelGGL((k_dslash_multi<GF, SF, R, 4, 18>), dim3(nb), dim3(MULTI_BLOCK), 0, st, m);
+    return hipGetLastError();
+}
 
 template <int GF, int SF, class R, int NR, int STAGE>
 hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, int sweep, hipStream_t st,

@@ -7,4 +7,8 @@ hipError_t dslash_launch_half(const DslashArgs &a, int rhs0, const DslashTile &t
     return dsl::launch_tile<GF_FIX16, SF_HALF16, float, true>(a, rhs0, t, st, nb);
 }
 
+hipError_t dslash_multi_half(const MultiArgs &m, int long_recon, hipStream_t st) {
+    return dsl::launch_multi<GF_FIX16, SF_HALF16, float>(m, long_recon, st);
+}
+
 }  // namespace hisq

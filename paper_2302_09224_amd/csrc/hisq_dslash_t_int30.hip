@@ -7,4 +7,8 @@ hipError_t dslash_launch_int30(const DslashArgs &a, int rhs0, const DslashTile &
     return dsl::launch_tile<GF_FIX32, SF_INT30, double, true>(a, rhs0, t, st, nb);
 }
 
+hipError_t dslash_multi_int30(const MultiArgs &m, int long_recon, hipStream_t st) {
+    return dsl::launch_multi<GF_FIX32, SF_INT30, double>(m, long_recon, st);
+}
+
 }  // namespace hisq

@@ -7,4 +7,8 @@ hipError_t dslash_launch_single(const DslashArgs &a, int rhs0, const DslashTile 
     return dsl::launch_tile<GF_F32, SF_F32, float, true>(a, rhs0, t, st, nb);
 }
 
+hipError_t dslash_multi_single(const MultiArgs &m, int long_recon, hipStream_t st) {
+    return dsl::launch_multi<GF_F32, SF_F32, float>(m, long_recon, st);
+}
+
 }  // namespace hisq

@@ -98,6 +98,17 @@ struct DslashPlan {
 
 // link pointers, fixed-point steps and long-link storage of a packed gauge
 void gauge_args(DslashArgs &a, const hisq_gauge *g);
+
+// Several independent lattices in one launch: lattice l owns blocks
+// [boff[l], boff[l+1]) of MULTI_BLOCK lanes, one output site per lane.
+constexpr int MULTI_BLOCK = 256;
+struct MultiArgs {
+    DslashArgs a[HISQ_MAX_LATTICES];
+    int boff[HISQ_MAX_LATTICES + 1];
+    int n;
+};
+static_assert(sizeof(MultiArgs) <= 4096, "kernel argument block too large");
+hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_recon, hipStream_t st);
 // link bytes one output site of a Dslash reads (8 fat + 8 long matrices)
 inline double dslash_link_bytes(const hisq_gauge *g) {
     const int b18 = gauge_matrix_bytes(g->fmt);

@@ -128,6 +128,7 @@ def load():
         "hisq_dslash_xpay": (i, [vp, vp, G, i, hisq_fmt, d, vp, d, vp]),
         "hisq_normal_op": (i, [vp, vp, vp, G, d, d, hisq_fmt, vp]),
         "hisq_dslash_batched": (i, [vp, vp, G, i, hisq_fmt, i, vp]),
+        "hisq_dslash_multi": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(G), i, hisq_fmt, vp]),
         "hisq_solver_params_default": (None, [P]),
         "hisq_cg_workspace_bytes": (sz, [ip, hisq_fmt, P]),
         "hisq_cg_solve": (i, [vp, vp, G, G, d, d, d, hisq_fmt, P, vp, sz, S, vp]),
@@ -231,6 +232,15 @@ def hisq_dslash_xpay(out, inp, gauge, parity, f, a, x, b, stream=None):
 def hisq_normal_op(out, inp, tmp, gauge, mass, shift, f, stream=None):
     _check(load().hisq_normal_op(_ptr(out), _ptr(inp), _ptr(tmp), ctypes.byref(gauge), float(mass), float(shift), f,
                                  _stream(stream)), "hisq_normal_op")
+
+
+def hisq_dslash_multi(outs, ins, gauges, parity, f, stream=None):
+    """one launch over several lattices: outs[i] = D ins[i] with gauges[i] (hisq_gauge descriptors)"""
+    n = len(outs)
+    o = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
+    a = (ctypes.c_void_p * n)(*[_ptr(t) for t in ins])
+    gp = (ctypes.POINTER(hisq_gauge) * n)(*[ctypes.pointer(g) for g in gauges])
+    _check(load().hisq_dslash_multi(n, o, a, gp, int(parity), f, _stream(stream)), "hisq_dslash_multi")
 
 
 def hisq_dslash_batched(out, inp, gauge, parity, f, nrhs, stream=None):

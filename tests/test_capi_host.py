@@ -93,6 +93,18 @@ def test_argument_errors(hisq):
     assert lib.hisq_gauge_pack(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, None) == -1
     dims = (ctypes.c_int * 4)(4, 4, 4, 4)
     assert lib.hisq_gauge_pack_recon(ctypes.byref(g), 4096, 4096, 4096, 4096, dims, 0, 9, None) == -1
+    # several lattices in one launch: count, null and aliasing checks before any launch
+    for k, v in enumerate((4, 4, 4, 4)):
+        g.dims[k] = v
+    g.fmt = hisq.GAUGE_F32
+    outs = (ctypes.c_void_p * 2)(4096 * 3, 4096 * 3)
+    ins = (ctypes.c_void_p * 2)(4096 * 4, 4096 * 5)
+    gp = (ctypes.POINTER(hisq.hisq_gauge) * 2)(ctypes.pointer(g), ctypes.pointer(g))
+    assert lib.hisq_dslash_multi(0, outs, ins, gp, 0, f, None) == -1
+    assert lib.hisq_dslash_multi(9, outs, ins, gp, 0, f, None) == -1
+    assert lib.hisq_dslash_multi(2, outs, ins, gp, 0, f, None) == -1     # two lattices write one field
+    assert "alias" in hisq.hisq_last_error()
+    assert lib.hisq_dslash_multi(2, outs, ins, None, 0, f, None) == -1
 
 
 def test_tune_set_validation(hisq):

@@ -156,6 +156,42 @@ def bench_multi(hisq, inputs, torch, dev, reps=50):
     return out
 
 
+def bench_cg_stability(hisq, inputs, torch, dev, dims=(16, 16, 16, 16), masses=(0.01, 0.001), tol=1e-10,
+                       maxiter=40000):
+    """Fig. 1 analog (Sec. 3.1): CG on rough (Haar) links at light masses, FP64
+    vs double-half with reliable updates only (Fletcher-Reeves beta, no gradient
+    re-projection) vs the stabilised double-half (Polak-Ribiere beta,
+    re-projection; the FP64 buffered solution in both mixed variants)."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    fat, lng = inputs.make_links(dims, "haar", inputs.GAUGE_SEED + 60, device=dev)
+    b = inputs.gaussian_spinor(V // 2, inputs.SOURCE_SEED + 60, device=dev)
+    g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+    g16 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_FIX16)
+    out = {}
+    for m in masses:
+        row = {}
+        for name, gs, sl, kw in (("double", g64, "double", dict(delta=0.0)),
+                                 ("double-half naive", g16, "half", dict(pr_beta=0, reproject=0)),
+                                 ("double-half stabilised", g16, "half", {})):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            try:
+                _, st = hisq.cg_solve(b, g64, gs, m, tol=tol, sloppy=sl, maxiter=maxiter, **kw)
+                status = st["status"]
+            except hisq.HisqError as e:      # iteration cap: report it
+                st, status = None, str(e).split(":")[1].strip()
+            torch.cuda.synchronize()
+            row[name] = dict(status=status, iters=st["iters"] if st else maxiter,
+                             reliable_updates=st["reliable_updates"] if st else None,
+                             true_resid=st["true_resid"] if st else None, seconds=round(time.perf_counter() - t, 3))
+        out[f"m={m}"] = row
+        log(f"[bench] CG stability {dims} Haar m={m}: " +
+            ", ".join(f"{k} {v['iters']} it ({v['status']})" for k, v in row.items()))
+    del g64, g16, fat, lng
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +295,7 @@ def main():
     if args.batched:
         batched = bench_batched(args, hisq, inputs, torch, dev)
     multi = bench_multi(hisq, inputs, torch, dev)
+    stability = None if args.kernels_only else bench_cg_stability(hisq, inputs, torch, dev)
     if args.kernels_only:
         tuning = hisq.hisq_tune_report().strip().splitlines()
         print(json.dumps(dict(kernels=kernels, batched=batched, multi_lattice=multi, tuning=tuning,
@@ -421,6 +458,7 @@ def main():
         "kernels": kernels,
         "batched": batched,
         "multi_lattice": multi,
+        "cg_stability": stability,
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -222,6 +222,90 @@ def multishift_cg(fat, lng, b, dims, mass, shifts, tol, maxiter=100000, parity=0
     return dict(x=xs, iters=iters, resid=resid, zeta=zeta, r=r, status=st)
 
 
+def full_op(fat, lng, x, dims, mass, lib=None):
+    """M x = 2m x + D x on the whole lattice (the unpreconditioned HISQ operator;
+    its even-site Schur complement M^dag M |_even is 4m^2 - D_eo D_oe)"""
+    return 2.0 * mass * _arr(x, np.complex128) + dslash(fat, lng, x, dims, -1, lib=lib)
+
+
+def bicgstab_l(fat, lng, b, dims, mass, l=4, tol=1e-10, maxiter=100000, x0=None, lib=None, on_mr=None):
+    """FP64 BiCGStab(l) (Sleijpen and Fokkema 1993, the method Sec. 5.1 runs in
+    mixed precision) for M x = b on the whole lattice, M = 2m + D.
+    Each cycle: l BiCG steps (building u_0..u_l and r_0..r_l with one shadow
+    residual), then the minimal-residual step over r_1..r_l by modified
+    Gram-Schmidt.  Inner products <a, b> = a^H b.  Returns (x, matvecs, true
+    relative residual, status 0 converged / 1 iteration cap / 2 breakdown).
+    on_mr(r0, rhat): test hook called after every minimal-residual step with the
+    new r_0 and the orthogonalised r_1..r_l."""
+    b = _arr(b, np.complex128)
+    M = lambda v: full_op(fat, lng, v, dims, mass, lib)
+    x = np.zeros_like(b) if x0 is None else _arr(x0, np.complex128).copy()
+    r = [b - M(x)] + [np.zeros_like(b) for _ in range(l)]
+    u = [np.zeros_like(b) for _ in range(l + 1)]
+    rt = r[0].copy()
+    rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros_like(b), 0, 0.0, 0
+    k = 0
+    status = 1
+    while k < maxiter:
+        if np.linalg.norm(r[0]) <= tol * bn:
+            status = 0
+            break
+        rho0 = -omega * rho0
+        # BiCG part
+        for j in range(l):
+            rho1 = np.vdot(rt, r[j])
+            if rho0 == 0:
+                return x, k, np.linalg.norm(b - M(x)) / bn, 2
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = M(u[j])
+            gam = np.vdot(rt, u[j + 1])
+            if gam == 0:
+                return x, k, np.linalg.norm(b - M(x)) / bn, 2
+            alpha = rho0 / gam
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = M(r[j])
+            x = x + alpha * u[0]
+            k += 2
+        # minimal-residual part
+        tau = np.zeros((l + 1, l + 1), dtype=np.complex128)
+        sigma = np.zeros(l + 1)
+        gp = np.zeros(l + 1, dtype=np.complex128)
+        for j in range(1, l + 1):
+            for i in range(1, j):
+                tau[i, j] = np.vdot(r[i], r[j]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = np.vdot(r[j], r[j]).real
+            if sigma[j] == 0.0:
+                return x, k, np.linalg.norm(b - M(x)) / bn, 2
+            gp[j] = np.vdot(r[j], r[0]) / sigma[j]
+        g = np.zeros(l + 1, dtype=np.complex128)
+        g[l] = gp[l]
+        omega = g[l]
+        for j in range(l - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, l + 1))
+        gpp = np.zeros(l + 1, dtype=np.complex128)
+        for j in range(1, l):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, l))
+        x = x + g[1] * r[0]
+        r[0] = r[0] - gp[l] * r[l]
+        u[0] = u[0] - g[l] * u[l]
+        for j in range(1, l):
+            u[0] = u[0] - g[j] * u[j]
+            x = x + gpp[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+        if on_mr is not None:
+            on_mr(r[0], r[1:])
+    res = np.linalg.norm(b - M(x)) / bn
+    return x, k, res, status
+
+
 # ---------------------------------------------------------------------------
 # storage codecs (per-site records)
 # ---------------------------------------------------------------------------

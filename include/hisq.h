@@ -276,6 +276,30 @@ hisq_status hisq_multishift_cg_solve(double *const *x, const double *b, const do
                                      const hisq_solver_params *p, void *ws, size_t ws_bytes,
                                      hisq_solver_stats *stats, void *stream);
 
+/* Workspace bytes for hisq_bicgstab_solve (0 for unsupported arguments). */
+#define HISQ_MAX_BICGSTAB_L 8
+size_t hisq_bicgstab_workspace_bytes(const int dims[4], int l, hisq_fmt sloppy);
+
+/* Mixed-precision BiCGStab(l) (Sec. 5.1, the solver of Sleijpen and Fokkema)
+ * for M x = b on the WHOLE lattice, M = 2m + D (D the HISQ Dslash of both
+ * parities; M^dag M restricted to even sites is the CG operator above).
+ * x, b: (device) canonical complex128 [V][3], all sites in lexicographic order
+ * (x: initial guess in, solution out).  The Krylov vectors r_0..r_l, u_0..u_l
+ * and the shadow residual are stored in the sloppy triplet (links gs); the
+ * solution is accumulated in FP64; a reliable update replaces r_0 by b - M x
+ * from the FP64 operator (links g64) whenever |r_0| drops below p->delta times
+ * its maximum since the previous one, or meets tol.  Converged when the FP64
+ * true residual |b - M x| <= tol |b|.  1 <= l <= HISQ_MAX_BICGSTAB_L, mass > 0.
+ * stats: iters = operator applications (2 per BiCG step), reliable_updates,
+ * true_resid, seconds.  p->maxiter bounds the operator applications
+ * (HISQ_ENOCONV beyond, x is the last iterate); HISQ_EBREAKDOWN when a BiCG
+ * or minimal-residual denominator vanishes.  Runs on `stream`, which it
+ * synchronises for every scalar. */
+hisq_status hisq_bicgstab_solve(double *x, const double *b, const hisq_gauge *g64, const hisq_gauge *gs,
+                                double mass, double tol, int l, hisq_fmt sloppy,
+                                const hisq_solver_params *p, void *ws, size_t ws_bytes,
+                                hisq_solver_stats *stats, void *stream);
+
 /* Workspace bytes for hisq_cg_solve_batched. */
 size_t hisq_cg_batched_workspace_bytes(const int dims[4], int nrhs, hisq_fmt sloppy,
                                        const hisq_solver_params *p);

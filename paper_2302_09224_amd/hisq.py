@@ -136,6 +136,8 @@ def load():
         "hisq_multishift_cg_solve": (i, [ctypes.POINTER(vp), vp, ctypes.POINTER(d), i, ctypes.POINTER(d), G, G, G,
                                          d, hisq_fmt, hisq_fmt, P, vp, sz, S, vp]),
         "hisq_cg_batched_workspace_bytes": (sz, [ip, i, hisq_fmt, P]),
+        "hisq_bicgstab_workspace_bytes": (sz, [ip, i, hisq_fmt]),
+        "hisq_bicgstab_solve": (i, [vp, vp, G, G, d, d, i, hisq_fmt, P, vp, sz, S, vp]),
         "hisq_cg_solve_batched": (i, [vp, vp, i, G, G, d, d, d, hisq_fmt, P, vp, sz, S, vp]),
         "hisq_last_error": (ctypes.c_char_p, []),
         "hisq_version": (ctypes.c_char_p, []),
@@ -413,6 +415,30 @@ def multishift_cg_solve(b, shifts, tol, g64, g_ms, g_ref, mass, ms_fmt="single",
     if status not in (0, -4):
         _check(status, "hisq_multishift_cg_solve")
     return xs, st.as_dict()
+
+
+def hisq_bicgstab_workspace_bytes(dims, l, sloppy):
+    return load().hisq_bicgstab_workspace_bytes(_dims(dims), int(l), sloppy)
+
+
+def bicgstab_solve(b, g64, gs, mass, tol=1e-10, l=4, sloppy="single", x0=None, **params):
+    """mixed-precision BiCGStab(l) for (2m + D) x = b on the whole lattice;
+    b complex128 [V,3] (all sites, lexicographic); returns (x, stats dict)"""
+    f = fmt(sloppy)
+    p = _solver_params(**params)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    nbytes = hisq_bicgstab_workspace_bytes(g64.dims, l, f)
+    if nbytes == 0:
+        raise HisqError(-1, "hisq_bicgstab_workspace_bytes", "unsupported arguments")
+    ws = _empty_bytes(nbytes, b.device)
+    st = hisq_solver_stats()
+    status = load().hisq_bicgstab_solve(_ptr(torch.view_as_real(x)), _ptr(torch.view_as_real(b.contiguous())),
+                                        ctypes.byref(g64.desc), ctypes.byref(gs.desc), float(mass), float(tol),
+                                        int(l), f, ctypes.byref(p), _ptr(ws), nbytes, ctypes.byref(st),
+                                        _stream(None))
+    if status not in (0, -4):
+        _check(status, "hisq_bicgstab_solve")
+    return x, st.as_dict()
 
 
 def cg_solve_batched(b, g64, gs, mass, shift=0.0, tol=1e-10, sloppy="half", x0=None, **params):

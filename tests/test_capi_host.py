@@ -54,6 +54,9 @@ def test_sizes(hisq):
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("half"), p) > 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(2, 1, 32), p) == 0   # unsupported triplet
     assert hisq.hisq_multishift_workspace_bytes(dims, 33, hisq.fmt("single"), hisq.fmt("half"), p) == 0
+    assert hisq.hisq_bicgstab_workspace_bytes(dims, 4, hisq.fmt("int20")) > 0
+    assert hisq.hisq_bicgstab_workspace_bytes(dims, 0, hisq.fmt("int20")) == 0
+    assert hisq.hisq_bicgstab_workspace_bytes(dims, 9, hisq.fmt("int20")) == 0
     assert p.batch_refine == 1
     wb = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
     p.batch_refine = 0

@@ -1,0 +1,77 @@
+"""Mixed-precision BiCGStab(l) (Sec. 5.1) for M x = b, M = 2m + D on the whole
+lattice, against the oracle: the FP64 true residual of the GPU solution with
+the oracle's operator, and the oracle's FP64 BiCGStab(4) solution (the
+solution is unique; M has eigenvalues 2m + i*lambda)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import need_gpu
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def system(dims, kind, mass):
+    key = (dims, kind, mass)
+    if key not in _cache:
+        fat, lng = inputs.make_links(dims, kind, seed=inputs.GAUGE_SEED + 80)
+        b = inputs.gaussian_spinor(oracle.volume(dims), inputs.SOURCE_SEED + 80).numpy()
+        xo, k, res, st = oracle.bicgstab_l(fat.numpy(), lng.numpy(), b, dims, mass, l=4, tol=1e-12)
+        assert st == 0
+        _cache[key] = (fat, lng, b, xo)
+    return _cache[key]
+
+
+def residual(fat, lng, x, b, dims, mass):
+    return np.linalg.norm(b - oracle.full_op(fat.numpy(), lng.numpy(), x, dims, mass)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("sloppy", ["double", "single", "int30", "int30_fp32", "int20", "half"])
+@pytest.mark.parametrize("dims,kind,mass", [((8, 8, 8, 8), "near_unit", 0.05), ((6, 8, 10, 12), "haar", 0.1)])
+def test_bicgstab4(sloppy, dims, kind, mass):
+    hisq = need_gpu()
+    fat, lng, b, xo = system(dims, kind, mass)
+    f = hisq.fmt(sloppy)
+    g64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    gs = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    x, st = hisq.bicgstab_solve(torch.from_numpy(b).cuda(), g64, gs, mass, tol=1e-10, l=4, sloppy=sloppy)
+    assert st["status"] == "HISQ_OK", st
+    x = x.cpu().numpy()
+    res = residual(fat, lng, x, b, dims, mass)
+    assert res <= 1e-10 * (1 + 1e-6), (res, st)
+    assert abs(res - st["true_resid"]) <= 1e-3 * res + 1e-16
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+
+
+@pytest.mark.parametrize("l", [1, 2, 8])
+def test_bicgstab_l(l):
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng, b, xo = system(dims, "near_unit", mass)
+    g64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    gs = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16, long_recon=12)
+    x, st = hisq.bicgstab_solve(torch.from_numpy(b).cuda(), g64, gs, mass, tol=1e-10, l=l, sloppy="int20")
+    assert st["status"] == "HISQ_OK", st
+    assert residual(fat, lng, x.cpu().numpy(), b, dims, mass) <= 1e-10 * (1 + 1e-6)
+
+
+def test_bicgstab_guess_zero_rhs_and_cap():
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng, b, xo = system(dims, "near_unit", mass)
+    g64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
+    gs = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F32)
+    bt = torch.from_numpy(b).cuda()
+    x, st = hisq.bicgstab_solve(bt, g64, gs, mass, tol=1e-10, sloppy="single", x0=torch.from_numpy(xo).cuda())
+    assert st["status"] == "HISQ_OK" and st["iters"] == 0
+    x, st = hisq.bicgstab_solve(torch.zeros_like(bt), g64, gs, mass, tol=1e-10, sloppy="single",
+                                x0=torch.ones_like(bt))
+    assert st["status"] == "HISQ_OK" and float(x.abs().max()) == 0.0
+    x, st = hisq.bicgstab_solve(bt, g64, gs, mass, tol=1e-12, sloppy="single", maxiter=16)
+    assert st["status"] == "HISQ_ENOCONV" and st["iters"] >= 16
+    res = residual(fat, lng, x.cpu().numpy(), b, dims, mass)
+    assert res < 1.0 and abs(res - st["true_resid"]) <= 1e-3 * res

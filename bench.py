@@ -192,6 +192,40 @@ def bench_cg_stability(hisq, inputs, torch, dev, dims=(16, 16, 16, 16), masses=(
     return out
 
 
+def bench_bicgstab(hisq, inputs, torch, dev, dims, mass, kind="near_unit", tol=1e-10, l=4, maxiter=200000):
+    """Table 2 analog (Sec. 5.1): BiCGStab(4) for the whole-lattice operator
+    2m + D in pure double and double-{single, int30, int20, half}."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
+    b = inputs.gaussian_spinor(V, inputs.SOURCE_SEED + 90, device=dev)
+    g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+    del fat, lng
+    out = {}
+    for name in ("double", "single", "int30", "int20", "half"):
+        f = hisq.fmt(name)
+        gs = g64 if name == "double" else _pack_like(hisq, inputs, dims, f.gauge, dev, kind)
+        kw = dict(delta=0.0) if name == "double" else {}
+        hisq.bicgstab_solve(b, g64, gs, mass, tol=tol, l=l, sloppy=name, maxiter=16, **kw)   # tune the shapes
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = hisq.bicgstab_solve(b, g64, gs, mass, tol=tol, l=l, sloppy=name, maxiter=maxiter, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[f"double-{name}" if name != "double" else "pure double"] = dict(
+            status=st["status"], operator_applications=st["iters"], reliable_updates=st["reliable_updates"],
+            true_resid=st["true_resid"], seconds=round(dt, 3))
+        log(f"[bench] BiCGStab({l}) {dims} {kind} m={mass} {name}: {st['iters']} applications, {dt:.2f}s, "
+            f"resid {st['true_resid']:.2e} ({st['status']})")
+        del gs
+        torch.cuda.empty_cache()
+    return dict(lattice=list(dims), links=kind, mass=mass, tol=tol, l=l, solvers=out)
+
+
+def _pack_like(hisq, inputs, dims, gf, dev, kind):
+    fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
+    return hisq.pack_gauge(fat, lng, dims, gf, long_recon=12)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +243,10 @@ def main():
                     help="refine the shifted systems together (1) or one after another (0)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-alt", action="store_true", help="skip the double-single-half mixed solve")
+    ap.add_argument("--bicgstab", type=str, default=None, metavar="X,Y,Z,T",
+                    help="also run the BiCGStab(4) precision comparison on this lattice (see --bicgstab-mass)")
+    ap.add_argument("--bicgstab-mass", type=float, default=0.001)
+    ap.add_argument("--bicgstab-links", type=str, default="near_unit", choices=("near_unit", "haar"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
@@ -296,6 +334,10 @@ def main():
         batched = bench_batched(args, hisq, inputs, torch, dev)
     multi = bench_multi(hisq, inputs, torch, dev)
     stability = None if args.kernels_only else bench_cg_stability(hisq, inputs, torch, dev)
+    bicg = None
+    if args.bicgstab:
+        bicg = bench_bicgstab(hisq, inputs, torch, dev, tuple(int(v) for v in args.bicgstab.split(",")),
+                              args.bicgstab_mass, args.bicgstab_links)
     if args.kernels_only:
         tuning = hisq.hisq_tune_report().strip().splitlines()
         print(json.dumps(dict(kernels=kernels, batched=batched, multi_lattice=multi, tuning=tuning,
@@ -459,6 +501,7 @@ def main():
         "batched": batched,
         "multi_lattice": multi,
         "cg_stability": stability,
+        "bicgstab": bicg,
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,

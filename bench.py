@@ -109,6 +109,43 @@ def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16
     return out
 
 
+def bench_batched_cg(hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, mass=0.01, tol=1e-10):
+    """16 right-hand sides on 32^3x64: one batched mixed-precision CG (FIX16/INT20
+    sloppy, two-row long links; every Dslash shared by the block) against 16
+    independent FP64 CG solves; solves per second of each."""
+    import numpy as np
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 4, device=dev)
+    bs = inputs.gaussian_spinor(V // 2, inputs.RHS_SEED, device=dev, nrhs=nrhs)
+    g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+    gs = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_FIX16, long_recon=12)
+    del fat, lng
+    hisq.cg_solve_batched(bs, g64, gs, mass, tol=tol, sloppy="int20")          # warm-up (launch shapes)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, sb = hisq.cg_solve_batched(bs, g64, gs, mass, tol=tol, sloppy="int20")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    hisq.cg_solve(bs[0], g64, g64, mass, tol=tol, sloppy="double", delta=0.0)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    iters64 = []
+    for j in range(nrhs):
+        _, s64 = hisq.cg_solve(bs[j], g64, g64, mass, tol=tol, sloppy="double", delta=0.0)
+        iters64.append(s64["iters"])
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t
+    out = dict(lattice=list(dims), nrhs=nrhs, mass=mass, tol=tol, batched_triplet="fix16/int20/fp32",
+               batched_seconds=round(tb, 3), batched_iters=sb["iters"], batched_resid_max=max(sb["shift_resid"][:nrhs]),
+               fp64_seconds=round(t64, 3), fp64_iters_mean=float(np.mean(iters64)),
+               solves_per_s_batched=round(nrhs / tb, 2), solves_per_s_fp64=round(nrhs / t64, 2),
+               speedup=round(t64 / tb, 2))
+    log(f"[bench] batched CG {out}")
+    del g64, gs, bs
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_multi(hisq, inputs, torch, dev, reps=50):
     """8^4 + 12^4 + 16^4 + 24^4 in one launch against one launch per lattice
     (HIP events; FIX16/INT20/FP32, two-row long links)."""
@@ -333,6 +370,7 @@ def main():
     if args.batched:
         batched = bench_batched(args, hisq, inputs, torch, dev)
     multi = bench_multi(hisq, inputs, torch, dev)
+    batched_cg = None if args.kernels_only else bench_batched_cg(hisq, inputs, torch, dev)
     stability = None if args.kernels_only else bench_cg_stability(hisq, inputs, torch, dev)
     bicg = None
     if args.bicgstab:
@@ -500,6 +538,7 @@ def main():
         "kernels": kernels,
         "batched": batched,
         "multi_lattice": multi,
+        "batched_cg": batched_cg,
         "cg_stability": stability,
         "bicgstab": bicg,
         "tuning": tuning,

@@ -209,7 +209,9 @@ def bench_cg_stability(hisq, inputs, torch, dev, dims=(16, 16, 16, 16), masses=(
         row = {}
         for name, gs, sl, kw in (("double", g64, "double", dict(delta=0.0)),
                                  ("double-half naive", g16, "half", dict(pr_beta=0, reproject=0)),
-                                 ("double-half stabilised", g16, "half", {})):
+                                 ("double-half stabilised", g16, "half", {}),
+                                 ("double-half stabilised, error-estimate updates", g16, "half",
+                                  dict(ru_estimate=1))):
             torch.cuda.synchronize()
             t = time.perf_counter()
             try:

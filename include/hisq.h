@@ -202,6 +202,11 @@ typedef struct {
                             <= 0 selects the sloppy format's epsilon */
     int batch_refine;    /* multi-shift: refine the shifted systems together, one Dslash per iteration shared
                             by up to 16 of them (1), or one after another (0); the base is always refined first */
+    int ru_estimate;     /* CG and the multi-shift base: 0 = reliable update when |r| drops below delta times its
+                            maximum since the last one; 1 = when an estimate of |r_true - r_iterated| (each
+                            iteration's sloppy roundoff, accumulated in quadrature: residual replacement in the
+                            manner of van der Vorst and Ye; Sec. 3 footnote) crosses sqrt(eps_sloppy) |r|.  The batched CG and BiCGStab
+                            use the delta rule. */
 } hisq_solver_params;
 
 typedef struct {
@@ -223,7 +228,7 @@ typedef struct {
 } hisq_solver_stats;
 
 /* Default parameters: delta 0.1, maxiter 100000, grad_buffer 4, PR beta,
- * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 1. */
+ * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 1, ru_estimate 0. */
 void hisq_solver_params_default(hisq_solver_params *p);
 
 /* Workspace bytes for hisq_cg_solve on `dims` with sloppy format `sloppy`. */

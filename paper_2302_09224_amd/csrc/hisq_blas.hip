@@ -354,9 +354,12 @@ __global__ void k_cg_axpy(char *r, const char *ap, const double *alpha, size_t n
 }
 
 template <int SF, class R>
-__global__ void k_cg_pupdate(char *pd, const char *r, const char *ps, const SolverCtrl *ctrl, size_t n, Guard gd) {
+__global__ void k_cg_pupdate(char *pd, const char *r, const char *ps, const SolverCtrl *ctrl, size_t n, double *ppart,
+                             Guard gd) {
+    __shared__ double lds[8];
     if (!gd.pass()) return;
     const R ar = (R)ctrl->pa_re, ai = (R)ctrl->pa_im, b = (R)ctrl->pb;
+    double acc[1] = {0.0};
     for (size_t s = gtid(); s < n; s += gstride()) {
         CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
         CVec<R> pv = SpinorIO<SF, R>::load(ps, n, s);
@@ -366,7 +369,15 @@ __global__ void k_cg_pupdate(char *pd, const char *r, const char *ps, const Solv
             o.re[c] = fma(ar, rv.re[c], fma(-ai, rv.im[c], b * pv.re[c]));
             o.im[c] = fma(ar, rv.im[c], fma(ai, rv.re[c], b * pv.im[c]));
         }
-        SpinorIO<SF, R>::store(pd, n, s, o);
+        const CVec<R> st = SpinorIO<SF, R>::store(pd, n, s, o);
+        if (ppart) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[0] += (double)st.re[c] * st.re[c] + (double)st.im[c] * st.im[c];
+        }
+    }
+    if (ppart) {
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) ppart[blockIdx.x] = acc[0];
     }
 }
 
@@ -757,9 +768,10 @@ hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n
     return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, size_t n, int sf,
+hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, double *ppart,
+                             size_t n, int sf,
                              int compute, Guard gd, hipStream_t st) {
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_pupdate<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, p_dst, r, p_src, ctrl, n, gd));
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_pupdate<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, p_dst, r, p_src, ctrl, n, ppart, gd));
     return hipGetLastError();
 }
 

@@ -175,6 +175,13 @@ struct SolverCtrl {
     double r2_true;  // |b - A x|^2 at the last true-residual computation
     double alpha_prev, beta_prev;
     double floor2;   // multi-shift: sloppy floor^2
+    // error-estimate trigger of the reliable updates (instead of the fixed delta)
+    int ru_est;
+    int pad1;
+    double eps_s;       // unit roundoff of the sloppy format
+    double anorm;       // running estimate of |A| (largest Rayleigh quotient pAp/|p|^2 seen)
+    double dev, dev_init;   // estimated |r_true - r_iterated| and its value after the last update
+    double rnorm_prev;      // |r| of the previous iteration
     double alpha_buf[HISQ_MAX_GRAD_BUFFER];
     double sh[HISQ_MAX_SHIFTS];       // shift_i - shift_0
     double tol2_i[HISQ_MAX_SHIFTS];
@@ -206,7 +213,8 @@ struct SpinorList {
 hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, int sf, int compute,
                           double *partial, Guard gd, hipStream_t st);
 // p_dst = pa*r + pb*p_src, (pa, pb) from the control block
-hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl,
+// (ppart: optional per-block |p_dst|^2 of the stored values)
+hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, double *ppart,
                              size_t n, int sf, int compute, Guard gd, hipStream_t st);
 // x64 += sum_i alpha_buf[i] p_i, i < count
 hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const double *alpha_buf, size_t n,

@@ -79,11 +79,14 @@ __global__ void k_fin_alpha(SolverCtrl *c, const double *partial, int n, int jb,
 }
 
 // beta and the decisions of one iteration; multi-shift: zeta recurrences
-__global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd, int multishift, int jb) {
-    __shared__ double lds[32];
+__global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd, int multishift, int jb,
+                           const double *ppart, int npp) {
+    __shared__ double lds[32], lds2[16];
     if (!gd.pass()) return;
     double v[2];
     fin_sums<2>(partial, n, v, lds);
+    double pv[1] = {0.0};   // |p_k|^2 from the update that produced p_k
+    if (c->ru_est) fin_sums<1>(ppart, npp, pv, lds2);
     if (threadIdx.x) return;
     const double rn = v[0], g = v[1];
     const int k = c->k + 1;
@@ -131,8 +134,27 @@ __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd
         if ((amask & ~1) == 0) reason = STOP_MSDONE;
     }
     c->rmax2 = fmax(c->rmax2, rn);
+    bool ru;
+    if (c->ru_est) {
+        // Error estimate of the iterated residual (residual replacement in the manner of
+        // van der Vorst and Ye): each sloppy update r -= alpha A p makes an error of about
+        // eps_s (|r| + |alpha| |A| |p|); the errors of successive iterations are independent,
+        // so they are accumulated in quadrature.  A reliable update is due when the estimate
+        // crosses sqrt(eps_s) |r| from below and has grown past 1.1x its value after the
+        // previous update.
+        const double rnorm = sqrt(rn);
+        if (pv[0] > 0.0) c->anorm = fmax(c->anorm, c->pi / pv[0]);
+        const double e = c->eps_s * (rnorm + fabs(c->alpha) * c->anorm * sqrt(pv[0]));
+        const double dnew = sqrt(c->dev * c->dev + e * e);
+        const double th = sqrt(c->eps_s);
+        ru = c->dev <= th * c->rnorm_prev && dnew > th * rnorm && dnew > 1.1 * c->dev_init;
+        c->dev = dnew;
+        c->rnorm_prev = rnorm;
+    } else {
+        ru = c->delta2 > 0.0 && rn < c->delta2 * c->rmax2;
+    }
     if (reason == STOP_NONE) {
-        if (c->delta2 > 0.0 && rn < c->delta2 * c->rmax2)
+        if (ru)
             reason = STOP_RU;
         else if (!multishift && rn <= c->tol2 * c->b2)
             reason = STOP_CONV;
@@ -190,6 +212,8 @@ __global__ void k_fin_ru_finish(SolverCtrl *c, const double *partial, int n, int
     c->beta = beta;
     c->rho = rho;
     c->rmax2 = rho;
+    c->dev = c->dev_init = c->eps_s * sqrt(rho);   // rounding of the freshly stored residual
+    c->rnorm_prev = sqrt(rho);
     c->reason = STOP_NONE;
     c->stop = STOP_NEVER;
 }
@@ -246,6 +270,7 @@ size_t partial_doubles(const Geom &g, int nrhs) {
 struct CgBuffers {
     SolverCtrl *ctrl;
     double *partial;
+    double *ppart;                     // per-block |p|^2 of the last p update
     char *x64, *b64, *r64, *t64;
     char *rs, *aps, *ts;
     char *p[HISQ_MAX_GRAD_BUFFER];
@@ -265,6 +290,7 @@ size_t carve_cg(CgBuffers *b, char *base, const Geom &g, int sloppy_bytes, int n
     CgBuffers &B = b ? *b : tmp;
     B.ctrl = (SolverCtrl *)cv.take(sizeof(SolverCtrl));
     B.partial = (double *)cv.take(partial_doubles(g, 1) * sizeof(double));
+    B.ppart = (double *)cv.take((size_t)BLAS_MAX_BLOCKS * sizeof(double));
     B.x64 = cv.take(48 * vh);
     B.b64 = cv.take(48 * vh);
     B.r64 = cv.take(48 * vh);
@@ -368,7 +394,7 @@ struct Run {
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_cg_axpy(B->rs, B->aps, &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), gns,
-                           multishift ? 1 : 0, jb);
+                           multishift ? 1 : 0, jb, B->ppart, blas_blocks(vh));
         HISQ_TRY_HIP(hipGetLastError());
         if (multishift) {
             SpinorList xl, pl;
@@ -384,7 +410,7 @@ struct Run {
             for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;
             HISQ_TRY_HIP(launch_flush_x(B->x64, pl, nb, c->alpha_buf, vh, fmt.spinor, fmt.compute, gs_, st));
         }
-        HISQ_TRY_HIP(launch_cg_pupdate(B->p[jn], B->rs, B->p[jb], c, vh, fmt.spinor, fmt.compute, gs_, st));
+        HISQ_TRY_HIP(launch_cg_pupdate(B->p[jn], B->rs, B->p[jb], c, B->ppart, vh, fmt.spinor, fmt.compute, gs_, st));
         return HISQ_OK;
     }
     double c_ = 0.0;
@@ -443,7 +469,8 @@ struct Run {
                                        &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, g0, st));
         hipLaunchKernelGGL(k_fin_ru_finish, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), mode, g0);
         HISQ_TRY_HIP(hipGetLastError());
-        HISQ_TRY_HIP(launch_cg_pupdate(B->p[0], B->rs, mode == 1 ? B->rs : p_src, c, vh, fmt.spinor, fmt.compute, g0, st));
+        HISQ_TRY_HIP(launch_cg_pupdate(B->p[0], B->rs, mode == 1 ? B->rs : p_src, c, B->ppart, vh, fmt.spinor,
+                                       fmt.compute, g0, st));
         const double bs = spinor_site_bytes(fmt.spinor);
         alg_bytes += vh * (48.0 + 5 * bs) + vh * 3 * bs;
         return HISQ_OK;
@@ -543,8 +570,10 @@ struct Run {
     }
 };
 
-void init_ctrl(SolverCtrl *h, const hisq_solver_params &p, double tol, double b2) {
+void init_ctrl(SolverCtrl *h, const hisq_solver_params &p, double tol, double b2, int sloppy_spinor) {
     memset(h, 0, sizeof(*h));
+    h->ru_est = p.ru_estimate;
+    h->eps_s = std::ldexp(1.0, -sloppy_floor_bits(sloppy_spinor));
     h->stop = STOP_NEVER;
     h->pr = p.pr_beta;
     h->reproject = p.reproject;
@@ -565,6 +594,7 @@ hisq_status check_params(const hisq_solver_params *p, hisq_solver_params *out) {
         return set_error(HISQ_EINVAL, "grad_buffer must be in [1,%d]", HISQ_MAX_GRAD_BUFFER);
     if (out->poll_every <= 0) out->poll_every = d.poll_every;
     if (out->batch_refine != 0 && out->batch_refine != 1) return set_error(HISQ_EINVAL, "batch_refine must be 0 or 1");
+    if (out->ru_estimate != 0 && out->ru_estimate != 1) return set_error(HISQ_EINVAL, "ru_estimate must be 0 or 1");
     return HISQ_OK;
 }
 
@@ -612,7 +642,7 @@ hisq_status enq_b2(Run &R) {
 // continue the gradient vector p_init (refinement format) with rho_prev.
 hisq_status cg_core(Run &R, const hisq_solver_params &p, double tol, int mode, const char *p_init, double rho_prev,
                     SolverCtrl *h, double *resid0) {
-    init_ctrl(h, p, tol, 0.0);
+    init_ctrl(h, p, tol, 0.0, R.fmt.spinor);
     h->rho_prev = rho_prev;
     HISQ_TRY_HIP(hipMemcpyAsync(R.B->ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, R.st));
     R.setup_plans();
@@ -669,6 +699,7 @@ extern "C" void hisq_solver_params_default(hisq_solver_params *p) {
     p->use_graph = 1;
     p->shift_floor = 0.0;
     p->batch_refine = 1;
+    p->ru_estimate = 0;
 }
 
 extern "C" size_t hisq_cg_workspace_bytes(const int dims[4], hisq_fmt sloppy, const hisq_solver_params *p) {
@@ -815,7 +846,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         R.B = &B;
         R.st = s_;
         R.ds = E.ds;
-        init_ctrl(h, q, tol[0], 0.0);
+        init_ctrl(h, q, tol[0], 0.0, ms_fmt.spinor);
         h->nshift = nshift;
         const double fl = q.shift_floor > 0 ? q.shift_floor : std::ldexp(1.0, -sloppy_floor_bits(ms_fmt.spinor));
         h->floor2 = fl * fl;

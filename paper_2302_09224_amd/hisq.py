@@ -54,7 +54,8 @@ RECON_18, RECON_12 = 18, 12
 class hisq_solver_params(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("maxiter", ctypes.c_int), ("grad_buffer", ctypes.c_int),
                 ("pr_beta", ctypes.c_int), ("reproject", ctypes.c_int), ("poll_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("shift_floor", ctypes.c_double), ("batch_refine", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("shift_floor", ctypes.c_double), ("batch_refine", ctypes.c_int),
+                ("ru_estimate", ctypes.c_int)]
 
 
 class hisq_solver_stats(ctypes.Structure):

@@ -69,6 +69,9 @@ def test_sizes(hisq):
     assert a == hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
     p.batch_refine = 2
     assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == 0
+    p.batch_refine = 1
+    p.ru_estimate = 2
+    assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == 0
 
 
 def test_argument_errors(hisq):

@@ -198,3 +198,32 @@ def test_batched_cg(sloppy, nrhs):
     for j in range(nrhs):
         res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x[j]), full(dims, ev, bs[j]), dims, mass)
         assert res <= 1e-10 * (1 + 1e-6), (j, res)
+
+
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "int30"])
+def test_cg_error_estimate_reliable_updates(sloppy):
+    """reliable updates triggered by the residual-deviation estimate instead of delta"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.02
+    fat, lng, ev, b = setup(dims, "haar")
+    pg = packed(hisq, fat, lng, dims, ["double", sloppy])
+    x, st = hisq.cg_solve(torch.from_numpy(b).cuda(), pg[0], pg[hisq.fmt(sloppy).gauge], mass, tol=1e-10,
+                          sloppy=sloppy, ru_estimate=1)
+    assert st["status"] == "HISQ_OK" and st["reliable_updates"] >= 1, st
+    res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x.cpu().numpy()), full(dims, ev, b), dims, mass)
+    assert res <= 1e-10 * (1 + 1e-6), (res, st)
+
+
+def test_multishift_error_estimate_reliable_updates():
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    shifts = [1e-4, 1e-2, 1.0]
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "int30", "int20"])
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, [1e-10] * 3, pg[0], pg[3], pg[2], mass,
+                                      ms_fmt="int30", ref_fmt="int20", ru_estimate=1)
+    assert st["status"] == "HISQ_OK", st
+    for i, s in enumerate(shifts):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[i].cpu().numpy()), full(dims, ev, b),
+                                   dims, mass, s)
+        assert res <= 1e-10 * (1 + 1e-6), (i, res)

@@ -56,7 +56,11 @@ enum {
     HISQ_SPINOR_F32 = 1,     /* IEEE FP32, 24 B/site */
     HISQ_SPINOR_HALF16 = 2,  /* QUDA half: 6 x int16 + FP32 site max, 16 B/site (Sec. 2, Listing 1) */
     HISQ_SPINOR_INT20 = 3,   /* 6 x 20-bit + 8-bit shared exponent, 16 B/site (Sec. 4, Listing 2, App. A) */
-    HISQ_SPINOR_INT30 = 4    /* 6 x 30-bit + 8-bit shared exponent, 24 B/site (Sec. 4, Listing 3) */
+    HISQ_SPINOR_INT30 = 4,   /* 6 x 30-bit + 8-bit shared exponent, 24 B/site (Sec. 4, Listing 3) */
+    HISQ_SPINOR_INT24 = 5    /* 6 x 24-bit + 8-bit shared exponent, 20 B/site: a member of the
+                                Sec. 4 family generated from the same rule (FP32 encode, the
+                                Appendix A word allocation); words 0-3 in a 16-B plane, word 4
+                                in a 4-B plane after it.  Paired with FIX32 links, FP32 compute. */
 };
 
 /* Gauge (link) storage formats. */
@@ -70,7 +74,7 @@ enum {
 /* Precision triplet gauge / fermion / compute of one stencil application
  * (Sec. 4).  compute is 32 (FP32) or 64 (FP64).  Supported triplets:
  *   F64/F64/64, F32/F32/32, FIX16/HALF16/32, FIX16/INT20/32,
- *   FIX32/INT30/64, FIX32/INT30/32. */
+ *   FIX32/INT30/64, FIX32/INT30/32, FIX32/INT24/32. */
 typedef struct {
     int gauge;
     int spinor;
@@ -131,9 +135,9 @@ hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void *long_dst,
 
 /* Pack `nsites` canonical FP64 colour vectors (device complex128 [nsites][3])
  * into `spinor_fmt` at dst (device, hisq_spinor_bytes bytes).
- * HALF16 and INT20 first round the values to FP32 (their compute precision),
- * INT30 works in FP64.  HALF16: per-site max M, q = rint(v * (32767/M)).
- * INT20/INT30: shared exponent E = (FP exponent of M/(2^(B-1)-1)) + 1,
+ * HALF16, INT20 and INT24 first round the values to FP32 (their compute
+ * precision), INT30 works in FP64.  HALF16: per-site max M, q = rint(v * (32767/M)).
+ * INT20/INT24/INT30: shared exponent E = (FP exponent of M/(2^(B-1)-1)) + 1,
  * q = rint(v * 2^(127-E)) (the packing of Appendix A; INT30 per Sec. 4). */
 hisq_status hisq_spinor_pack(void *dst, const double *src, long nsites, int spinor_fmt, void *stream);
 
@@ -165,7 +169,9 @@ hisq_status hisq_normal_op(void *out, const void *in, void *tmp, const hisq_gaug
 
 /* Batched Dslash (block of right-hand sides, Sec. 1 "Block solvers"): nrhs
  * consecutive packed fields in `in` and `out` (each hisq_spinor_bytes(Vh))
- * share one pass over the links.  1 <= nrhs <= 16. */
+ * share one pass over the links.  1 <= nrhs <= 16.  Every triplet but
+ * FIX32/INT30/32 (a refinement option only) has this form; that one gives
+ * HISQ_EINVAL. */
 hisq_status hisq_dslash_batched(void *out, const void *in, const hisq_gauge *g, int parity,
                                 hisq_fmt fmt, int nrhs, void *stream);
 

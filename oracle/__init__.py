@@ -377,6 +377,84 @@ def int30_decode(w, lib=None):
     return v
 
 
+# ---------------------------------------------------------------------------
+# the shared-exponent family (Sec. 4): the 20- and 30-bit spinors are two
+# members of one rule with component width B.  Written here once more in
+# numpy, independently of the C codecs above, so that B = 20 and B = 30 can
+# be checked against them (and through them against the worked examples of
+# Appendix A and Listing 3); B = 24 (20 bytes per site) is the generated member.
+# ---------------------------------------------------------------------------
+
+def shared_exponent_words(bits):
+    """32-bit words of one site record: six B-bit components and an 8-bit exponent"""
+    return (6 * bits + 8 + 31) // 32
+
+
+def _shared_exponent_fields(bits):
+    """(word, bit offset, width) of re0, im0, re1, im1, re2, im2, E: the fields
+    follow one another from the least significant bit of word 0 (Appendix A)"""
+    return [((f * bits) // 32, (f * bits) % 32, bits if f < 6 else 8) for f in range(7)]
+
+
+def shared_exponent_encode(v, bits):
+    """records uint32 [n, words] of colour vectors v in the B-bit member.
+    M = max |component| of the site; t = M / (2^(B-1) - 1); the stored exponent
+    E is the biased exponent of t plus one (t rounded up to a power of two),
+    clamped to [1, 254] (1 for t = 0); q = round-half-even(v * 2^(127-E)).  The
+    arithmetic is FP32 for B <= 24 (the input is first rounded to FP32, as for
+    the 20-bit format) and FP64 above (as for the 30-bit format).  A field that
+    crosses a word boundary keeps its high bits at the top of the earlier word
+    and its low bits at the bottom of the next one (Appendix A)."""
+    ft = np.float32 if bits <= 24 else np.float64
+    a = _reals6(v, ft)
+    m = np.abs(a).max(axis=1)
+    t = m / ft(2 ** (bits - 1) - 1)
+    _, ex = np.frexp(t)                        # t = f 2^ex, f in [1/2, 1): unbiased exponent ex - 1
+    e = np.where(t > 0, ex.astype(np.int64) + 127, 1).clip(1, 254)
+    inv = np.ldexp(ft(1.0), (127 - e).astype(np.int32)).astype(ft)
+    q = np.rint(a * inv[:, None]).astype(np.int64)
+    vals = [q[:, k] & ((1 << bits) - 1) for k in range(6)] + [e]
+    words = np.zeros((a.shape[0], shared_exponent_words(bits)), dtype=np.uint64)
+    for val, (k, off, width) in zip(vals, _shared_exponent_fields(bits)):
+        val = val.astype(np.uint64)
+        spill = off + width - 32               # bits that go to the next word
+        if spill <= 0:
+            words[:, k] |= val << np.uint64(off)
+        else:
+            words[:, k] |= (val >> np.uint64(spill)) << np.uint64(off)
+            words[:, k + 1] |= val & np.uint64((1 << spill) - 1)
+    return (words & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def shared_exponent_decode(w, bits):
+    """reals [n, 6] (FP32 for B <= 24, else FP64) of records of the B-bit member:
+    v = q * 2^(E-127) with q the B-bit two's-complement components"""
+    ft = np.float32 if bits <= 24 else np.float64
+    w = np.asarray(w, dtype=np.uint32).reshape(-1, shared_exponent_words(bits)).astype(np.uint64)
+    vals = []
+    for k, off, width in _shared_exponent_fields(bits):
+        spill = off + width - 32
+        if spill <= 0:
+            x = (w[:, k] >> np.uint64(off)) & np.uint64((1 << width) - 1)
+        else:
+            hi = (w[:, k] >> np.uint64(off)) & np.uint64((1 << (width - spill)) - 1)
+            x = (hi << np.uint64(spill)) | (w[:, k + 1] & np.uint64((1 << spill) - 1))
+        vals.append(x.astype(np.int64))
+    q = np.stack(vals[:6], axis=1)
+    q = np.where(q >= 2 ** (bits - 1), q - 2 ** bits, q)
+    scale = np.ldexp(ft(1.0), (vals[6] - 127).astype(np.int32)).astype(ft)
+    return q.astype(ft) * scale[:, None]
+
+
+def int24_encode(v, lib=None):
+    """24-bit shared-exponent spinor (generated member): uint32 [n,5]; FP32 input"""
+    return shared_exponent_encode(v, 24)
+
+
+def int24_decode(w, lib=None):
+    return shared_exponent_decode(w, 24)
+
+
 def field_absmax(u):
     """global max over the real and imaginary parts of a link field"""
     u = np.asarray(u)
@@ -419,7 +497,7 @@ def fix_decode(q, absmax, compute_bits, shape=None, lib=None):
 # storage emulation: what a field looks like after a round trip through a format
 # ---------------------------------------------------------------------------
 
-SPINOR_FORMATS = ("f64", "f32", "half16", "int20", "int30")
+SPINOR_FORMATS = ("f64", "f32", "half16", "int20", "int30", "int24")
 GAUGE_FORMATS = ("f64", "f32", "fix16", "fix32")
 
 
@@ -437,13 +515,15 @@ def spinor_roundtrip(v, fmt, lib=None):
         return _complex3(int20_decode(int20_encode(v, lib), lib))
     if fmt == "int30":
         return _complex3(int30_decode(int30_encode(v, lib), lib))
+    if fmt == "int24":
+        return _complex3(int24_decode(int24_encode(v)))
     raise ValueError(fmt)
 
 
 def spinor_decode_records(rec, fmt, lib=None):
     """per-site records of a format -> complex128 [n,3].
     rec: f64 complex [n,3]; f32 complex64 [n,3]; half16 (q [n,6], norm [n]);
-    int20 uint32 [n,4]; int30 uint32 [n,6]"""
+    int20 uint32 [n,4]; int30 uint32 [n,6]; int24 uint32 [n,5]"""
     if fmt in ("f64", "f32"):
         return np.asarray(rec).astype(np.complex128).reshape(-1, 3)
     if fmt == "half16":
@@ -453,6 +533,8 @@ def spinor_decode_records(rec, fmt, lib=None):
         return _complex3(int20_decode(rec, lib))
     if fmt == "int30":
         return _complex3(int30_decode(rec, lib))
+    if fmt == "int24":
+        return _complex3(int24_decode(rec))
     raise ValueError(fmt)
 
 
@@ -483,6 +565,8 @@ def spinor_quantum(v, fmt):
         return m * 2.0 ** -18
     if fmt == "int30":
         return m * 2.0 ** -28
+    if fmt == "int24":
+        return m * 2.0 ** -22
     raise ValueError(fmt)
 
 

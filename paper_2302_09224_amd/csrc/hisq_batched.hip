@@ -437,7 +437,7 @@ BDev g_bdev[64];
 }  // namespace
 
 bool batched_fmt_ok(const hisq_fmt &f) {
-    return triplet_ok(f) && !(f.gauge == HISQ_GAUGE_FIX32 && f.compute == 32);
+    return triplet_ok(f) && has_batched_form(f);
 }
 
 size_t batched_ws_bytes(const Geom &g, int nrhs, int sf, int nb) {

@@ -191,6 +191,7 @@ __global__ void k_bl_merge(double *dst, const char *src, Geom g, size_t fb64) {
         case SF_INT20 * 2 + 0: { constexpr int SFc = SF_INT20; typedef float Rc; CALL; } break;      \
         case SF_INT30 * 2 + 1: { constexpr int SFc = SF_INT30; typedef double Rc; CALL; } break;     \
         case SF_INT30 * 2 + 0: { constexpr int SFc = SF_INT30; typedef float Rc; CALL; } break;      \
+        case SF_INT24 * 2 + 0: { constexpr int SFc = SF_INT24; typedef float Rc; CALL; } break;      \
         default: return set_error(HISQ_EINVAL, "bicgstab: unsupported sloppy triplet");             \
         }                                                                                            \
     } while (0)

@@ -660,6 +660,7 @@ __global__ void k_bru_convert(char *rs, const char *r64, size_t fs64, const char
         case SF_INT20 * 2 + 0: { constexpr int SFc = SF_INT20; typedef float Rc; CALL; } break; \
         case SF_INT30 * 2 + 1: { constexpr int SFc = SF_INT30; typedef double Rc; CALL; } break; \
         case SF_INT30 * 2 + 0: { constexpr int SFc = SF_INT30; typedef float Rc; CALL; } break; \
+        case SF_INT24 * 2 + 0: { constexpr int SFc = SF_INT24; typedef float Rc; CALL; } break; \
         default: return hipErrorInvalidValue;                                         \
         }                                                                             \
     } while (0)
@@ -672,6 +673,7 @@ __global__ void k_bru_convert(char *rs, const char *r64, size_t fs64, const char
         case SF_HALF16: { constexpr int SFc = SF_HALF16; CALL; } break;              \
         case SF_INT20: { constexpr int SFc = SF_INT20; CALL; } break;                \
         case SF_INT30: { constexpr int SFc = SF_INT30; CALL; } break;                \
+        case SF_INT24: { constexpr int SFc = SF_INT24; CALL; } break;                \
         default: return hipErrorInvalidValue;                                         \
         }                                                                             \
     } while (0)
@@ -706,6 +708,7 @@ hipError_t launch_spinor_convert(char *dst, int sf_dst, const char *src, int sf_
     case SF_HALF16: return convert_from<SF_HALF16>(dst, src, sf_src, n, st);
     case SF_INT20: return convert_from<SF_INT20>(dst, src, sf_src, n, st);
     case SF_INT30: return convert_from<SF_INT30>(dst, src, sf_src, n, st);
+    case SF_INT24: return convert_from<SF_INT24>(dst, src, sf_src, n, st);
     default: return hipErrorInvalidValue;
     }
 }

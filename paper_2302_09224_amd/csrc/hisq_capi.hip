@@ -68,7 +68,8 @@ bool triplet_ok(const hisq_fmt &f) {
     case GF_FIX16 * 100 + SF_HALF16 * 10 + 0:
     case GF_FIX16 * 100 + SF_INT20 * 10 + 0:
     case GF_FIX32 * 100 + SF_INT30 * 10 + 1:
-    case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return true;
+    case GF_FIX32 * 100 + SF_INT30 * 10 + 0:
+    case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return true;
     default: return false;
     }
 }
@@ -156,7 +157,7 @@ extern "C" size_t hisq_gauge_bytes(const int dims[4], int gauge_fmt) {
 }
 
 extern "C" size_t hisq_spinor_bytes(long nsites, int spinor_fmt) {
-    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 4) return 0;
+    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 5) return 0;
     return spinor_field_bytes((size_t)nsites, spinor_fmt);
 }
 
@@ -251,7 +252,7 @@ extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void 
 
 extern "C" hisq_status hisq_spinor_pack(void *dst, const double *src, long nsites, int spinor_fmt, void *stream) {
     if (!dst || !src) return set_error(HISQ_EINVAL, "hisq_spinor_pack: null pointer");
-    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 4) return set_error(HISQ_EINVAL, "hisq_spinor_pack: bad size or format");
+    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 5) return set_error(HISQ_EINVAL, "hisq_spinor_pack: bad size or format");
     if (!aligned16(dst) || !aligned16(src)) return set_error(HISQ_EALIGN, "hisq_spinor_pack: unaligned pointer");
     HISQ_TRY_HIP(launch_spinor_pack((char *)dst, src, (size_t)nsites, spinor_fmt, (hipStream_t)stream));
     return HISQ_OK;
@@ -259,7 +260,7 @@ extern "C" hisq_status hisq_spinor_pack(void *dst, const double *src, long nsite
 
 extern "C" hisq_status hisq_spinor_unpack(double *dst, const void *src, long nsites, int spinor_fmt, void *stream) {
     if (!dst || !src) return set_error(HISQ_EINVAL, "hisq_spinor_unpack: null pointer");
-    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 4) return set_error(HISQ_EINVAL, "hisq_spinor_unpack: bad size or format");
+    if (nsites < 0 || spinor_fmt < 0 || spinor_fmt > 5) return set_error(HISQ_EINVAL, "hisq_spinor_unpack: bad size or format");
     if (!aligned16(dst) || !aligned16(src)) return set_error(HISQ_EALIGN, "hisq_spinor_unpack: unaligned pointer");
     HISQ_TRY_HIP(launch_spinor_unpack(dst, (const char *)src, (size_t)nsites, spinor_fmt, (hipStream_t)stream));
     return HISQ_OK;
@@ -336,7 +337,7 @@ extern "C" hisq_status hisq_dslash_batched(void *out, const void *in, const hisq
                                            int nrhs, void *stream) {
     HISQ_TRY(dslash_common(out, in, g, parity, fmt, "hisq_dslash_batched"));
     if (nrhs < 1 || nrhs > 16) return set_error(HISQ_EINVAL, "hisq_dslash_batched: nrhs must be in [1,16]");
-    if (fmt.gauge == HISQ_GAUGE_FIX32 && fmt.compute == 32)
+    if (!has_batched_form(fmt))
         return set_error(HISQ_EINVAL, "hisq_dslash_batched: triplet FIX32/INT30/32 has no batched kernel");
     DslashArgs a = base_args(g, out, in, parity);
     a.nrhs = nrhs;

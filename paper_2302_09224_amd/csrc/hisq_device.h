@@ -29,7 +29,7 @@
 
 namespace hisq {
 
-enum SpinorFmt { SF_F64 = 0, SF_F32 = 1, SF_HALF16 = 2, SF_INT20 = 3, SF_INT30 = 4 };
+enum SpinorFmt { SF_F64 = 0, SF_F32 = 1, SF_HALF16 = 2, SF_INT20 = 3, SF_INT30 = 4, SF_INT24 = 5 };
 enum GaugeFmt { GF_F64 = 0, GF_F32 = 1, GF_FIX16 = 2, GF_FIX32 = 3 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -40,7 +40,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // bytes per site record / per link matrix
 __host__ __device__ constexpr int spinor_site_bytes(int sf) {
-    return sf == SF_F64 ? 48 : (sf == SF_F32 || sf == SF_INT30) ? 24 : 16;
+    return sf == SF_F64 ? 48 : (sf == SF_F32 || sf == SF_INT30) ? 24 : sf == SF_INT24 ? 20 : 16;
 }
 __host__ __device__ constexpr int gauge_matrix_bytes(int gf) {
     return gf == GF_F64 ? 144 : gf == GF_FIX16 ? 36 : 72;
@@ -304,6 +304,127 @@ template <class R> struct SpinorIO<SF_INT30, R> {
         st<u32x4>(base + 16 * s, a);
         st<u32x2>(base + 16 * n + 8 * s, b);
         return decode(a, b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Shared-exponent format generator (Sec. 4: the 20- and 30-bit formats are two
+// members of a family): six B-bit two's-complement components and an 8-bit
+// biased exponent E, in the order re0, im0, re1, im1, re2, im2, E, allocated
+// LSB-first in 32-bit words; a field that does not fit in the rest of a word
+// puts its high bits at the top of that word and its low bits at the bottom of
+// the next (the allocation of the appendix's 20-bit struct).  Encoding: M =
+// max |component|, E = biased exponent of M / (2^(B-1) - 1) plus one, q =
+// rint(v * 2^(127-E)), decode q * 2^(E-127); in FP32 for B <= 24, FP64 above
+// (2^(B-1) - 1 must be exact).  B = 20 gives the INT20 words, B = 30 the INT30
+// words; SF_INT24 (B = 24: 152 bits in five words) is generated.
+// ---------------------------------------------------------------------------
+
+template <int B> struct SxFmt {
+    static_assert(B >= 9 && B <= 31, "component width");
+    static constexpr int W = (6 * B + 8 + 31) / 32;
+    static __host__ __device__ constexpr int width(int f) { return f < 6 ? B : 8; }
+    static __host__ __device__ constexpr unsigned mask(int n) { return n >= 32 ? 0xffffffffu : ((1u << n) - 1u); }
+    static __host__ __device__ __forceinline__ void put(unsigned (&w)[W], int f, unsigned v) {
+        const int n = width(f), p = f * B, k = p >> 5, o = p & 31;
+        if (o + n <= 32) {
+            w[k] |= (v & mask(n)) << o;
+        } else {
+            const int l = n - (32 - o);     // low bits that go to the next word
+            w[k] |= ((v & mask(n)) >> l) << o;
+            w[k + 1] |= v & mask(l);
+        }
+    }
+    static __host__ __device__ __forceinline__ unsigned get(const unsigned (&w)[W], int f) {
+        const int n = width(f), p = f * B, k = p >> 5, o = p & 31;
+        if (o + n <= 32) return (w[k] >> o) & mask(n);
+        const int l = n - (32 - o);
+        return ((w[k] >> o) << l) | (w[k + 1] & mask(l));
+    }
+    static __host__ __device__ __forceinline__ int sext(unsigned u) {
+        const unsigned sign = 1u << (B - 1);
+        return (int)((u & mask(B)) ^ sign) - (int)sign;
+    }
+};
+
+template <int B, class R> struct SxCodec {
+    typedef SxFmt<B> F;
+    static __device__ __forceinline__ void encode(const CVec<R> &vin, unsigned (&w)[F::W]) {
+#pragma unroll
+        for (int k = 0; k < F::W; k++) w[k] = 0u;
+        unsigned e, q[6];
+        if (B <= 24) {
+            const float f[6] = {(float)vin.re[0], (float)vin.im[0], (float)vin.re[1],
+                                (float)vin.im[1], (float)vin.re[2], (float)vin.im[2]};
+            float m = fabsf(f[0]);
+#pragma unroll
+            for (int k = 1; k < 6; k++) m = fmaxf(m, fabsf(f[k]));
+            const float t = m / (float)((1 << (B - 1)) - 1);
+            e = ((__float_as_uint(t) >> 23) & 0xffu) + 1u;
+            e = e > 254u ? 254u : e;
+            const float inv = __uint_as_float((254u - e) << 23);
+#pragma unroll
+            for (int k = 0; k < 6; k++) q[k] = (unsigned)(int)__builtin_rintf(f[k] * inv);
+        } else {
+            const double f[6] = {(double)vin.re[0], (double)vin.im[0], (double)vin.re[1],
+                                 (double)vin.im[1], (double)vin.re[2], (double)vin.im[2]};
+            double m = fabs(f[0]);
+#pragma unroll
+            for (int k = 1; k < 6; k++) m = fmax(m, fabs(f[k]));
+            const double t = m / (double)((1u << (B - 1)) - 1u);
+            int ei = 1;
+            if (t > 0.0) {
+                ei = (int)((__double_as_longlong(t) >> 52) & 0x7ff) - 895;
+                ei = ei < 1 ? 1 : (ei > 254 ? 254 : ei);
+            }
+            e = (unsigned)ei;
+            const double inv = pow2_f64(254u - e);
+#pragma unroll
+            for (int k = 0; k < 6; k++) q[k] = (unsigned)(int)__builtin_rint(f[k] * inv);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) F::put(w, k, q[k]);
+        F::put(w, 6, e);
+    }
+    static __device__ __forceinline__ CVec<R> decode(const unsigned (&w)[F::W]) {
+        const unsigned e = F::get(w, 6);
+        CVec<R> v;
+        if (B <= 24) {
+            const float sc = pow2_f32(e);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                v.re[c] = (R)((float)F::sext(F::get(w, 2 * c)) * sc);
+                v.im[c] = (R)((float)F::sext(F::get(w, 2 * c + 1)) * sc);
+            }
+        } else {
+            const double sc = pow2_f64(e);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                v.re[c] = (R)((double)F::sext(F::get(w, 2 * c)) * sc);
+                v.im[c] = (R)((double)F::sext(F::get(w, 2 * c + 1)) * sc);
+            }
+        }
+        return v;
+    }
+};
+
+// SoA storage of a generated record of W words: words 0-3 in the 16-byte plane
+// (16 s), the rest in a tail plane of (W-4)*4 bytes per site after it.
+template <class R> struct SpinorIO<SF_INT24, R> {
+    typedef SxFmt<24> F;
+    static __device__ __forceinline__ CVec<R> load(const char *base, size_t n, size_t s) {
+        const u32x4 a = ld<u32x4>(base + 16 * s);
+        const unsigned w[F::W] = {a.x, a.y, a.z, a.w, ld<unsigned>(base + 16 * n + 4 * s)};
+        return SxCodec<24, R>::decode(w);
+    }
+    static __device__ __forceinline__ CVec<R> store(char *base, size_t n, size_t s, const CVec<R> &v) {
+        unsigned w[F::W];
+        SxCodec<24, R>::encode(v, w);
+        u32x4 a;
+        a.x = w[0]; a.y = w[1]; a.z = w[2]; a.w = w[3];
+        st<u32x4>(base + 16 * s, a);
+        st<unsigned>(base + 16 * n + 4 * s, w[4]);
+        return SxCodec<24, R>::decode(w);
     }
 };
 

@@ -26,6 +26,7 @@ HISQ_DECL_TRIPLET(half)
 HISQ_DECL_TRIPLET(int20)
 HISQ_DECL_TRIPLET(int30)
 HISQ_DECL_TRIPLET(int30_fp32)
+HISQ_DECL_TRIPLET(int24)
 
 namespace {
 
@@ -39,6 +40,7 @@ hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const Ds
     case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_launch_int20(a, rhs0, t, st, nb);
     case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_launch_int30(a, rhs0, t, st, nb);
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_launch_int30_fp32(a, rhs0, t, st, nb);
+    case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return dslash_launch_int24(a, rhs0, t, st, nb);
     default: return hipErrorInvalidValue;
     }
 }
@@ -113,7 +115,7 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second.first;
-    const bool batched_ok = !(f.gauge == GF_FIX32 && f.compute == 32);
+    const bool batched_ok = has_batched_form(f);
     DslashTile best = default_tile(c);
     if (!probe || !tuning_enabled()) return best;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -164,6 +166,7 @@ hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_r
     case GF_FIX16 * 100 + SF_INT20 * 10 + 0: return dslash_multi_int20(m, long_recon, st);
     case GF_FIX32 * 100 + SF_INT30 * 10 + 1: return dslash_multi_int30(m, long_recon, st);
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_multi_int30_fp32(m, long_recon, st);
+    case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return dslash_multi_int24(m, long_recon, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -190,7 +193,7 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
         return set_error(HISQ_EINVAL, "hisq_tune_set: long_recon must be 18 or 12");
     const bool pow2 = rhs_block >= 1 && rhs_block <= 16 && (rhs_block & (rhs_block - 1)) == 0;
     if (!pow2) return set_error(HISQ_EINVAL, "hisq_tune_set: rhs_block must be 1, 2, 4, 8 or 16");
-    if (rhs_block > 1 && fmt.gauge == HISQ_GAUGE_FIX32 && fmt.compute == 32)
+    if (rhs_block > 1 && !has_batched_form(fmt))
         return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
     bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
     ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);

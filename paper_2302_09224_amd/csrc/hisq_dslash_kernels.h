@@ -221,6 +221,7 @@ template <> struct SpinRaw<SF_F32> { f32x4 a; f32x2 b; };
 template <> struct SpinRaw<SF_HALF16> { u32x4 w; };
 template <> struct SpinRaw<SF_INT20> { u32x4 w; };
 template <> struct SpinRaw<SF_INT30> { u32x4 a; u32x2 b; };
+template <> struct SpinRaw<SF_INT24> { u32x4 a; unsigned b; };
 
 template <int SF> __device__ __forceinline__ SpinRaw<SF> spin_load(const char *base, size_t n, size_t s);
 template <> __device__ __forceinline__ SpinRaw<SF_F64> spin_load<SF_F64>(const char *base, size_t n, size_t s) {
@@ -251,6 +252,12 @@ template <> __device__ __forceinline__ SpinRaw<SF_INT30> spin_load<SF_INT30>(con
     P.b = ld<u32x2>(base + 16 * n + 8 * s);
     return P;
 }
+template <> __device__ __forceinline__ SpinRaw<SF_INT24> spin_load<SF_INT24>(const char *base, size_t n, size_t s) {
+    SpinRaw<SF_INT24> P;
+    P.a = ld<u32x4>(base + 16 * s);
+    P.b = ld<unsigned>(base + 16 * n + 4 * s);
+    return P;
+}
 
 template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_F64> &P) {
     CVec<R> v;
@@ -274,6 +281,10 @@ template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<
 }
 template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT30> &P) {
     return SpinorIO<SF_INT30, R>::decode(P.a, P.b);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT24> &P) {
+    const unsigned w[SxFmt<24>::W] = {P.a.x, P.a.y, P.a.z, P.a.w, P.b};
+    return SxCodec<24, R>::decode(w);
 }
 
 // ---------------------------------------------------------------------------

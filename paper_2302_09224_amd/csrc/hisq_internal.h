@@ -40,6 +40,9 @@ Geom make_geom(const int dims[4]);
 size_t spinor_field_bytes(size_t nsites, int sf);
 size_t gauge_field_bytes(const int dims[4], int gf);
 bool triplet_ok(const hisq_fmt &f);
+// triplets whose Dslash is also built for blocks of right-hand sides
+// (FIX32/INT30/FP32 is not: it exists only as a refinement option)
+inline bool has_batched_form(const hisq_fmt &f) { return !(f.spinor == HISQ_SPINOR_INT30 && f.compute == 32); }
 bool aligned16(const void *p);
 
 // ---------------------------------------------------------------------------

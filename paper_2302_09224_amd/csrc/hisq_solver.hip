@@ -318,6 +318,7 @@ int sloppy_floor_bits(int sf) {
     case SF_HALF16: return 15;
     case SF_INT20: return 19;
     case SF_INT30: return 29;
+    case SF_INT24: return 23;
     }
     return 24;
 }

@@ -10,7 +10,7 @@ import torch
 import oracle
 from paper_2302_09224_amd import inputs
 
-FMT_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}
+FMT_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
 GFMT_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
 
 
@@ -24,7 +24,7 @@ def need_gpu():
 
 def spinor_records(packed, n, fmt):
     """packed uint8 (numpy) SoA field -> per-site records as the oracle codecs use"""
-    b = np.ascontiguousarray(packed[: n * {0: 48, 1: 24, 2: 16, 3: 16, 4: 24}[fmt]])
+    b = np.ascontiguousarray(packed[: n * {0: 48, 1: 24, 2: 16, 3: 16, 4: 24, 5: 20}[fmt]])
     if fmt == 0:
         a = b.view(np.float64).reshape(3, n, 2)
         return (a[..., 0] + 1j * a[..., 1]).T.copy()
@@ -45,6 +45,10 @@ def spinor_records(packed, n, fmt):
     if fmt == 4:
         p0 = b[: 16 * n].view(np.uint32).reshape(n, 4)
         p1 = b[16 * n: 24 * n].view(np.uint32).reshape(n, 2)
+        return np.concatenate([p0, p1], axis=1)
+    if fmt == 5:
+        p0 = b[: 16 * n].view(np.uint32).reshape(n, 4)
+        p1 = b[16 * n: 20 * n].view(np.uint32).reshape(n, 1)
         return np.concatenate([p0, p1], axis=1)
     raise ValueError(fmt)
 

@@ -41,6 +41,11 @@ def test_sizes(hisq):
     assert hisq.hisq_gauge_bytes(dims, hisq.GAUGE_F64) == 4 * V * 144
     assert hisq.hisq_spinor_bytes(V // 2, hisq.SPINOR_INT20) == V // 2 * 16
     assert hisq.hisq_spinor_bytes(V // 2, hisq.SPINOR_INT30) == V // 2 * 24
+    assert hisq.hisq_spinor_bytes(V // 2, hisq.SPINOR_INT24) == V // 2 * 20
+    assert hisq.hisq_spinor_bytes(V // 2, 6) == 0
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("int24"), hisq.hisq_solver_params_default()) > 0
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(3, 5, 64), hisq.hisq_solver_params_default()) == 0
+    assert hisq.hisq_bicgstab_workspace_bytes(dims, 4, hisq.fmt("int24")) > 0
     assert hisq.hisq_gauge_bytes((5, 4, 4, 4), 0) == 0          # odd extent
     assert hisq.hisq_gauge_bytes((2, 4, 4, 4), 0) == 0          # extent below 4
     assert hisq.hisq_spinor_bytes(10, 9) == 0                   # unknown format
@@ -62,6 +67,9 @@ def test_sizes(hisq):
     p.batch_refine = 0
     ws = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
     assert wb > ws > 0                                           # room for a block of 11 shifted systems
+    p.batch_refine = 1
+    assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int24"), p) > ws
+    p.batch_refine = 0
     # refinement in FIX32/INT30/FP32 has no batched form: no extra room
     p.batch_refine = 1
     a = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
@@ -119,6 +127,7 @@ def test_tune_set_validation(hisq):
     hisq.hisq_tune_set("half", dims, 1, 1, 1, 4, 128, 0)
     hisq.hisq_tune_set("half", dims, 1, 1, 1, 2, 128, 0, long_recon=12)
     hisq.hisq_tune_set("double", dims, 4, 2, 2, 1, 256, 2048, sweep=1)
+    hisq.hisq_tune_set("int24", dims, 4, 4, 1, 1, 256, 0)
     rep = hisq.hisq_tune_report()
     assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
     assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0 sweep 0" in rep

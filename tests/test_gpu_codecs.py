@@ -19,7 +19,7 @@ def spread_spinor(n, seed, zero_every=97):
     return v
 
 
-@pytest.mark.parametrize("fmt", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n", [1, 257, 5000])
 def test_spinor_pack_bit_exact(fmt, n):
     hisq = need_gpu()
@@ -28,7 +28,7 @@ def test_spinor_pack_bit_exact(fmt, n):
     packed = hisq.pack_spinor(dev, fmt)
     torch.cuda.synchronize()
     rec = spinor_records(packed.cpu().numpy(), n, fmt)
-    name = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}[fmt]
+    name = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}[fmt]
     if name == "f64":
         assert np.array_equal(rec.view(np.float64), v.view(np.float64))
     elif name == "f32":
@@ -38,6 +38,8 @@ def test_spinor_pack_bit_exact(fmt, n):
         assert np.array_equal(rec[0], q) and np.array_equal(rec[1].view(np.uint32), nm.view(np.uint32))
     elif name == "int20":
         assert np.array_equal(rec, oracle.int20_encode(v))
+    elif name == "int24":
+        assert np.array_equal(rec, oracle.int24_encode(v))
     else:
         assert np.array_equal(rec, oracle.int30_encode(v))
     # decode: the library's unpack equals the oracle's decode of the same records, exactly

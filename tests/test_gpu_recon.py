@@ -11,8 +11,8 @@ from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32"]
-SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30"}
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24"]
+SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
 GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
 
 

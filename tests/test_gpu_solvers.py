@@ -56,7 +56,7 @@ def test_cg_config0_dense():
     assert oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass) <= 1e-10
 
 
-@pytest.mark.parametrize("sloppy", ["double", "single", "half", "int20", "int30", "int30_fp32"])
+@pytest.mark.parametrize("sloppy", ["double", "single", "half", "int20", "int30", "int30_fp32", "int24"])
 @pytest.mark.parametrize("dims,kind,mass", [((8, 8, 8, 8), "near_unit", 0.05), ((6, 8, 10, 12), "haar", 0.2)])
 def test_cg_mixed(sloppy, dims, kind, mass):
     hisq = need_gpu()
@@ -113,7 +113,7 @@ def test_cg_maxiter_reports_noconv():
 
 @pytest.mark.parametrize("ms,ref,batch", [("single", "half", 1), ("int30", "int20", 1), ("double", "double", 1),
                                           ("single", "single", 1), ("int30", "int20", 0), ("single", "half", 0),
-                                          ("int30", "int30_fp32", 1)])
+                                          ("int30", "int30_fp32", 1), ("int30", "int24", 1)])
 def test_multishift(ms, ref, batch):
     """batch: refine the shifted systems together (1) or one after another (0);
     int30_fp32 has no batched form, so it refines one after another either way"""
@@ -182,7 +182,7 @@ def test_multishift_single_shift():
     assert st["status"] == "HISQ_OK" and res <= 1e-10 * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "double"])
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "double", "int24"])
 @pytest.mark.parametrize("nrhs", [1, 4, 16])
 def test_batched_cg(sloppy, nrhs):
     hisq = need_gpu()
@@ -200,7 +200,7 @@ def test_batched_cg(sloppy, nrhs):
         assert res <= 1e-10 * (1 + 1e-6), (j, res)
 
 
-@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "int30"])
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "int30", "int24"])
 def test_cg_error_estimate_reliable_updates(sloppy):
     """reliable updates triggered by the residual-deviation estimate instead of delta"""
     hisq = need_gpu()

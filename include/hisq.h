@@ -47,7 +47,8 @@ typedef enum {
     HISQ_ENOCONV = -4,     /* solver hit maxiter; stats are filled, x is the best iterate */
     HISQ_EBREAKDOWN = -5,  /* solver breakdown: <p,Ap> <= 0 or a non-finite residual */
     HISQ_EWORKSPACE = -6,  /* workspace too small (see the *_workspace_bytes queries) */
-    HISQ_ERANGE = -7       /* a value exceeds what the storage format can hold */
+    HISQ_ERANGE = -7,      /* a value exceeds what the storage format can hold */
+    HISQ_EIO = -8          /* a field file cannot be opened, read or written, or is inconsistent */
 } hisq_status;
 
 /* Spinor (fermion) storage formats. */
@@ -335,6 +336,55 @@ hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrhs, const hi
  * on the first application of a shape key (never inside stream capture);
  * environment HISQ_TUNE=0 selects fixed defaults instead. */
 size_t hisq_tune_report(char *buf, size_t len);
+
+/* ---------------------------------------------------------------------------
+ * Offline storage of packed fields (Sec. 7 outlook: gauge fields and
+ * propagators kept on disk in the bit-packed formats).  A file holds a
+ * 128-byte header (magic "HISQPK01", field kind, format, lattice extents or
+ * site count, long-link storage, the gauge scales, payload sizes and an
+ * FNV-1a checksum over 64-bit words of the payload) followed by the packed
+ * device bytes verbatim (gauge: fat links, then long links), so a field
+ * comes back bit for bit without being unpacked.  Copies go through a
+ * 64 MiB pinned staging buffer on `stream`; the calls return when the file
+ * is complete (save) or the device holds the field (load).  A file whose
+ * header is malformed, whose length differs from its header or whose
+ * checksum does not match gives HISQ_EIO (after a checksum mismatch the
+ * destination holds the file's bytes); a file that is well formed but holds
+ * another kind, format or size than asked gives HISQ_EINVAL.
+ * ------------------------------------------------------------------------- */
+enum { HISQ_FIELD_SPINOR = 1, HISQ_FIELD_GAUGE = 2 };
+
+typedef struct {
+    int kind;        /* HISQ_FIELD_SPINOR or HISQ_FIELD_GAUGE */
+    int fmt;         /* spinor or gauge storage format */
+    int dims[4];     /* gauge: lattice extents; spinor: zeros */
+    long nsites;     /* spinor: sites; gauge: lattice volume */
+    int long_recon;  /* gauge: HISQ_RECON_18 or HISQ_RECON_12 */
+    size_t bytes0;   /* spinor payload or fat-link payload */
+    size_t bytes1;   /* long-link payload (0 for a spinor) */
+} hisq_field_header;
+
+/* Read the header of `path` (host string) into *info: what to allocate
+ * before hisq_spinor_load / hisq_gauge_load. */
+hisq_status hisq_field_info(const char *path, hisq_field_header *info);
+
+/* Write the packed spinor field src (device, hisq_spinor_bytes(nsites,
+ * spinor_fmt) bytes) to `path`, replacing the file. */
+hisq_status hisq_spinor_save(const char *path, const void *src, long nsites, int spinor_fmt, void *stream);
+
+/* Read a spinor file into dst (device, hisq_spinor_bytes(nsites, spinor_fmt)
+ * bytes); the file must hold exactly nsites sites in spinor_fmt. */
+hisq_status hisq_spinor_load(const char *path, void *dst, long nsites, int spinor_fmt, void *stream);
+
+/* Write the packed links of g (filled by hisq_gauge_pack or hisq_gauge_load)
+ * with their scales and long-link storage to `path`. */
+hisq_status hisq_gauge_save(const char *path, const hisq_gauge *g, void *stream);
+
+/* Read a gauge file into fat_dst and long_dst (device buffers of fat_bytes
+ * and long_bytes, at least the file's bytes0 and bytes1) and fill *g as
+ * hisq_gauge_pack would have. */
+hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size_t fat_bytes,
+                            void *long_dst, size_t long_bytes, void *stream);
 
 /* Fix the launch shape of the Dslash for triplet fmt on lattice dims with long
  * links stored as long_recon (HISQ_RECON_18 or HISQ_RECON_12) and a block of

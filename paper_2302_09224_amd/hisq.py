@@ -33,7 +33,7 @@ HISQ_MAX_SHIFTS = 32
 HISQ_MAX_GRAD_BUFFER = 16
 
 STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EALIGN", -3: "HISQ_EHIP", -4: "HISQ_ENOCONV",
-          -5: "HISQ_EBREAKDOWN", -6: "HISQ_EWORKSPACE", -7: "HISQ_ERANGE"}
+          -5: "HISQ_EBREAKDOWN", -6: "HISQ_EWORKSPACE", -7: "HISQ_ERANGE", -8: "HISQ_EIO"}
 
 
 class hisq_fmt(ctypes.Structure):
@@ -50,6 +50,12 @@ class hisq_gauge(ctypes.Structure):
 
 
 RECON_18, RECON_12 = 18, 12
+FIELD_SPINOR, FIELD_GAUGE = 1, 2
+
+
+class hisq_field_header(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("fmt", ctypes.c_int), ("dims", ctypes.c_int * 4), ("nsites", ctypes.c_long),
+                ("long_recon", ctypes.c_int), ("bytes0", ctypes.c_size_t), ("bytes1", ctypes.c_size_t)]
 
 
 class hisq_solver_params(ctypes.Structure):
@@ -147,6 +153,11 @@ def load():
         "hisq_tune_report": (sz, [ctypes.c_char_p, sz]),
         "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
         "hisq_tune_clear": (None, []),
+        "hisq_field_info": (i, [ctypes.c_char_p, ctypes.POINTER(hisq_field_header)]),
+        "hisq_spinor_save": (i, [ctypes.c_char_p, vp, ctypes.c_long, i, vp]),
+        "hisq_spinor_load": (i, [ctypes.c_char_p, vp, ctypes.c_long, i, vp]),
+        "hisq_gauge_save": (i, [ctypes.c_char_p, G, vp]),
+        "hisq_gauge_load": (i, [ctypes.c_char_p, G, vp, sz, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -371,6 +382,47 @@ def unpack_spinor(packed, nsites, spinor_fmt, stream=None):
     out = torch.empty((int(nsites), 3), dtype=torch.complex128, device=packed.device)
     hisq_spinor_unpack(torch.view_as_real(out), packed, nsites, spinor_fmt, stream)
     return out
+
+
+def field_info(path):
+    """header of a packed-field file as a dict (no device access)"""
+    info = hisq_field_header()
+    _check(load().hisq_field_info(os.fsencode(path), ctypes.byref(info)), "hisq_field_info")
+    return dict(kind=info.kind, fmt=info.fmt, dims=tuple(info.dims), nsites=info.nsites, long_recon=info.long_recon,
+                bytes0=info.bytes0, bytes1=info.bytes1)
+
+
+def save_spinor(path, packed, nsites, spinor_fmt, stream=None):
+    _check(load().hisq_spinor_save(os.fsencode(path), _ptr(packed), int(nsites), int(spinor_fmt), _stream(stream)),
+           "hisq_spinor_save")
+
+
+def load_spinor(path, device="cuda", stream=None):
+    """-> (packed uint8 field on device, nsites, spinor format)"""
+    info = field_info(path)
+    if info["kind"] != FIELD_SPINOR:
+        raise HisqError(-1, "load_spinor", f"{path} holds a gauge field")
+    out = _empty_bytes(info["bytes0"], device)
+    _check(load().hisq_spinor_load(os.fsencode(path), _ptr(out), info["nsites"], info["fmt"], _stream(stream)),
+           "hisq_spinor_load")
+    return out, info["nsites"], info["fmt"]
+
+
+def save_gauge(path, gauge: PackedGauge, stream=None):
+    _check(load().hisq_gauge_save(os.fsencode(path), ctypes.byref(gauge.desc), _stream(stream)), "hisq_gauge_save")
+
+
+def load_gauge(path, device="cuda", stream=None):
+    """-> PackedGauge read from a file written by save_gauge"""
+    info = field_info(path)
+    if info["kind"] != FIELD_GAUGE:
+        raise HisqError(-1, "load_gauge", f"{path} holds a spinor field")
+    fd = _empty_bytes(info["bytes0"], device)
+    ld = _empty_bytes(info["bytes1"], device)
+    g = hisq_gauge()
+    _check(load().hisq_gauge_load(os.fsencode(path), ctypes.byref(g), _ptr(fd), fd.numel(), _ptr(ld), ld.numel(),
+                                  _stream(stream)), "hisq_gauge_load")
+    return PackedGauge(fd, ld, g, tuple(g.dims), g.fmt)
 
 
 def dslash(packed_in, gauge: PackedGauge, parity, f, stream=None):

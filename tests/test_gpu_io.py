@@ -1,0 +1,72 @@
+"""Offline storage of packed fields on the device: a saved and reloaded field
+is bit for bit the packed field (byte work: exact), a reloaded gauge field
+gives the same Dslash, and damaged files are refused."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import need_gpu
+from paper_2302_09224_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3, 4, 5])
+def test_spinor_roundtrip(fmt, tmp_path):
+    hisq = need_gpu()
+    n = 1003
+    v = inputs.gaussian_spinor(n, 900 + fmt, device="cuda")
+    packed = hisq.pack_spinor(v, fmt)
+    path = str(tmp_path / "s.hisq")
+    hisq.save_spinor(path, packed, n, fmt)
+    back, nb, fb = hisq.load_spinor(path)
+    nbytes = hisq.hisq_spinor_bytes(n, fmt)
+    assert (nb, fb) == (n, fmt) and torch.equal(back[:nbytes], packed[:nbytes])
+    # one flipped payload bit: checksum mismatch
+    raw = bytearray(open(path, "rb").read())
+    raw[128 + nbytes // 2] ^= 0x10
+    open(path, "wb").write(bytes(raw))
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.load_spinor(path)
+    assert e.value.status == -8
+    # truncated payload
+    open(path, "wb").write(bytes(raw[:-5]))
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.load_spinor(path)
+    assert e.value.status == -8
+
+
+def test_spinor_several_chunks(tmp_path):
+    """a field larger than the 64 MiB staging buffer (3 chunks)"""
+    hisq = need_gpu()
+    n = 3_000_000                                  # INT30: 72 MB
+    v = inputs.gaussian_spinor(n, 950, device="cuda")
+    packed = hisq.pack_spinor(v, hisq.SPINOR_INT30)
+    path = str(tmp_path / "big.hisq")
+    hisq.save_spinor(path, packed, n, hisq.SPINOR_INT30)
+    back, _, _ = hisq.load_spinor(path)
+    nbytes = hisq.hisq_spinor_bytes(n, hisq.SPINOR_INT30)
+    assert nbytes > 64 << 20 and torch.equal(back[:nbytes], packed[:nbytes])
+
+
+@pytest.mark.parametrize("gfmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("recon", [18, 12])
+def test_gauge_roundtrip_same_dslash(gfmt, recon, tmp_path):
+    hisq = need_gpu()
+    dims = (4, 4, 6, 8)
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 70, device="cuda")
+    pg = hisq.pack_gauge(fat, lng, dims, gfmt, long_recon=recon)
+    path = str(tmp_path / "g.hisq")
+    hisq.save_gauge(path, pg)
+    info = hisq.field_info(path)
+    assert info["dims"] == dims and info["fmt"] == gfmt and info["long_recon"] == recon
+    lg = hisq.load_gauge(path)
+    b0, b1 = hisq.hisq_gauge_bytes(dims, gfmt), hisq.hisq_gauge_long_bytes(dims, gfmt, recon)
+    assert torch.equal(lg.fat[:b0], pg.fat[:b0]) and torch.equal(lg.lng[:b1], pg.lng[:b1])
+    for k in ("fat_max", "long_max", "long_coeff", "long_recon", "fmt"):
+        assert getattr(lg.desc, k) == getattr(pg.desc, k), k
+    name = {0: "double", 1: "single", 2: "int20", 3: "int30"}[gfmt]
+    f = hisq.fmt(name)
+    vh = int(np.prod(dims)) // 2
+    pin = hisq.pack_spinor(inputs.gaussian_spinor(vh, 960, device="cuda"), f.spinor)
+    assert torch.equal(hisq.dslash(pin, lg, 0, f), hisq.dslash(pin, pg, 0, f))

@@ -292,7 +292,7 @@ hisq_status hisq_multishift_cg_solve(double *const *x, const double *b, const do
 #define HISQ_MAX_BICGSTAB_L 8
 size_t hisq_bicgstab_workspace_bytes(const int dims[4], int l, hisq_fmt sloppy);
 
-/* Mixed-precision BiCGStab(l) (Sec. 5.1, the solver of Sleijpen and Fokkema)
+/* Mixed-precision BiCGStab(l) (Sec. 6.1, the solver of Sleijpen and Fokkema)
  * for M x = b on the WHOLE lattice, M = 2m + D (D the HISQ Dslash of both
  * parities; M^dag M restricted to even sites is the CG operator above).
  * x, b: (device) canonical complex128 [V][3], all sites in lexicographic order

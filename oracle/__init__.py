@@ -229,7 +229,7 @@ def full_op(fat, lng, x, dims, mass, lib=None):
 
 
 def bicgstab_l(fat, lng, b, dims, mass, l=4, tol=1e-10, maxiter=100000, x0=None, lib=None, on_mr=None):
-    """FP64 BiCGStab(l) (Sleijpen and Fokkema 1993, the method Sec. 5.1 runs in
+    """FP64 BiCGStab(l) (Sleijpen and Fokkema 1993, the method Sec. 6.1 runs in
     mixed precision) for M x = b on the whole lattice, M = 2m + D.
     Each cycle: l BiCG steps (building u_0..u_l and r_0..r_l with one shadow
     residual), then the minimal-residual step over r_1..r_l by modified

@@ -1,4 +1,4 @@
-// hisq_bicgstab.hip -- mixed-precision BiCGStab(l) (Sec. 5.1; the method of
+// hisq_bicgstab.hip -- mixed-precision BiCGStab(l) (Sec. 6.1; the method of
 // Sleijpen and Fokkema) for the whole-lattice HISQ operator M = 2m + D.
 //
 // The Krylov vectors r_0..r_l, u_0..u_l and the shadow residual live in the

@@ -1,4 +1,4 @@
-"""Mixed-precision BiCGStab(l) (Sec. 5.1) for M x = b, M = 2m + D on the whole
+"""Mixed-precision BiCGStab(l) (Sec. 6.1) for M x = b, M = 2m + D on the whole
 lattice, against the oracle: the FP64 true residual of the GPU solution with
 the oracle's operator, and the oracle's FP64 BiCGStab(4) solution (the
 solution is unique; M has eigenvalues 2m + i*lambda)."""

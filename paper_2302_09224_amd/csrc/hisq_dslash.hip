@@ -61,7 +61,7 @@ bool tuning_enabled() {
 std::vector<DslashTile> candidates(int c, bool batched_ok) {
     std::vector<DslashTile> v;
     if (c == 1) {
-        for (int st : {1, 2, 4, 8})
+        for (int st : {1, 2, 4, 8, -1, -2})
             for (int blk : {128, 256})
                 for (int per_cu : {0, 4, 8})
                     for (int sw : {0, 1}) v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk), sw});
@@ -197,7 +197,8 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
         return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
     bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
     ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);
-    ok = ok && (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8) : stage == 1);
+    ok = ok && (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8 || stage == -1 || stage == -2)
+                        : stage == 1);
     if (!ok)
         return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d",
                          nr, rg, stage, block, grid, sweep);

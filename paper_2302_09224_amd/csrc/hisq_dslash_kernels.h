@@ -447,42 +447,62 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
             }
         }
     }
+    // STAGE > 0: the raw words of STAGE hops are loaded, then unpacked and
+    // applied; STAGE < 0: -STAGE hops per stage, double-buffered, the next
+    // stage's loads issued before this stage's arithmetic so that every wave
+    // keeps loads in flight while it computes
+    constexpr int SB = STAGE < 0 ? -STAGE : STAGE;
+    constexpr bool PIPE = STAGE < 0;
+    constexpr int NBUF = PIPE ? 2 : 1;
+    constexpr int NST = (NR > 1 && STAGE == 1) ? 0 : 16 / SB;
     const Nbrs n = neighbours(g, s, p);
+    LinkRaw<GF> L[NBUF][SB];
+    LinkRaw12<GF> L12[NBUF][SB];
+    SpinRaw<SF> P[NBUF][SB][NR];
+    auto load_stage = [&](int h0, int bf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h0 = 0; h0 < ((NR > 1 && STAGE == 1) ? 0 : 16); h0 += STAGE) {
-        LinkRaw<GF> L[STAGE];
-        LinkRaw12<GF> L12[STAGE];
-        SpinRaw<SF> P[STAGE][NR];
-#pragma unroll
-        for (int i = 0; i < STAGE; i++) {
+        for (int i = 0; i < SB; i++) {
             const int h = h0 + i;
             const int ss = hop_spinor_site(n, h);
             const int ls = (h & 1) ? ss : s;
             const int lpar = (h & 1) ? q : p;
             if (LR == 12 && (h & 2))
-                L12[i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
+                L12[bf][i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
             else
-                L[i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+                L[bf][i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-            for (int j = 0; j < NR; j++) P[i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
+            for (int j = 0; j < NR; j++)
+                P[bf][i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
         }
-        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto apply_stage = [&](int h0, int bf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int i = 0; i < STAGE; i++) {
+        for (int i = 0; i < SB; i++) {
             const int h = h0 + i;
             const Mat<R> U = (LR == 12 && (h & 2))
-                                 ? link_decode12<R>(L12[i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
-                                 : link_decode<R>(L[i], (h & 2) ? gl : gf);
+                                 ? link_decode12<R>(L12[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
+                                 : link_decode<R>(L[bf][i], (h & 2) ? gl : gf);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 if (NR > 1 && !((live >> j) & 1u)) continue;
-                const CVec<R> v = spin_decode<R>(P[i][j]);
+                const CVec<R> v = spin_decode<R>(P[bf][i][j]);
                 if (h & 1)
                     mdv_sub(acc[j], U, v);
                 else
                     mv_add(acc[j], U, v);
             }
         }
+    };
+    if (PIPE && NST > 0) load_stage(0, 0);
+#pragma unroll
+    for (int k = 0; k < NST; k++) {
+        if (!PIPE)
+            load_stage(k * SB, 0);
+        else if (k + 1 < NST)
+            load_stage((k + 1) * SB, (k + 1) % NBUF);
+        __builtin_amdgcn_sched_barrier(0);
+        apply_stage(k * SB, k % NBUF);
+        if (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
     const R b = (R)A.b, cc = (R)A.c;
 #pragma unroll
@@ -661,6 +681,8 @@ hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipSt
         t.grid < 0 || (t.grid & 7) || (t.sweep != 0 && t.sweep != 1))
         return hipErrorInvalidValue;
     switch (t.nr * 100 + t.stage) {
+    case 99: return launch_cfg<GF, SF, R, 1, -1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+    case 98: return launch_cfg<GF, SF, R, 1, -2>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     case 101: return launch_cfg<GF, SF, R, 1, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     case 102: return launch_cfg<GF, SF, R, 1, 2>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     case 104: return launch_cfg<GF, SF, R, 1, 4>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);

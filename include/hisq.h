@@ -69,13 +69,17 @@ enum {
     HISQ_GAUGE_F64 = 0,      /* IEEE FP64, 144 B/matrix */
     HISQ_GAUGE_F32 = 1,      /* IEEE FP32, 72 B/matrix */
     HISQ_GAUGE_FIX16 = 2,    /* 16-bit fixed point, global scale, 36 B/matrix (Sec. 2 footnote, Sec. 4) */
-    HISQ_GAUGE_FIX32 = 3     /* 32-bit fixed point, global scale, 72 B/matrix (Sec. 4) */
+    HISQ_GAUGE_FIX32 = 3,    /* 32-bit fixed point, global scale, 72 B/matrix (Sec. 4) */
+    HISQ_GAUGE_SX24 = 4      /* each row a 24-bit shared-exponent record (the spinor generator of
+                                HISQ_SPINOR_INT24 applied to the three colour rows), 60 B/matrix:
+                                words 0-3 of row r in 16-B plane r, word 4 in 4-B plane r after the
+                                three 16-B planes; two-row long links 40 B.  No global scale. */
 };
 
 /* Precision triplet gauge / fermion / compute of one stencil application
  * (Sec. 4).  compute is 32 (FP32) or 64 (FP64).  Supported triplets:
  *   F64/F64/64, F32/F32/32, FIX16/HALF16/32, FIX16/INT20/32,
- *   FIX32/INT30/64, FIX32/INT30/32, FIX32/INT24/32. */
+ *   FIX32/INT30/64, FIX32/INT30/32, FIX32/INT24/32, SX24/INT24/32. */
 typedef struct {
     int gauge;
     int spinor;

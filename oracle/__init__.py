@@ -498,7 +498,7 @@ def fix_decode(q, absmax, compute_bits, shape=None, lib=None):
 # ---------------------------------------------------------------------------
 
 SPINOR_FORMATS = ("f64", "f32", "half16", "int20", "int30", "int24")
-GAUGE_FORMATS = ("f64", "f32", "fix16", "fix32")
+GAUGE_FORMATS = ("f64", "f32", "fix16", "fix32", "sx24")
 
 
 def spinor_roundtrip(v, fmt, lib=None):
@@ -538,9 +538,23 @@ def spinor_decode_records(rec, fmt, lib=None):
     raise ValueError(fmt)
 
 
+def sx24_rows_encode(u):
+    """link rows (complex [..., nrow, 3]) as 24-bit shared-exponent records,
+    uint32 [..., nrow, 5]: each colour row is one record of the B = 24 member"""
+    u = np.asarray(u, dtype=np.complex128)
+    return shared_exponent_encode(u.reshape(-1, 3), 24).reshape(u.shape[:-1] + (5,))
+
+
+def sx24_rows_roundtrip(u):
+    u = np.asarray(u, dtype=np.complex128)
+    return _complex3(shared_exponent_decode(sx24_rows_encode(u).reshape(-1, 5), 24)).reshape(u.shape)
+
+
 def gauge_roundtrip(u, fmt, compute_bits, lib=None):
     """links after encode in `fmt` and decode in the compute precision"""
     u = np.asarray(u, dtype=np.complex128)
+    if fmt == "sx24":
+        return sx24_rows_roundtrip(u)
     if fmt == "f64":
         return u.astype(np.complex64).astype(np.complex128) if compute_bits == 32 else u.copy()
     if fmt == "f32":
@@ -629,6 +643,8 @@ def long_recon_roundtrip(lng, dims, fmt, compute_bits, lib=None):
         scale = max(np.abs(u.real).max(), np.abs(u.imag).max())
         q, _ = fix_encode(rows, 16 if fmt == "fix16" else 32, absmax=scale, lib=lib)
         rows = fix_decode(q, scale, compute_bits, shape=rows.shape, lib=lib)
+    elif fmt == "sx24":
+        rows = sx24_rows_roundtrip(rows)
     elif fmt == "f32" or compute_bits == 32:
         rows = rows.astype(np.complex64).astype(np.complex128)
     full = np.concatenate([rows, su3_third_row(rows)[..., None, :]], axis=-2)

@@ -101,6 +101,23 @@ __global__ void k_reduce_max(const double *partial, int n, double *out) {
     }
 }
 
+// row r of a link as a 24-bit shared-exponent record: words 0-3 in 16-byte
+// plane r, word 4 in 4-byte plane r after the nrow 16-byte planes
+__device__ __forceinline__ void sx24_store_row(char *base, size_t vh, size_t s, int r, int nrow, const double *v) {
+    CVec<double> c;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        c.re[k] = v[2 * k];
+        c.im[k] = v[2 * k + 1];
+    }
+    unsigned w[SxFmt<24>::W];
+    SxCodec<24, double>::encode(c, w);
+    u32x4 a;
+    a.x = w[0]; a.y = w[1]; a.z = w[2]; a.w = w[3];
+    st<u32x4>(base + r * 16 * vh + 16 * s, a);
+    st<unsigned>(base + nrow * 16 * vh + r * 4 * vh + 4 * s, w[4]);
+}
+
 // canonical FP64 links [4][V][3][3] -> packed sub-fields (mu, parity)
 template <int GF> __global__ void k_gauge_pack(char *dst, const double *src, Geom g, const double *absmax) {
     const size_t V = 2 * (size_t)g.vh;
@@ -153,6 +170,9 @@ template <int GF> __global__ void k_gauge_pack(char *dst, const double *src, Geo
                 st<u32x4>(base + k * 16 * vh + 16 * s, w);
             }
             st<unsigned>(base + 32 * vh + 4 * s, q[16] | (q[17] << 16));
+        } else if (GF == GF_SX24) {
+#pragma unroll
+            for (int r = 0; r < 3; r++) sx24_store_row(base, vh, s, r, 3, u + 6 * r);
         } else {  // GF_FIX32
             unsigned q[18];
 #pragma unroll
@@ -295,6 +315,8 @@ template <int GF> __global__ void k_gauge_pack12(char *dst, const double *src, G
             b.y = q[10] | (q[11] << 16);
             st<u32x4>(base + 16 * s, a);
             st<u32x2>(base + 16 * vh + 8 * s, b);
+        } else if (GF == GF_SX24) {
+            for (int r = 0; r < 2; r++) sx24_store_row(base, vh, s, r, 2, w + 6 * r);
         } else {
             unsigned q[12];
             for (int k = 0; k < 12; k++) q[k] = (unsigned)(int)__builtin_rint(w[k] * qs);
@@ -733,6 +755,7 @@ hipError_t launch_gauge_pack(char *dst, const double *src, const Geom &g, int gf
     case GF_F32: hipLaunchKernelGGL((k_gauge_pack<GF_F32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
     case GF_FIX16: hipLaunchKernelGGL((k_gauge_pack<GF_FIX16>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
     case GF_FIX32: hipLaunchKernelGGL((k_gauge_pack<GF_FIX32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
+    case GF_SX24: hipLaunchKernelGGL((k_gauge_pack<GF_SX24>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, absmax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -753,6 +776,7 @@ hipError_t launch_gauge_pack12(char *dst, const double *src, const Geom &g, int 
     case GF_F32: hipLaunchKernelGGL((k_gauge_pack12<GF_F32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
     case GF_FIX16: hipLaunchKernelGGL((k_gauge_pack12<GF_FIX16>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
     case GF_FIX32: hipLaunchKernelGGL((k_gauge_pack12<GF_FIX32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
+    case GF_SX24: hipLaunchKernelGGL((k_gauge_pack12<GF_SX24>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, coef, umax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

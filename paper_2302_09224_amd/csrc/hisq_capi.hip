@@ -69,7 +69,8 @@ bool triplet_ok(const hisq_fmt &f) {
     case GF_FIX16 * 100 + SF_INT20 * 10 + 0:
     case GF_FIX32 * 100 + SF_INT30 * 10 + 1:
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0:
-    case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return true;
+    case GF_FIX32 * 100 + SF_INT24 * 10 + 0:
+    case GF_SX24 * 100 + SF_INT24 * 10 + 0: return true;
     default: return false;
     }
 }
@@ -79,9 +80,11 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 void gauge_args(DslashArgs &a, const hisq_gauge *g) {
     a.fat = (const char *)g->fat;
     a.lng = (const char *)g->lng;
-    const double q = g->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : 2147483647.0;
-    a.gfat = g->fat_max / q;
-    a.glong = g->long_max / q;
+    // fixed point: element = q * max / Q; shared-exponent rows carry their own scale
+    const double q = g->fmt == HISQ_GAUGE_FIX16 ? 32767.0 : g->fmt == HISQ_GAUGE_FIX32 ? 2147483647.0 : 0.0;
+    const bool fixed = q > 0.0;
+    a.gfat = fixed ? g->fat_max / q : 1.0;
+    a.glong = fixed ? g->long_max / q : 1.0;
     a.long_recon = g->long_recon == HISQ_RECON_12 ? 12 : 18;
     a.lcoef = g->long_coeff;
 }
@@ -152,7 +155,7 @@ extern "C" const char *hisq_last_error(void) { return hisq::g_err; }
 extern "C" const char *hisq_version(void) { return "libhisq 0.1 (gfx950)"; }
 
 extern "C" size_t hisq_gauge_bytes(const int dims[4], int gauge_fmt) {
-    if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > 3) return 0;
+    if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > HISQ_GAUGE_SX24) return 0;
     return gauge_field_bytes(dims, gauge_fmt);
 }
 
@@ -162,7 +165,7 @@ extern "C" size_t hisq_spinor_bytes(long nsites, int spinor_fmt) {
 }
 
 extern "C" size_t hisq_gauge_long_bytes(const int dims[4], int gauge_fmt, int long_recon) {
-    if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > 3) return 0;
+    if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > HISQ_GAUGE_SX24) return 0;
     if (long_recon == HISQ_RECON_18) return gauge_field_bytes(dims, gauge_fmt);
     if (long_recon != HISQ_RECON_12) return 0;
     const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
@@ -182,7 +185,7 @@ extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void 
     if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
         return set_error(HISQ_EINVAL, "hisq_gauge_pack: long_recon must be 18 or 12");
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "hisq_gauge_pack: dims must be even and >= 4");
-    if (gauge_fmt < 0 || gauge_fmt > 3) return set_error(HISQ_EINVAL, "hisq_gauge_pack: bad gauge format %d", gauge_fmt);
+    if (gauge_fmt < 0 || gauge_fmt > HISQ_GAUGE_SX24) return set_error(HISQ_EINVAL, "hisq_gauge_pack: bad gauge format %d", gauge_fmt);
     if (!aligned16(fat_dst) || !aligned16(long_dst) || !aligned16(fat_src) || !aligned16(long_src))
         return set_error(HISQ_EALIGN, "hisq_gauge_pack: pointers must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
@@ -226,7 +229,8 @@ extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void 
             imr = std::max(imr, c[5]);
             umax = std::max(umax, c[6]);
         }
-        const double tol = gauge_fmt == HISQ_GAUGE_F64 ? 1e-13 : gauge_fmt == HISQ_GAUGE_F32 ? 1e-7
+        const double tol = gauge_fmt == HISQ_GAUGE_F64 ? 1e-13
+                           : (gauge_fmt == HISQ_GAUGE_F32 || gauge_fmt == HISQ_GAUGE_SX24) ? 1e-7
                            : gauge_fmt == HISQ_GAUGE_FIX16 ? 1e-5 : 1e-9;
         const double lam = 0.5 * (mn + mxl);
         if (!(lam > 0.0) || (mxl - mn) > tol * lam || defect > tol || imr > tol || (np > 0 && nn > 0))

@@ -30,7 +30,7 @@
 namespace hisq {
 
 enum SpinorFmt { SF_F64 = 0, SF_F32 = 1, SF_HALF16 = 2, SF_INT20 = 3, SF_INT30 = 4, SF_INT24 = 5 };
-enum GaugeFmt { GF_F64 = 0, GF_F32 = 1, GF_FIX16 = 2, GF_FIX32 = 3 };
+enum GaugeFmt { GF_F64 = 0, GF_F32 = 1, GF_FIX16 = 2, GF_FIX32 = 3, GF_SX24 = 4 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -43,11 +43,11 @@ __host__ __device__ constexpr int spinor_site_bytes(int sf) {
     return sf == SF_F64 ? 48 : (sf == SF_F32 || sf == SF_INT30) ? 24 : sf == SF_INT24 ? 20 : 16;
 }
 __host__ __device__ constexpr int gauge_matrix_bytes(int gf) {
-    return gf == GF_F64 ? 144 : gf == GF_FIX16 ? 36 : 72;
+    return gf == GF_F64 ? 144 : gf == GF_FIX16 ? 36 : gf == GF_SX24 ? 60 : 72;
 }
 // two rows (12 reals) of a long link stored for reconstruction
 __host__ __device__ constexpr int gauge_matrix_bytes12(int gf) {
-    return gf == GF_F64 ? 96 : gf == GF_FIX16 ? 24 : 48;
+    return gf == GF_F64 ? 96 : gf == GF_FIX16 ? 24 : gf == GF_SX24 ? 40 : 48;
 }
 
 // ---------------------------------------------------------------------------

@@ -43,6 +43,9 @@ template <> struct LinkRaw<GF_F64> { f64x2 w[9]; };
 template <> struct LinkRaw<GF_F32> { f32x4 w[4]; f32x2 t; };
 template <> struct LinkRaw<GF_FIX16> { u32x4 w[2]; unsigned t; };
 template <> struct LinkRaw<GF_FIX32> { u32x4 w[4]; u32x2 t; };
+// rows as 24-bit shared-exponent records: words 0-3 of row r in 16-byte plane
+// r, word 4 of row r in 4-byte plane r after the three 16-byte planes
+template <> struct LinkRaw<GF_SX24> { u32x4 w[3]; unsigned t[3]; };
 
 template <int GF> __device__ __forceinline__ LinkRaw<GF> link_load(const char *sub, size_t vh, size_t s);
 
@@ -72,6 +75,26 @@ template <> __device__ __forceinline__ LinkRaw<GF_FIX32> link_load<GF_FIX32>(con
     for (int k = 0; k < 4; k++) L.w[k] = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
     L.t = ld_nt<u32x2>(sub + 64 * vh + 8 * s);
     return L;
+}
+
+template <> __device__ __forceinline__ LinkRaw<GF_SX24> link_load<GF_SX24>(const char *sub, size_t vh, size_t s) {
+    LinkRaw<GF_SX24> L;
+#pragma unroll
+    for (int r = 0; r < 3; r++) L.w[r] = ld_nt<u32x4>(sub + r * 16 * vh + 16 * s);
+#pragma unroll
+    for (int r = 0; r < 3; r++) L.t[r] = ld_nt<unsigned>(sub + 48 * vh + r * 4 * vh + 4 * s);
+    return L;
+}
+
+// one row of a shared-exponent link record
+template <class R> __device__ __forceinline__ void sx24_row(Mat<R> &U, int r, u32x4 a, unsigned t) {
+    const unsigned w[SxFmt<24>::W] = {a.x, a.y, a.z, a.w, t};
+    const CVec<R> v = SxCodec<24, R>::decode(w);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        U.re[3 * r + c] = v.re[c];
+        U.im[3 * r + c] = v.im[c];
+    }
 }
 
 template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_F64> &L, R) {
@@ -121,6 +144,14 @@ template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<G
     return U;
 }
 
+// shared-exponent rows carry their own scale
+template <class R> __device__ __forceinline__ Mat<R> link_decode(const LinkRaw<GF_SX24> &L, R) {
+    Mat<R> U;
+#pragma unroll
+    for (int r = 0; r < 3; r++) sx24_row(U, r, L.w[r], L.t[r]);
+    return U;
+}
+
 // Long links stored as two rows (12 reals) of U, where L = c * s * U with U in
 // SU(3), c a global real constant and s = +-1 the staggered phase of the link
 // (Sec. 1 "Compression": a special unitary matrix is fixed by two of its rows).
@@ -130,6 +161,7 @@ template <> struct LinkRaw12<GF_F64> { f64x2 w[6]; };
 template <> struct LinkRaw12<GF_F32> { f32x4 w[3]; };
 template <> struct LinkRaw12<GF_FIX16> { u32x4 w; u32x2 t; };
 template <> struct LinkRaw12<GF_FIX32> { u32x4 w[3]; };
+template <> struct LinkRaw12<GF_SX24> { u32x4 w[2]; unsigned t[2]; };
 
 template <int GF> __device__ __forceinline__ LinkRaw12<GF> link_load12(const char *sub, size_t vh, size_t s);
 template <> __device__ __forceinline__ LinkRaw12<GF_F64> link_load12<GF_F64>(const char *sub, size_t vh, size_t s) {
@@ -154,6 +186,15 @@ template <> __device__ __forceinline__ LinkRaw12<GF_FIX32> link_load12<GF_FIX32>
     LinkRaw12<GF_FIX32> L;
 #pragma unroll
     for (int k = 0; k < 3; k++) L.w[k] = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+
+template <> __device__ __forceinline__ LinkRaw12<GF_SX24> link_load12<GF_SX24>(const char *sub, size_t vh, size_t s) {
+    LinkRaw12<GF_SX24> L;
+#pragma unroll
+    for (int r = 0; r < 2; r++) L.w[r] = ld_nt<u32x4>(sub + r * 16 * vh + 16 * s);
+#pragma unroll
+    for (int r = 0; r < 2; r++) L.t[r] = ld_nt<unsigned>(sub + 32 * vh + r * 4 * vh + 4 * s);
     return L;
 }
 
@@ -212,6 +253,12 @@ template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw
         U.re[2 * k] = (R)(int)L.w[k].x * g; U.im[2 * k] = (R)(int)L.w[k].y * g;
         U.re[2 * k + 1] = (R)(int)L.w[k].z * g; U.im[2 * k + 1] = (R)(int)L.w[k].w * g;
     }
+    return complete_su3(U, c);
+}
+template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_SX24> &L, R, R c) {
+    Mat<R> U;
+#pragma unroll
+    for (int r = 0; r < 2; r++) sx24_row(U, r, L.w[r], L.t[r]);
     return complete_su3(U, c);
 }
 

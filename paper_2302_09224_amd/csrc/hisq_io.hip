@@ -102,7 +102,7 @@ hisq_status read_header(FILE *f, FileHeader &h) {
             h.bytes0 != spinor_field_bytes((size_t)h.nsites, h.fmt) || h.bytes1 != 0)
             return set_error(HISQ_EIO, "inconsistent spinor header");
     } else if (h.kind == HISQ_FIELD_GAUGE) {
-        if (h.fmt < 0 || h.fmt > HISQ_GAUGE_FIX32 || !dims_ok(h.dims) ||
+        if (h.fmt < 0 || h.fmt > HISQ_GAUGE_SX24 || !dims_ok(h.dims) ||
             (h.long_recon != HISQ_RECON_18 && h.long_recon != HISQ_RECON_12))
             return set_error(HISQ_EIO, "inconsistent gauge header");
         if (h.bytes0 != hisq_gauge_bytes(h.dims, h.fmt) ||
@@ -185,7 +185,7 @@ extern "C" hisq_status hisq_spinor_load(const char *path, void *dst, long nsites
 
 extern "C" hisq_status hisq_gauge_save(const char *path, const hisq_gauge *g, void *stream) {
     if (!path || !g || !g->fat || !g->lng) return set_error(HISQ_EINVAL, "hisq_gauge_save: null pointer");
-    if (!dims_ok(g->dims) || g->fmt < 0 || g->fmt > HISQ_GAUGE_FIX32 ||
+    if (!dims_ok(g->dims) || g->fmt < 0 || g->fmt > HISQ_GAUGE_SX24 ||
         (g->long_recon != HISQ_RECON_18 && g->long_recon != HISQ_RECON_12))
         return set_error(HISQ_EINVAL, "hisq_gauge_save: descriptor not filled by hisq_gauge_pack");
     FileHeader h;

@@ -21,13 +21,13 @@ LIB_PATH = os.path.join(_HERE, "libhisq.so")
 
 # storage formats (include/hisq.h)
 SPINOR_F64, SPINOR_F32, SPINOR_HALF16, SPINOR_INT20, SPINOR_INT30, SPINOR_INT24 = range(6)
-GAUGE_F64, GAUGE_F32, GAUGE_FIX16, GAUGE_FIX32 = range(4)
+GAUGE_F64, GAUGE_F32, GAUGE_FIX16, GAUGE_FIX32, GAUGE_SX24 = range(5)
 SPINOR_BYTES = {SPINOR_F64: 48, SPINOR_F32: 24, SPINOR_HALF16: 16, SPINOR_INT20: 16, SPINOR_INT30: 24,
                 SPINOR_INT24: 20}
-GAUGE_BYTES = {GAUGE_F64: 144, GAUGE_F32: 72, GAUGE_FIX16: 36, GAUGE_FIX32: 72}
+GAUGE_BYTES = {GAUGE_F64: 144, GAUGE_F32: 72, GAUGE_FIX16: 36, GAUGE_FIX32: 72, GAUGE_SX24: 60}
 SPINOR_NAMES = {SPINOR_F64: "f64", SPINOR_F32: "f32", SPINOR_HALF16: "half16", SPINOR_INT20: "int20",
                 SPINOR_INT30: "int30", SPINOR_INT24: "int24"}
-GAUGE_NAMES = {GAUGE_F64: "f64", GAUGE_F32: "f32", GAUGE_FIX16: "fix16", GAUGE_FIX32: "fix32"}
+GAUGE_NAMES = {GAUGE_F64: "f64", GAUGE_F32: "f32", GAUGE_FIX16: "fix16", GAUGE_FIX32: "fix32", GAUGE_SX24: "sx24"}
 
 HISQ_MAX_SHIFTS = 32
 HISQ_MAX_GRAD_BUFFER = 16
@@ -95,6 +95,7 @@ TRIPLETS = {
     "int30": (GAUGE_FIX32, SPINOR_INT30, 64),
     "int30_fp32": (GAUGE_FIX32, SPINOR_INT30, 32),
     "int24": (GAUGE_FIX32, SPINOR_INT24, 32),      # generated shared-exponent member
+    "sx24": (GAUGE_SX24, SPINOR_INT24, 32),        # links and spinors both 24-bit shared-exponent records
 }
 
 

@@ -11,7 +11,7 @@ import oracle
 from paper_2302_09224_amd import inputs
 
 FMT_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
-GFMT_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+GFMT_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32", 4: "sx24"}
 
 
 def need_gpu():
@@ -55,18 +55,23 @@ def spinor_records(packed, n, fmt):
 
 def gauge_reals(packed, dims, gfmt):
     """packed link field -> canonical-order array [4, V, 18] of the stored
-    integers (fixed point) or reals (IEEE)"""
+    integers (fixed point) or reals (IEEE); SX24: [4, V, 15], the five words
+    of each of the three row records"""
     V = oracle.volume(dims)
     vh = V // 2
     b = np.ascontiguousarray(packed)
-    mb = {0: 144, 1: 72, 2: 36, 3: 72}[gfmt]
-    dt = {0: np.float64, 1: np.float32, 2: np.int16, 3: np.int32}[gfmt]
-    out = np.zeros((4, V, 18), dtype=dt)
+    mb = {0: 144, 1: 72, 2: 36, 3: 72, 4: 60}[gfmt]
+    dt = {0: np.float64, 1: np.float32, 2: np.int16, 3: np.int32, 4: np.uint32}[gfmt]
+    out = np.zeros((4, V, 15 if gfmt == 4 else 18), dtype=dt)
     for mu in range(4):
         for p in range(2):
             sub = b[(2 * mu + p) * mb * vh:(2 * mu + p + 1) * mb * vh]
             if gfmt == 0:
                 r = sub.view(np.float64).reshape(9, vh, 2).transpose(1, 0, 2).reshape(vh, 18)
+            elif gfmt == 4:
+                p0 = sub[: 48 * vh].view(np.uint32).reshape(3, vh, 4)
+                p1 = sub[48 * vh: 60 * vh].view(np.uint32).reshape(3, vh, 1)
+                r = np.concatenate([p0, p1], axis=2).transpose(1, 0, 2).reshape(vh, 15)
             elif gfmt in (1, 3):
                 p0 = sub[: 64 * vh].view(dt).reshape(4, vh, 4).transpose(1, 0, 2).reshape(vh, 16)
                 p1 = sub[64 * vh: 72 * vh].view(dt).reshape(vh, 2)

@@ -46,6 +46,11 @@ def test_sizes(hisq):
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("int24"), hisq.hisq_solver_params_default()) > 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(3, 5, 64), hisq.hisq_solver_params_default()) == 0
     assert hisq.hisq_bicgstab_workspace_bytes(dims, 4, hisq.fmt("int24")) > 0
+    assert hisq.hisq_gauge_bytes(dims, hisq.GAUGE_SX24) == 4 * V * 60
+    assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_SX24, 12) == 4 * V * 40
+    assert hisq.hisq_gauge_bytes(dims, 5) == 0
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("sx24"), hisq.hisq_solver_params_default()) > 0
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(4, 3, 32), hisq.hisq_solver_params_default()) == 0
     assert hisq.hisq_gauge_bytes((5, 4, 4, 4), 0) == 0          # odd extent
     assert hisq.hisq_gauge_bytes((2, 4, 4, 4), 0) == 0          # extent below 4
     assert hisq.hisq_spinor_bytes(10, 9) == 0                   # unknown format

@@ -30,7 +30,7 @@ def residual(fat, lng, x, b, dims, mass):
     return np.linalg.norm(b - oracle.full_op(fat.numpy(), lng.numpy(), x, dims, mass)) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("sloppy", ["double", "single", "int30", "int30_fp32", "int20", "half", "int24"])
+@pytest.mark.parametrize("sloppy", ["double", "single", "int30", "int30_fp32", "int20", "half", "int24", "sx24"])
 @pytest.mark.parametrize("dims,kind,mass", [((8, 8, 8, 8), "near_unit", 0.05), ((6, 8, 10, 12), "haar", 0.1)])
 def test_bicgstab4(sloppy, dims, kind, mass):
     hisq = need_gpu()

@@ -48,7 +48,7 @@ def test_spinor_pack_bit_exact(fmt, n):
     assert np.array_equal(back.view(np.float64), want.view(np.float64))
 
 
-@pytest.mark.parametrize("gfmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("gfmt", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 4)])
 def test_gauge_pack_bit_exact(gfmt, dims):
     hisq = need_gpu()
@@ -64,6 +64,8 @@ def test_gauge_pack_bit_exact(gfmt, dims):
             assert np.array_equal(got, reals)
         elif gfmt == 1:
             assert np.array_equal(got, reals.astype(np.float32))
+        elif gfmt == 4:
+            assert np.array_equal(got, oracle.sx24_rows_encode(src).reshape(4, -1, 15))
         else:
             q, _ = oracle.fix_encode(src, 16 if gfmt == 2 else 32)
             assert np.array_equal(got.reshape(-1), q)

@@ -22,9 +22,9 @@ from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24"]
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"]
 SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
-GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32", 4: "sx24"}
 # 4^4: x+3mu and x-mu coincide; (6,8,10,12): Vh = 2880, a ragged last block;
 # (8,8,8,8): Vh = 2048, whole blocks; (4,6,4,8) non-cubic
 DIMS = [(4, 4, 4, 4), (6, 8, 10, 12), (8, 8, 8, 8), (4, 6, 4, 8)]
@@ -121,7 +121,7 @@ def test_xpay(name):
 
 
 @pytest.mark.parametrize("name,tol", [("double", 1e-13), ("single", 2e-6), ("int30", 1e-8), ("int20", 2e-4),
-                                      ("half", 2e-4), ("int24", 4e-6)])
+                                      ("half", 2e-4), ("int24", 4e-6), ("sx24", 4e-6)])
 def test_normal_op(name, tol):
     """(4m^2+s) p - D_eo D_oe p; the intermediate D_oe p is stored in the
     sloppy format, so the bound is the format's precision (max-norm relative)"""
@@ -144,7 +144,7 @@ def test_normal_op(name, tol):
     assert rel_inf(y, ref) <= tol
 
 
-@pytest.mark.parametrize("name", ["double", "single", "half", "int20", "int30", "int24"])
+@pytest.mark.parametrize("name", ["double", "single", "half", "int20", "int30", "int24", "sx24"])
 @pytest.mark.parametrize("nrhs", [1, 3, 16])
 def test_batched_matches_single(name, nrhs):
     """one link load for a block of right-hand sides gives every right-hand
@@ -219,7 +219,7 @@ def test_full_size_sampled(recon):
         umax = float(torch.view_as_real(U).abs().amax())
         del U
         u_h = lng_h / (-1.0 / 24.0 * oracle.long_phases(dims).reshape(4 * V)[lidx, None, None])
-    for name in ("half", "int20", "int30", "int24", "single", "double"):
+    for name in ("half", "int20", "int30", "int24", "sx24", "single", "double"):
         f = hisq.fmt(name)
         pg = hisq.pack_gauge(fat, lng, dims, f.gauge, long_recon=recon)
         pin = hisq.pack_spinor(psi, f.spinor)
@@ -244,6 +244,8 @@ def test_full_size_sampled(recon):
             if gname in ("fix16", "fix32"):
                 q, _ = oracle.fix_encode(rows, 16 if gname == "fix16" else 32, absmax=umax)
                 rows = oracle.fix_decode(q, umax, f.compute, shape=rows.shape)
+            elif gname == "sx24":
+                rows = oracle.gauge_roundtrip(rows, "sx24", f.compute)
             elif gname == "f32" or f.compute == 32:
                 rows = rows.astype(np.complex64).astype(np.complex128)
             full3 = np.concatenate([rows, oracle.su3_third_row(rows)[:, None, :]], axis=1)

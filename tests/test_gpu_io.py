@@ -49,7 +49,7 @@ def test_spinor_several_chunks(tmp_path):
     assert nbytes > 64 << 20 and torch.equal(back[:nbytes], packed[:nbytes])
 
 
-@pytest.mark.parametrize("gfmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("gfmt", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("recon", [18, 12])
 def test_gauge_roundtrip_same_dslash(gfmt, recon, tmp_path):
     hisq = need_gpu()
@@ -65,7 +65,7 @@ def test_gauge_roundtrip_same_dslash(gfmt, recon, tmp_path):
     assert torch.equal(lg.fat[:b0], pg.fat[:b0]) and torch.equal(lg.lng[:b1], pg.lng[:b1])
     for k in ("fat_max", "long_max", "long_coeff", "long_recon", "fmt"):
         assert getattr(lg.desc, k) == getattr(pg.desc, k), k
-    name = {0: "double", 1: "single", 2: "int20", 3: "int30"}[gfmt]
+    name = {0: "double", 1: "single", 2: "int20", 3: "int30", 4: "sx24"}[gfmt]
     f = hisq.fmt(name)
     vh = int(np.prod(dims)) // 2
     pin = hisq.pack_spinor(inputs.gaussian_spinor(vh, 960, device="cuda"), f.spinor)

@@ -11,9 +11,9 @@ from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24"]
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"]
 SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
-GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32", 4: "sx24"}
 # the uneven batch of the block-solver workload plus a non-cubic one
 LATTICES = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (4, 6, 4, 8)]
 

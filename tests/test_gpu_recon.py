@@ -11,9 +11,9 @@ from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24"]
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"]
 SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
-GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32"}
+GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32", 4: "sx24"}
 
 
 def eps_c(compute):
@@ -47,7 +47,7 @@ def test_dslash_recon12(name, dims):
             assert worst <= 1.0, f"{name} {dims} {kind} parity {parity}: max err/bound {worst:.3f}"
 
 
-@pytest.mark.parametrize("name", ["single", "half", "int20", "int30"])
+@pytest.mark.parametrize("name", ["single", "half", "int20", "int30", "sx24"])
 def test_batched_recon12_matches_single(name):
     hisq = need_gpu()
     dims, nrhs = (6, 8, 10, 12), 5
@@ -91,7 +91,7 @@ def _full(dims, ev, v):
     return f
 
 
-@pytest.mark.parametrize("sloppy", ["half", "int20", "single"])
+@pytest.mark.parametrize("sloppy", ["half", "int20", "single", "sx24"])
 def test_cg_recon12_sloppy(sloppy):
     """mixed CG whose sloppy operator reads two-row long links; the reliable
     updates use the full FP64 operator, so the solution meets the target"""

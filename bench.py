@@ -223,6 +223,7 @@ def bench_cg_stability(hisq, inputs, torch, dev, dims=(16, 16, 16, 16), masses=(
             row[name] = dict(status=status, iters=st["iters"] if st else maxiter,
                              reliable_updates=st["reliable_updates"] if st else None,
                              true_resid=st["true_resid"] if st else None, seconds=round(time.perf_counter() - t, 3))
+            log(f"[bench] CG stability m={m} {name}: {row[name]['iters']} it, {status}, {row[name]['seconds']} s")
         out[f"m={m}"] = row
         log(f"[bench] CG stability {dims} Haar m={m}: " +
             ", ".join(f"{k} {v['iters']} it ({v['status']})" for k, v in row.items()))

@@ -15,7 +15,7 @@ analog), the roofline of the dominant kernel, the FP64 GPU multi-shift
 comparator (time to the same residuals), and the FP64 CPU oracle timed on the
 host cores as a reported baseline.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-fp64] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-fp64] [--no-cpu] [--no-stability]
 """
 from __future__ import annotations
 
@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--batch-refine", type=int, default=1, choices=(0, 1),
                     help="refine the shifted systems together (1) or one after another (0)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-stability", action="store_true",
+                    help="skip the 16^4 CG-stability table (not part of the timed step)")
     ap.add_argument("--no-alt", action="store_true", help="skip the double-single-half mixed solve")
     ap.add_argument("--bicgstab", type=str, default=None, metavar="X,Y,Z,T",
                     help="also run the BiCGStab(4) precision comparison on this lattice (see --bicgstab-mass)")
@@ -374,7 +376,7 @@ def main():
         batched = bench_batched(args, hisq, inputs, torch, dev)
     multi = bench_multi(hisq, inputs, torch, dev)
     batched_cg = None if args.kernels_only else bench_batched_cg(hisq, inputs, torch, dev)
-    stability = None if args.kernels_only else bench_cg_stability(hisq, inputs, torch, dev)
+    stability = None if (args.kernels_only or args.no_stability) else bench_cg_stability(hisq, inputs, torch, dev)
     bicg = None
     if args.bicgstab:
         bicg = bench_bicgstab(hisq, inputs, torch, dev, tuple(int(v) for v in args.bicgstab.split(",")),

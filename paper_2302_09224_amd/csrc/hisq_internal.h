@@ -82,7 +82,9 @@ struct DslashArgs {
 
 // Launch shape of one Dslash launch: each lane accumulates `nr` right-hand
 // sides of one site, `rg` adjacent lanes share a site (nr*rg right-hand sides
-// per launch), the 16 hops are loaded in stages of `stage`, `block` threads,
+// per launch), the 16 hops are loaded in stages of `stage` (negative: stages
+// of -stage hops, double-buffered, the next stage's loads issued before this
+// stage's arithmetic; one right-hand side per lane only), `block` threads,
 // `grid` blocks (0: one tile of lanes per block; otherwise a persistent grid,
 // a multiple of 8, sweeping the tiles), `sweep` the order of the tiles: 0 =
 // XCD k (blocks b with b % 8 == k) takes the k-th eighth of the lattice, 1 =

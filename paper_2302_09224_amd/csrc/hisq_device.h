@@ -217,14 +217,20 @@ template <class R> struct SpinorIO<SF_HALF16, R> {
 // q = rint(v * 2^(127-E)), v = q * 2^(E-127).
 template <class R> struct SpinorIO<SF_INT20, R> {
     static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
-        float sc = pow2_f32(w.w >> 24);
+        // A field inside one word is a signed bit-field extract.  A field split
+        // over two words has its high bits at the top of the earlier word, so
+        // inserting the next word's low bits just below them gives the field
+        // times 2^12 as a signed 32-bit integer (exact in FP32); its scale is
+        // sc * 2^-12 (exact, a subnormal power of two for E < 13).
+        const float sc = pow2_f32(w.w >> 24);
+        const float sl = sc * 0x1p-12f;
         CVec<R> v;
-        v.re[0] = (float)sext20(w.x) * sc;
-        v.im[0] = (float)sext20(((w.x >> 20) << 8) | (w.y & 0xffu)) * sc;
-        v.re[1] = (float)sext20(w.y >> 8) * sc;
-        v.im[1] = (float)sext20(((w.y >> 28) << 16) | (w.z & 0xffffu)) * sc;
-        v.re[2] = (float)sext20(((w.z >> 16) << 4) | (w.w & 0xfu)) * sc;
-        v.im[2] = (float)sext20(w.w >> 4) * sc;
+        v.re[0] = (float)((int)(w.x << 12) >> 12) * sc;
+        v.im[0] = (float)(int)((w.x & 0xfff00000u) | ((w.y & 0xffu) << 12)) * sl;
+        v.re[1] = (float)((int)(w.y << 4) >> 12) * sc;
+        v.im[1] = (float)(int)((w.y & 0xf0000000u) | ((w.z & 0xffffu) << 12)) * sl;
+        v.re[2] = (float)(int)((w.z & 0xffff0000u) | ((w.w & 0xfu) << 12)) * sl;
+        v.im[2] = (float)((int)(w.w << 8) >> 12) * sc;
         return v;
     }
     static __device__ __forceinline__ u32x4 encode(const CVec<R> &vin) {

@@ -459,8 +459,8 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     CVec<R> acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
-    if (NR > 1 && STAGE == 1) {
-        // several right-hand sides per lane: one hop at a time (bounded registers)
+    if (NR > 8 && STAGE == 1) {
+        // 16 right-hand sides per lane: one hop at a time in a loop (bounded registers)
         const Coords c = coords_of(g, s, p);
 #pragma unroll 1
         for (int h = 0; h < 16; h++) {
@@ -501,7 +501,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     constexpr int SB = STAGE < 0 ? -STAGE : STAGE;
     constexpr bool PIPE = STAGE < 0;
     constexpr int NBUF = PIPE ? 2 : 1;
-    constexpr int NST = (NR > 1 && STAGE == 1) ? 0 : 16 / SB;
+    constexpr int NST = (NR > 8 && STAGE == 1) ? 0 : 16 / SB;
     const Nbrs n = neighbours(g, s, p);
     LinkRaw<GF> L[NBUF][SB];
     LinkRaw12<GF> L12[NBUF][SB];

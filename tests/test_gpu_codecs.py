@@ -79,3 +79,22 @@ def test_gauge_pack_rejects_nonfinite():
     with pytest.raises(hisq.HisqError) as e:
         hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16)
     assert e.value.status == -7
+
+
+@pytest.mark.parametrize("fmt", [3, 5])
+def test_shared_exponent_tiny_sites_bit_exact(fmt):
+    """sites near the bottom of the FP32 range (exponents E < 13, where the
+    decode's scale for word-straddling fields is a subnormal power of two)"""
+    hisq = need_gpu()
+    n = 4096
+    rng = np.random.default_rng(700 + fmt)
+    v = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    v *= 10.0 ** rng.uniform(-37.5, -30, size=(n, 1))
+    v = v.astype(np.complex64).astype(np.complex128)     # FP32 inputs, as the encoders see them
+    packed = hisq.pack_spinor(torch.from_numpy(v).cuda(), fmt)
+    rec = spinor_records(packed.cpu().numpy(), n, fmt)
+    name = {3: "int20", 5: "int24"}[fmt]
+    assert np.array_equal(rec, oracle.int20_encode(v) if fmt == 3 else oracle.int24_encode(v))
+    back = hisq.unpack_spinor(packed, n, fmt).cpu().numpy()
+    assert np.array_equal(back.view(np.float64), oracle.spinor_decode_records(rec, name).view(np.float64))
+    assert (((rec[:, 3] >> 24) if fmt == 3 else ((rec[:, 4] >> 16) & 0xFF)) < 13).any()

@@ -435,77 +435,6 @@ template <class R> struct SpinorIO<SF_INT24, R> {
 };
 
 // ---------------------------------------------------------------------------
-// gauge codecs: load one 3x3 complex matrix of sub-field `sub` (Vh matrices)
-// ---------------------------------------------------------------------------
-
-template <int GF, class R> struct GaugeIO;
-
-template <class R> struct GaugeIO<GF_F64, R> {
-    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R) {
-        Mat<R> U;
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            f64x2 w = ld_nt<f64x2>(sub + k * 16 * vh + 16 * s);
-            U.re[k] = (R)w.x;
-            U.im[k] = (R)w.y;
-        }
-        return U;
-    }
-};
-
-template <class R> struct GaugeIO<GF_F32, R> {
-    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R) {
-        Mat<R> U;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            f32x4 w = ld_nt<f32x4>(sub + k * 16 * vh + 16 * s);
-            U.re[2 * k] = w.x; U.im[2 * k] = w.y; U.re[2 * k + 1] = w.z; U.im[2 * k + 1] = w.w;
-        }
-        f32x2 t = ld_nt<f32x2>(sub + 64 * vh + 8 * s);
-        U.re[8] = t.x;
-        U.im[8] = t.y;
-        return U;
-    }
-};
-
-// 16-bit fixed point: u = q * g, g = (compute precision)(max/32767)
-template <class R> struct GaugeIO<GF_FIX16, R> {
-    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R g) {
-        Mat<R> U;
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-            u32x4 w = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
-            unsigned ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                U.re[4 * k + j] = (R)sext16(ws[j]) * g;
-                U.im[4 * k + j] = (R)sext16(ws[j] >> 16) * g;
-            }
-        }
-        unsigned t = ld_nt<unsigned>(sub + 32 * vh + 4 * s);
-        U.re[8] = (R)sext16(t) * g;
-        U.im[8] = (R)sext16(t >> 16) * g;
-        return U;
-    }
-};
-
-template <class R> struct GaugeIO<GF_FIX32, R> {
-    static __device__ __forceinline__ Mat<R> load(const char *sub, size_t vh, size_t s, R g) {
-        Mat<R> U;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            u32x4 w = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
-            U.re[2 * k] = (R)(int)w.x * g; U.im[2 * k] = (R)(int)w.y * g;
-            U.re[2 * k + 1] = (R)(int)w.z * g; U.im[2 * k + 1] = (R)(int)w.w * g;
-        }
-        u32x2 t = ld_nt<u32x2>(sub + 64 * vh + 8 * s);
-        U.re[8] = (R)(int)t.x * g;
-        U.im[8] = (R)(int)t.y * g;
-        return U;
-    }
-};
-
-// ---------------------------------------------------------------------------
 // lattice geometry (checkerboarded, X even)
 // ---------------------------------------------------------------------------
 

@@ -234,14 +234,14 @@ def bench_cg_stability(hisq, inputs, torch, dev, dims=(16, 16, 16, 16), masses=(
 
 def bench_bicgstab(hisq, inputs, torch, dev, dims, mass, kind="near_unit", tol=1e-10, l=4, maxiter=200000):
     """Table 2 analog (Sec. 6.1): BiCGStab(4) for the whole-lattice operator
-    2m + D in pure double and double-{single, int30, int20, half}."""
+    2m + D in pure double and double-{single, int30, int24, sx24, int20, half}."""
     V = dims[0] * dims[1] * dims[2] * dims[3]
     fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
     b = inputs.gaussian_spinor(V, inputs.SOURCE_SEED + 90, device=dev)
     g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
     del fat, lng
     out = {}
-    for name in ("double", "single", "int30", "int20", "half"):
+    for name in ("double", "single", "int30", "int24", "sx24", "int20", "half"):
         f = hisq.fmt(name)
         gs = g64 if name == "double" else _pack_like(hisq, inputs, dims, f.gauge, dev, kind)
         kw = dict(delta=0.0) if name == "double" else {}

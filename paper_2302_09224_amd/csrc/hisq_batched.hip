@@ -55,32 +55,35 @@ __device__ __forceinline__ void csum(const double *col, int nb, double (&v)[1], 
     __syncthreads();
 }
 
+// one block per right-hand side j (launched with nrhs blocks): the columns are
+// independent, and a Dslash over rg lanes per site leaves rg times more partials
+// per column than sites per block; each column is summed in a fixed order
 __global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, NbList nl, int nrhs, int jb, Guard gd) {
     __shared__ double lds[16];
-    if (!gd.pass()) return;
-    for (int j = 0; j < nrhs; j++) {
-        double v[1];
-        csum(partial + (size_t)j * nl.pstride, nl.nb[j], v, lds);
-        if (threadIdx.x) continue;
-        const double pi = v[0];
-        c->bpi[j] = pi;
-        if (!c->bactive[j]) {
-            c->balpha[j] = 0.0;
-            c->balpha_buf[jb][j] = 0.0;
-            continue;
-        }
-        if (!(pi > 0.0) || !__builtin_isfinite(pi)) {
-            c->stop = gd.j - 1;
-            c->reason = STOP_BREAKDOWN;
-            c->breakdown = 1;
-            c->balpha[j] = 0.0;
-            c->balpha_buf[jb][j] = 0.0;
-            continue;
-        }
-        const double a = c->brho[j] / pi;
-        c->balpha[j] = a;
-        c->balpha_buf[jb][j] = a;
+    const int j = blockIdx.x;
+    if (j >= nrhs || !gd.pass()) return;
+    double v[1];
+    csum(partial + (size_t)j * nl.pstride, nl.nb[j], v, lds);
+    if (threadIdx.x) return;
+    const double pi = v[0];
+    c->bpi[j] = pi;
+    if (!c->bactive[j]) {
+        c->balpha[j] = 0.0;
+        c->balpha_buf[jb][j] = 0.0;
+        return;
     }
+    if (!(pi > 0.0) || !__builtin_isfinite(pi)) {
+        // every block that finds a breakdown writes the same stop record
+        c->stop = gd.j - 1;
+        c->reason = STOP_BREAKDOWN;
+        c->breakdown = 1;
+        c->balpha[j] = 0.0;
+        c->balpha_buf[jb][j] = 0.0;
+        return;
+    }
+    const double a = c->brho[j] / pi;
+    c->balpha[j] = a;
+    c->balpha_buf[jb][j] = a;
 }
 
 __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nrhs, Guard gd) {
@@ -338,7 +341,7 @@ struct BRun {
         Bk.pstride = ms_.nl.pstride;
         Bk.guard = gns;
         HISQ_TRY_HIP(launch_dslash(Bk, fmt, ms_.plan, st, nullptr));
-        hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, ms_.nl, nrhs, jb, gns);
+        hipLaunchKernelGGL(k_bfin_alpha, dim3(nrhs), dim3(FIN_THREADS), 0, st, c, B->partial, ms_.nl, nrhs, jb, gns);
         HISQ_TRY_HIP(hipGetLastError());
         HISQ_TRY_HIP(launch_bcg_axpy(B->rs, B->aps, c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, gns, st));
         hipLaunchKernelGGL(k_bfin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs, gns);

@@ -261,6 +261,52 @@ def bench_bicgstab(hisq, inputs, torch, dev, dims, mass, kind="near_unit", tol=1
     return dict(lattice=list(dims), links=kind, mass=mass, tol=tol, l=l, solvers=out)
 
 
+def bench_formats(hisq, inputs, torch, dev, reps, dims=(32, 32, 32, 32), mass=0.01, tol=1e-10):
+    """Per-triplet table on 32^4 (near-unit links, m = 0.01): Dslash time and
+    algorithmic GB/s (18-real links), and the mixed CG to a 1e-10 true residual
+    with that triplet as the sloppy one (iterations, reliable updates, time)."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    vh = V // 2
+    fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 13, device=dev)
+    psi = inputs.gaussian_spinor(vh, inputs.SOURCE_SEED + 13, device=dev)
+    b = inputs.gaussian_spinor(vh, inputs.SOURCE_SEED + 14, device=dev)
+    g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name in ("double", "single", "int30", "int30_fp32", "int24", "sx24", "int20", "half"):
+        f = hisq.fmt(name)
+        pg = g64 if f.gauge == hisq.GAUGE_F64 else hisq.pack_gauge(fat, lng, dims, f.gauge)
+        pin = hisq.pack_spinor(psi, f.spinor)
+        y = torch.empty_like(pin)
+        for _ in range(3):
+            hisq.hisq_dslash(y, pin, pg.desc, 0, f)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            hisq.hisq_dslash(y, pin, pg.desc, 0, f)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        nbytes = vh * (16 * hisq.GAUGE_BYTES[f.gauge] + 2 * hisq.SPINOR_BYTES[f.spinor])
+        hisq.cg_solve(b, g64, pg, mass, tol=tol, sloppy=name)            # launch shapes tuned here
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = hisq.cg_solve(b, g64, pg, mass, tol=tol, sloppy=name)
+        torch.cuda.synchronize()
+        out[name] = dict(triplet=repr(f), dslash_us=round(us, 1), gbs=round(nbytes / us / 1e3, 1),
+                         cg_iters=st["iters"], reliable_updates=st["reliable_updates"],
+                         true_resid=float(f"{st['true_resid']:.3g}"), cg_seconds=round(time.perf_counter() - t, 4))
+        log(f"[bench] 32^4 {name:10s} dslash {us:7.1f} us {out[name]['gbs']:7.1f} GB/s; CG {st['iters']} it, "
+            f"{out[name]['cg_seconds']:.3f} s")
+        del pin, y
+        if pg is not g64:
+            del pg
+        torch.cuda.empty_cache()
+    del g64, fat, lng
+    torch.cuda.empty_cache()
+    return dict(lattice=list(dims), mass=mass, tol=tol, triplets=out)
+
+
 def _pack_like(hisq, inputs, dims, gf, dev, kind):
     fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
     return hisq.pack_gauge(fat, lng, dims, gf, long_recon=12)
@@ -290,6 +336,10 @@ def main():
     ap.add_argument("--bicgstab-mass", type=float, default=0.001)
     ap.add_argument("--bicgstab-links", type=str, default="near_unit", choices=("near_unit", "haar"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-cg", action="store_true",
+                    help="also time a lone FP64 CG per shift (the plain FP64 baseline, about 15 s)")
+    ap.add_argument("--formats", action="store_true",
+                    help="per-triplet Dslash GB/s and mixed CG iterations/time on 32^4, m = 0.01")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -381,9 +431,10 @@ def main():
     if args.bicgstab:
         bicg = bench_bicgstab(hisq, inputs, torch, dev, tuple(int(v) for v in args.bicgstab.split(",")),
                               args.bicgstab_mass, args.bicgstab_links)
+    formats = bench_formats(hisq, inputs, torch, dev, args.dslash_reps) if args.formats else None
     if args.kernels_only:
         tuning = hisq.hisq_tune_report().strip().splitlines()
-        print(json.dumps(dict(kernels=kernels, batched=batched, multi_lattice=multi, tuning=tuning,
+        print(json.dumps(dict(kernels=kernels, batched=batched, multi_lattice=multi, tuning=tuning, formats=formats,
                               config={"lattice": list(dims)})))
         return
     gauges.clear()
@@ -464,6 +515,26 @@ def main():
                     phase_seconds=[round(v, 3) for v in st64["phase_seconds"]],
                     resid_max=max(st64["shift_resid"]), speedup_mixed=round(t64 / (ms_per_step / 1e3), 3))
         log(f"[bench]   FP64: {t64:.2f}s, iters {st64['iters']}, refine {st64['refine_iters']}")
+    fp64_cg = None
+    if args.fp64_cg:
+        log("[bench] FP64 CG per shift (one plain FP64 CG solve per shift, no reliable updates)")
+        g64c = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=args.recon)
+        hisq.cg_solve(b, g64c, g64c, args.mass, shift=shifts[-1], tol=args.tol, sloppy="double", delta=0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, res = [], []
+        for sv, tv in zip(shifts, tols):
+            x1, s1 = hisq.cg_solve(b, g64c, g64c, args.mass, shift=sv, tol=tv, sloppy="double", delta=0.0)
+            its.append(s1["iters"])
+            res.append(float(f"{s1['true_resid']:.3g}"))
+            del x1
+        torch.cuda.synchronize()
+        tcg = time.perf_counter() - t0
+        fp64_cg = dict(seconds=round(tcg, 3), iters=its, resid=res,
+                       speedup_mixed=round(tcg / (ms_per_step / 1e3), 3))
+        log(f"[bench]   FP64 CG per shift: {tcg:.2f}s, iters {its}")
+        del g64c
+        torch.cuda.empty_cache()
     alt = None
     if not args.no_alt:
         log("[bench] mixed double-single-half multi-shift")
@@ -539,13 +610,15 @@ def main():
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],
                        "resid_after_ms": [float(f"{r:.3g}") for r in last["shift_resid_ms"]],
                        "resid": [float(f"{r:.3g}") for r in last["shift_resid"]], "all_converged": resid_ok,
-                       "step_alg_bytes": step_bytes, "fp64_gpu": fp64, "double_single_half": alt},
+                       "step_alg_bytes": step_bytes, "fp64_gpu": fp64, "fp64_cg_per_shift": fp64_cg,
+                       "double_single_half": alt},
         "kernels": kernels,
         "batched": batched,
         "multi_lattice": multi,
         "batched_cg": batched_cg,
         "cg_stability": stability,
         "bicgstab": bicg,
+        "formats": formats,
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,

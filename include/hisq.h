@@ -202,7 +202,8 @@ typedef struct {
     double delta;        /* reliable update when |r| < delta * max|r| since the last one (Sec. 3 footnote: 0.1);
                             <= 0 disables reliable updates (the residual is only checked at the end) */
     int maxiter;         /* iteration cap per solve (per phase for multi-shift) */
-    int grad_buffer;     /* gradient vectors buffered before the FP64 solution update (Sec. 3.1 item 1), 1..16 */
+    int grad_buffer;     /* gradient vectors buffered before the FP64 solution update (Sec. 3.1 item 1), 1..16;
+                            default 8 */
     int pr_beta;         /* 1: Polak-Ribiere beta (Sec. 3.1 item 3); 0: Fletcher-Reeves */
     int reproject;       /* 1: re-project the gradient vector at each reliable update (Sec. 3.1 item 2) */
     int poll_every;      /* iterations enqueued between host polls of the device state (rounded up to a

@@ -693,7 +693,7 @@ extern "C" void hisq_solver_params_default(hisq_solver_params *p) {
     memset(p, 0, sizeof(*p));
     p->delta = 0.1;
     p->maxiter = 100000;
-    p->grad_buffer = 4;
+    p->grad_buffer = 8;
     p->pr_beta = 1;
     p->reproject = 1;
     p->poll_every = 32;

@@ -60,7 +60,7 @@ def test_sizes(hisq):
     assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_FIX32, 12) == 4 * V * 48
     assert hisq.hisq_gauge_long_bytes(dims, hisq.GAUGE_F32, 8) == 0  # unknown storage
     p = hisq.hisq_solver_params_default()
-    assert p.delta == 0.1 and p.grad_buffer == 4 and p.pr_beta == 1 and p.reproject == 1
+    assert p.delta == 0.1 and p.grad_buffer == 8 and p.pr_beta == 1 and p.reproject == 1
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("half"), p) > 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(2, 1, 32), p) == 0   # unsupported triplet
     assert hisq.hisq_multishift_workspace_bytes(dims, 33, hisq.fmt("single"), hisq.fmt("half"), p) == 0

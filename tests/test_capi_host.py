@@ -154,3 +154,36 @@ def test_tune_set_validation(hisq):
             hisq.hisq_tune_set(*args)
     hisq.hisq_tune_clear()
     assert hisq.hisq_tune_report() == ""
+
+
+def test_workspace_too_small_is_reported_before_any_device_work(hisq):
+    """every solver checks its workspace before touching the device (pointers
+    here are never dereferenced)"""
+    import ctypes
+    lib = hisq.load()
+    dims = (4, 4, 4, 4)
+    fake = 1 << 20
+
+    def gauge(fmt):
+        g = hisq.hisq_gauge()
+        for k in range(4):
+            g.dims[k] = dims[k]
+        g.fmt, g.fat, g.lng, g.fat_max, g.long_max = fmt, fake, fake, 1.0, 1.0
+        g.long_recon, g.long_coeff = 18, 1.0
+        return g
+
+    g64, g16 = gauge(hisq.GAUGE_F64), gauge(hisq.GAUGE_FIX16)
+    p = hisq.hisq_solver_params_default()
+    st = hisq.hisq_solver_stats()
+    half = hisq.fmt("half")
+    assert lib.hisq_cg_solve(fake, fake, g64, g16, 0.1, 0.0, 1e-10, half, p, fake, 16, ctypes.byref(st), None) == -6
+    shifts = (ctypes.c_double * 2)(0.0, 0.1)
+    tols = (ctypes.c_double * 2)(1e-10, 1e-10)
+    xs = (ctypes.c_void_p * 2)(fake, fake)
+    assert lib.hisq_multishift_cg_solve(xs, fake, shifts, 2, tols, g64, g16, g16, 0.1, half, half, p, fake, 16,
+                                        ctypes.byref(st), None) == -6
+    assert lib.hisq_cg_solve_batched(fake, fake, 4, g64, g16, 0.1, 0.0, 1e-10, half, p, fake, 16,
+                                     ctypes.byref(st), None) == -6
+    assert lib.hisq_bicgstab_solve(fake, fake, g64, g16, 0.1, 1e-10, 4, half, p, fake, 16, ctypes.byref(st),
+                                   None) == -6
+    assert "workspace" in hisq.hisq_last_error()

@@ -227,3 +227,33 @@ def test_multishift_error_estimate_reliable_updates():
         res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[i].cpu().numpy()), full(dims, ev, b),
                                    dims, mass, s)
         assert res <= 1e-10 * (1 + 1e-6), (i, res)
+
+
+def test_iteration_caps_report_enoconv():
+    """an iteration cap ends every solver with HISQ_ENOCONV, its stats filled
+    and the best iterate finite"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.01
+    fat, lng, ev, b = setup(dims, "haar")
+    pg = packed(hisq, fat, lng, dims, ["double", "half"])
+    bt = torch.from_numpy(b).cuda()
+    xs, st = hisq.multishift_cg_solve(bt, [0.0, 0.01, 0.1], 1e-12, pg[0], pg[2], pg[2], mass, ms_fmt="half",
+                                      ref_fmt="half", maxiter=10)
+    assert st["status"] == "HISQ_ENOCONV" and st["iters"] >= 10, st
+    assert all(bool(torch.isfinite(torch.view_as_real(x)).all()) for x in xs)
+    bs = inputs.gaussian_spinor(ev.size, inputs.RHS_SEED, nrhs=4).cuda()
+    x, st = hisq.cg_solve_batched(bs, pg[0], pg[2], mass, tol=1e-12, sloppy="half", maxiter=6)
+    assert st["status"] == "HISQ_ENOCONV", st
+    assert bool(torch.isfinite(torch.view_as_real(x)).all())
+
+
+def test_nonfinite_source_is_a_breakdown():
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "single"])
+    bad = b.copy()
+    bad[17, 1] = complex(float("nan"), 0.0)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.cg_solve(torch.from_numpy(bad).cuda(), pg[0], pg[1], mass, tol=1e-10, sloppy="single")
+    assert e.value.status == -5

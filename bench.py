@@ -348,8 +348,8 @@ def main():
                     help="also time the 16-right-hand-side Dslash on 32^3x64 against 16 single applications")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
+              "domain decomposition over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

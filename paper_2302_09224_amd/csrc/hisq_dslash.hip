@@ -60,7 +60,7 @@ bool tuning_enabled() {
 
 // candidate shapes for a block of c right-hand sides (c a power of two <= 16)
 // grids: 0 = one tile per block; 256*k = a persistent grid of k blocks per CU
-std::vector<DslashTile> candidates(int c, bool batched_ok) {
+std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32) {
     std::vector<DslashTile> v;
     if (c == 1) {
         for (int st : {1, 2, 4, 8, -1, -2})
@@ -79,6 +79,10 @@ std::vector<DslashTile> candidates(int c, bool batched_ok) {
                 if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid, sw});
             }
     }
+    // the matrix-core path: four lanes per site, FP32 compute only
+    if (fp32 && c >= 4)
+        for (int grid : {0, 2048})
+            for (int sw : {0, 1}) v.push_back(DslashTile{c / 4, 4, 5, 256, grid, sw});
     return v;
 }
 
@@ -128,7 +132,7 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     p.guard = Guard{nullptr, 0, 0};
     p.nrhs = std::max(1, std::min(c, probe->nrhs));   // only the columns the probe's buffers hold
     float tbest = -1.f;
-    for (const DslashTile &t : candidates(c, batched_ok)) {
+    for (const DslashTile &t : candidates(c, batched_ok, f.compute == 32)) {
         const float ms = time_tile(p, f, t, st);
         if (ms > 0.f && (tbest < 0.f || ms < tbest)) {
             tbest = ms;
@@ -200,8 +204,10 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
         return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
     bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
     ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);
-    ok = ok && (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8 || stage == -1 || stage == -2)
-                        : stage == 1);
+    const bool mfma = stage == 5 && rg == 4 && nr <= 4 && fmt.compute == 32;   // the matrix-core path
+    ok = ok && (mfma || (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8 || stage == -1 ||
+                                    stage == -2)
+                                 : stage == 1));
     if (!ok)
         return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d",
                          nr, rg, stage, block, grid, sweep);

@@ -29,6 +29,8 @@
 // per-block partial of Re<x,out> or |out|^2 on the stored values (per
 // right-hand side), which fuses the solver's xpay and first reduction.
 #pragma once
+#include <type_traits>
+
 #include "hisq_internal.h"
 
 namespace hisq {
@@ -441,6 +443,57 @@ __device__ __forceinline__ bool colvalid(const DslashArgs &A, int k, int ncol) {
     return A.cmapped ? ((A.cvalid >> k) & 1u) != 0 : k < ncol;
 }
 
+// The epilogue of one output site: out = b*D(in) + a*x + c*y for each live
+// right-hand side of the lane, packed and stored, and the optional reduction.
+template <int SF, class R, int NR, bool RED>
+__device__ __forceinline__ void site_epilogue(const DslashArgs &A, int s, int r0, unsigned live, const R (&acoef)[NR],
+                                              CVec<R> (&acc)[NR], double (&red)[NR]) {
+    const size_t fs = A.field_stride;
+    const size_t vh = (size_t)A.g.vh;
+    const R b = (R)A.b, cc = (R)A.c;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        if (!((live >> j) & 1u)) continue;
+        const size_t off = (size_t)colmap(A, r0 + j) * fs;
+        const R a = acoef[j];
+        CVec<R> xv;
+        cvec_zero(xv);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[j].re[c] *= b;
+            acc[j].im[c] *= b;
+        }
+        if (A.x) {
+            xv = SpinorIO<SF, R>::load(A.x + off, vh, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[j].re[c] = fma(a, xv.re[c], acc[j].re[c]);
+                acc[j].im[c] = fma(a, xv.im[c], acc[j].im[c]);
+            }
+        }
+        if (A.y) {
+            const CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[j].re[c] = fma(cc, yv.re[c], acc[j].re[c]);
+                acc[j].im[c] = fma(cc, yv.im[c], acc[j].im[c]);
+            }
+        }
+        const CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
+        if (RED) {
+            if (A.red == RED_DOT_X) {
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+            }
+        }
+    }
+}
+
 // One output site s for the lane's right-hand sides r0..r0+NR-1 (those in
 // `live`): the 16 hops, the epilogue out = b*D(in) + a*x + c*y, the packed
 // store, and the optional reduction into red[].
@@ -551,48 +604,111 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
         apply_stage(k * SB, k % NBUF);
         if (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
-    const R b = (R)A.b, cc = (R)A.c;
+    site_epilogue<SF, R, NR, RED>(A, s, r0, live, acoef, acc, red);
+}
+
+// Batched sites on the matrix cores (STAGE == MFMA_STAGE, FP32 compute, rg = 4
+// lanes per site).  The four lanes of a site form one block of the 16-block
+// 4x4x1 FP32 MFMA: lane i supplies row i of the operand A (a column of the
+// link's 6x6 real form), lane j supplies column j of B (a component of its own
+// right-hand side's neighbour spinor), and lane j receives column j of the
+// 4x4 product in its four accumulator registers.  Output rows 0-2 are the real
+// parts of colours 0-2 (rows 4-6 the imaginary parts, in the second tile);
+// rows 3 and 7 are padding, lane 3 supplies zeros for them.  The 16 hops
+// accumulate in place, so after the last hop each lane holds the six output
+// reals of each of its NR right-hand sides, as the FMA path would.
+constexpr int MFMA_STAGE = 5;
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <int GF, int SF, int NR, bool RED, int LR>
+__device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, bool valid, int r0, unsigned live,
+                                                 const float (&acoef)[NR], double (&red)[NR]) {
+    const Geom &g = A.g;
+    const size_t fs = A.field_stride;
+    const size_t vh = (size_t)g.vh;
+    const int p = A.parity, q = 1 - p;
+    const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
+    const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
+    const float gf = (float)A.gfat, gl = (float)A.glong, lc = (float)A.lcoef;
+    const int li = (int)(threadIdx.x & 3u);          // row of the site's block this lane supplies
+    const int se = valid ? s : 0;                     // invalid lanes read site 0 and contribute zeros
+    const unsigned lv = valid ? live : 0u;
+    auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
+    f32x4v acc_re[NR], acc_im[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) {
-        if (!((live >> j) & 1u)) continue;
-        const size_t off = (size_t)colmap(A, r0 + j) * fs;
-        const R a = acoef[j];
-        CVec<R> xv;
-        cvec_zero(xv);
+        acc_re[j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+        acc_im[j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+    const Nbrs n = neighbours(g, se, p);
+#pragma unroll
+    for (int h = 0; h < 16; h++) {
+        const int ss = hop_spinor_site(n, h);
+        const int ls = (h & 1) ? ss : se;
+        const int lpar = (h & 1) ? q : p;
+        Mat<float> U;
+        if (LR == 12 && (h & 2)) {
+            const LinkRaw12<GF> L = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
+            U = link_decode12<float>(L, gl, lc * ((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]));
+        } else {
+            const LinkRaw<GF> L = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+            U = link_decode<float>(L, (h & 2) ? gl : gf);
+        }
+        CVec<float> v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            if ((lv >> j) & 1u)
+                v[j] = spin_decode<float>(spin_load<SF>(in_col(j), vh, ss));
+            else
+                cvec_zero(v[j]);
+        }
+        // this lane's entries of the real form: forward hops U (row li), backward
+        // hops -U^dagger (column li of U); lane 3 pads with zeros
+        float ur[3], ui[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            acc[j].re[c] *= b;
-            acc[j].im[c] *= b;
+            // entry (li, c) of U (forward) or (c, li) (backward) for li = 0, 1, 2
+            const int e0 = (h & 1) ? 3 * c : c, e1 = (h & 1) ? 3 * c + 1 : 3 + c, e2 = (h & 1) ? 3 * c + 2 : 6 + c;
+            ur[c] = li == 0 ? U.re[e0] : li == 1 ? U.re[e1] : li == 2 ? U.re[e2] : 0.f;
+            ui[c] = li == 0 ? U.im[e0] : li == 1 ? U.im[e1] : li == 2 ? U.im[e2] : 0.f;
         }
-        if (A.x) {
-            xv = SpinorIO<SF, R>::load(A.x + off, vh, s);
+        // operand A for K index k (k < 3: Re of input colour k, k >= 3: Im of colour k-3)
+        float a_re[6], a_im[6];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc[j].re[c] = fma(a, xv.re[c], acc[j].re[c]);
-                acc[j].im[c] = fma(a, xv.im[c], acc[j].im[c]);
+        for (int c = 0; c < 3; c++) {
+            if (h & 1) {   // -conj(U[c][li]) x: Re row: -ur xr - ui xi, Im row: ui xr - ur xi
+                a_re[c] = -ur[c];
+                a_re[3 + c] = -ui[c];
+                a_im[c] = ui[c];
+                a_im[3 + c] = -ur[c];
+            } else {       // U[li][c] x: Re row: ur xr - ui xi, Im row: ui xr + ur xi
+                a_re[c] = ur[c];
+                a_re[3 + c] = -ui[c];
+                a_im[c] = ui[c];
+                a_im[3 + c] = ur[c];
             }
         }
-        if (A.y) {
-            const CVec<R> yv = SpinorIO<SF, R>::load(A.y + off, vh, s);
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc[j].re[c] = fma(cc, yv.re[c], acc[j].re[c]);
-                acc[j].im[c] = fma(cc, yv.im[c], acc[j].im[c]);
-            }
-        }
-        const CVec<R> o = SpinorIO<SF, R>::store(A.out + off, vh, s, acc[j]);
-        if (RED) {
-            if (A.red == RED_DOT_X) {
+        for (int k = 0; k < 6; k++) {
 #pragma unroll
-                for (int c = 0; c < 3; c++)
-                    red[j] += (double)xv.re[c] * (double)o.re[c] + (double)xv.im[c] * (double)o.im[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-                    red[j] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
+            for (int j = 0; j < NR; j++) {
+                const float bk = k < 3 ? v[j].re[k] : v[j].im[k - 3];
+                acc_re[j] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_re[k], bk, acc_re[j], 0, 0, 0);
+                acc_im[j] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_im[k], bk, acc_im[j], 0, 0, 0);
             }
         }
     }
+    if (!lv) return;
+    CVec<float> acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[j].re[c] = acc_re[j][c];
+            acc[j].im[c] = acc_im[j][c];
+        }
+    }
+    site_epilogue<SF, float, NR, RED>(A, s, r0, lv, acoef, acc, red);
 }
 
 // GUARD: launched inside a solver's block of iterations (may return at once);
@@ -641,7 +757,12 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     const int s = rg == 1 ? tid : fdiv(tid, drg);
     const int grp = tid - s * rg;
     const int r0 = rhs0 + grp * NR;   // == rc
-    if (s < g.vh && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
+    if constexpr (STAGE == MFMA_STAGE) {
+        // every lane takes part in the matrix instructions of its site's block
+        dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, s < g.vh, r0, live, acoef, red);
+    } else {
+        if (s < g.vh && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
+    }
     }
     if (RED) {
         // per right-hand side: sum over the lanes of the same group (lanes l with
@@ -735,6 +856,17 @@ hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipSt
     case 104: return launch_cfg<GF, SF, R, 1, 4>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     case 108: return launch_cfg<GF, SF, R, 1, 8>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
     default: break;
+    }
+    if constexpr (BATCHED && std::is_same<R, float>::value) {
+        if (t.stage == MFMA_STAGE) {
+            if (t.rg != 4) return hipErrorInvalidValue;
+            switch (t.nr) {
+            case 1: return launch_cfg<GF, SF, R, 1, MFMA_STAGE>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+            case 2: return launch_cfg<GF, SF, R, 2, MFMA_STAGE>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+            case 4: return launch_cfg<GF, SF, R, 4, MFMA_STAGE>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+            default: return hipErrorInvalidValue;
+            }
+        }
     }
     if (BATCHED) {
         switch (t.nr * 100 + t.stage) {

@@ -134,6 +134,7 @@ def test_tune_set_validation(hisq):
     hisq.hisq_tune_set("double", dims, 4, 2, 2, 1, 256, 2048, sweep=1)
     hisq.hisq_tune_set("int24", dims, 4, 4, 1, 1, 256, 0)
     hisq.hisq_tune_set("int30", dims, 1, 1, 1, -2, 256, 0)
+    hisq.hisq_tune_set("int20", dims, 16, 4, 4, 5, 256, 0)      # matrix-core path, four lanes per site
     rep = hisq.hisq_tune_report()
     assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
     assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0 sweep 0" in rep
@@ -143,6 +144,8 @@ def test_tune_set_validation(hisq):
            ("half", dims, 2, 2, 1, 2, 256, 0),          # stages only with one right-hand side per lane
            ("half", dims, 2, 2, 1, -1, 256, 0),         # double-buffered stages: one right-hand side only
            ("half", dims, 1, 1, 1, -4, 256, 0),         # double-buffered stages of 1 or 2 hops
+           ("half", dims, 16, 8, 2, 5, 256, 0),         # matrix-core path needs four lanes per site
+           ("double", dims, 16, 4, 4, 5, 256, 0),       # matrix-core path is FP32 only
            ("half", dims, 1, 1, 1, 1, 192, 0),          # block size
            ("half", dims, 1, 1, 1, 1, 256, 12),         # grid not a multiple of 8
            ("int30_fp32", dims, 2, 1, 2, 1, 256, 0),    # no batched form

@@ -124,10 +124,11 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
         for (int j = 0; j < nrhs; j++) c->bru[j] = c->bactive[j];   // report every true residual
     }
     if (reason == STOP_RU || reason == STOP_CONV) {
-        // systems within a factor 2 of their own trigger join this reliable update
+        // systems whose residual norm is within a factor of about 3 (10 in its square) of
+        // their own trigger join this reliable update
         // (one FP64 application serves them all instead of one each shortly after)
         for (int j = 0; j < nrhs; j++)
-            if (c->bactive[j] && c->delta2 > 0.0 && c->brho[j] < 4.0 * c->delta2 * c->brmax2[j]) c->bru[j] = 1;
+            if (c->bactive[j] && c->delta2 > 0.0 && c->brho[j] < 10.0 * c->delta2 * c->brmax2[j]) c->bru[j] = 1;
     }
     if (reason != STOP_NONE) {
         c->reason = reason;

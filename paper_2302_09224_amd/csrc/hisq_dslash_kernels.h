@@ -559,6 +559,16 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     LinkRaw<GF> L[NBUF][SB];
     LinkRaw12<GF> L12[NBUF][SB];
     SpinRaw<SF> P[NBUF][SB][NR];
+    // input column of each of the lane's right-hand sides, computed once per
+    // site; a column the lane does not compute reads its first live column
+    // (valid memory, result discarded by the epilogue), so the hops carry no
+    // per-column branches: the other lanes of the wave compute that column anyway
+    const char *colp[NR];
+    {
+        const char *first = in_col(NR == 1 ? 0 : __builtin_ctz(live));
+#pragma unroll
+        for (int j = 0; j < NR; j++) colp[j] = (NR == 1 || ((live >> j) & 1u)) ? in_col(j) : first;
+    }
     auto load_stage = [&](int h0, int bf) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < SB; i++) {
@@ -572,7 +582,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
                 L[bf][i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
             for (int j = 0; j < NR; j++)
-                P[bf][i][j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
+                P[bf][i][j] = (NR == 1 || ((live >> j) & 1u)) ? spin_load<SF>(colp[j], vh, ss) : SpinRaw<SF>{};
         }
     };
     auto apply_stage = [&](int h0, int bf) __attribute__((always_inline)) {
@@ -631,9 +641,14 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
     const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
     const float gf = (float)A.gfat, gl = (float)A.glong, lc = (float)A.lcoef;
     const int li = (int)(threadIdx.x & 3u);          // row of the site's block this lane supplies
-    const int se = valid ? s : 0;                     // invalid lanes read site 0 and contribute zeros
+    const int se = valid ? s : 0;                     // invalid lanes read site 0, results discarded
     const unsigned lv = valid ? live : 0u;
-    auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
+    // input column of each right-hand side; columns the lane does not compute
+    // (and every column of an invalid lane) read valid memory whose products
+    // only reach this lane's own, unstored, outputs
+    const char *colp[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) colp[j] = ((lv >> j) & 1u) ? A.in + (size_t)colmap(A, r0 + j) * fs : A.in;
     f32x4v acc_re[NR], acc_im[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) {
@@ -656,12 +671,7 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
         }
         CVec<float> v[NR];
 #pragma unroll
-        for (int j = 0; j < NR; j++) {
-            if ((lv >> j) & 1u)
-                v[j] = spin_decode<float>(spin_load<SF>(in_col(j), vh, ss));
-            else
-                cvec_zero(v[j]);
-        }
+        for (int j = 0; j < NR; j++) v[j] = spin_decode<float>(spin_load<SF>(colp[j], vh, ss));
         // this lane's entries of the real form: forward hops U (row li), backward
         // hops -U^dagger (column li of U); lane 3 pads with zeros
         float ur[3], ui[3];

@@ -174,8 +174,10 @@ template <class R> struct SpinorIO<SF_F32, R> {
 // QUDA half: q = rint(v * (32767/M)) with M the FP32 site max; v = q * (M * (1/32767)).
 // A site whose M is zero or whose 32767/M overflows stores zeros with M = 0.
 template <class R> struct SpinorIO<SF_HALF16, R> {
-    static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
-        float d = __uint_as_float(w.w) * (1.0f / 32767.0f);
+    // f: an extra factor folded into the site scale (the Dslash folds link
+    // scales there, one multiply per site instead of one per link element)
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f = 1.0f) {
+        float d = __uint_as_float(w.w) * (1.0f / 32767.0f) * f;
         CVec<R> v;
         v.re[0] = (float)sext16(w.x) * d; v.im[0] = (float)sext16(w.x >> 16) * d;
         v.re[1] = (float)sext16(w.y) * d; v.im[1] = (float)sext16(w.y >> 16) * d;
@@ -216,13 +218,14 @@ template <class R> struct SpinorIO<SF_HALF16, R> {
 // 20-bit shared exponent (Appendix A): E = biased exponent of fl(M/(2^19-1)) + 1,
 // q = rint(v * 2^(127-E)), v = q * 2^(E-127).
 template <class R> struct SpinorIO<SF_INT20, R> {
-    static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f = 1.0f) {
         // A field inside one word is a signed bit-field extract.  A field split
         // over two words has its high bits at the top of the earlier word, so
         // inserting the next word's low bits just below them gives the field
         // times 2^12 as a signed 32-bit integer (exact in FP32); its scale is
-        // sc * 2^-12 (exact, a subnormal power of two for E < 13).
-        const float sc = pow2_f32(w.w >> 24);
+        // sc * 2^-12 (exact for f = 1, a subnormal power of two for E < 13).
+        // f: an extra factor folded into the site scale.
+        const float sc = pow2_f32(w.w >> 24) * f;
         const float sl = sc * 0x1p-12f;
         CVec<R> v;
         v.re[0] = (float)((int)(w.x << 12) >> 12) * sc;
@@ -265,8 +268,8 @@ template <class R> struct SpinorIO<SF_INT20, R> {
 
 // 30-bit shared exponent: the 20-bit rule with scale 2^29-1 in FP64.
 template <class R> struct SpinorIO<SF_INT30, R> {
-    static __device__ __forceinline__ CVec<R> decode(u32x4 a, u32x2 b) {
-        R sc = (R)pow2_f64((b.y >> 20) & 0xffu);
+    static __device__ __forceinline__ CVec<R> decode(u32x4 a, u32x2 b, R f = R(1)) {
+        const R sc = (R)pow2_f64((b.y >> 20) & 0xffu) * f;   // f: folded into the site scale
         CVec<R> v;
         v.re[0] = (R)sext30(a.x) * sc;
         v.im[0] = (R)sext30(((a.x >> 30) << 28) | (a.y & 0x0fffffffu)) * sc;
@@ -392,18 +395,19 @@ template <int B, class R> struct SxCodec {
         for (int k = 0; k < 6; k++) F::put(w, k, q[k]);
         F::put(w, 6, e);
     }
-    static __device__ __forceinline__ CVec<R> decode(const unsigned (&w)[F::W]) {
+    // f: an extra factor folded into the site scale
+    static __device__ __forceinline__ CVec<R> decode(const unsigned (&w)[F::W], R f = R(1)) {
         const unsigned e = F::get(w, 6);
         CVec<R> v;
         if (B <= 24) {
-            const float sc = pow2_f32(e);
+            const float sc = pow2_f32(e) * (float)f;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 v.re[c] = (R)((float)F::sext(F::get(w, 2 * c)) * sc);
                 v.im[c] = (R)((float)F::sext(F::get(w, 2 * c + 1)) * sc);
             }
         } else {
-            const double sc = pow2_f64(e);
+            const double sc = pow2_f64(e) * (double)f;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 v.re[c] = (R)((double)F::sext(F::get(w, 2 * c)) * sc);

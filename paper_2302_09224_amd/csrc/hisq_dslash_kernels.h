@@ -200,8 +200,9 @@ template <> __device__ __forceinline__ LinkRaw12<GF_SX24> link_load12<GF_SX24>(c
     return L;
 }
 
-// rows 1-2 -> full matrix; third row conj(r0 x r1); everything times c
-template <class R> __device__ __forceinline__ Mat<R> complete_su3(Mat<R> U, R c) {
+// rows 1-2 -> full matrix; third row conj(r0 x r1); rows 1-2 times c, row 3
+// times c3
+template <class R> __device__ __forceinline__ Mat<R> complete_su3(Mat<R> U, R c, R c3) {
     const R ar[3] = {U.re[0], U.re[1], U.re[2]}, ai[3] = {U.im[0], U.im[1], U.im[2]};
     const R br[3] = {U.re[3], U.re[4], U.re[5]}, bi[3] = {U.im[3], U.im[4], U.im[5]};
 #pragma unroll
@@ -210,35 +211,36 @@ template <class R> __device__ __forceinline__ Mat<R> complete_su3(Mat<R> U, R c)
         // (a_i b_j - a_j b_i), conjugated
         const R re = ar[i] * br[j] - ai[i] * bi[j] - (ar[j] * br[i] - ai[j] * bi[i]);
         const R im = ar[i] * bi[j] + ai[i] * br[j] - (ar[j] * bi[i] + ai[j] * br[i]);
-        U.re[6 + k] = re;
-        U.im[6 + k] = -im;
+        U.re[6 + k] = re * c3;
+        U.im[6 + k] = -im * c3;
     }
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = 0; k < 6; k++) {
         U.re[k] *= c;
         U.im[k] *= c;
     }
     return U;
 }
 
-template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_F64> &L, R, R c) {
+// rows 1-2 of a two-row link (fixed point scaled by g)
+template <class R> __device__ __forceinline__ Mat<R> link_rows12(const LinkRaw12<GF_F64> &L, R) {
     Mat<R> U;
 #pragma unroll
     for (int k = 0; k < 6; k++) {
         U.re[k] = (R)L.w[k].x;
         U.im[k] = (R)L.w[k].y;
     }
-    return complete_su3(U, c);
+    return U;
 }
-template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_F32> &L, R, R c) {
+template <class R> __device__ __forceinline__ Mat<R> link_rows12(const LinkRaw12<GF_F32> &L, R) {
     Mat<R> U;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         U.re[2 * k] = L.w[k].x; U.im[2 * k] = L.w[k].y; U.re[2 * k + 1] = L.w[k].z; U.im[2 * k + 1] = L.w[k].w;
     }
-    return complete_su3(U, c);
+    return U;
 }
-template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_FIX16> &L, R g, R c) {
+template <class R> __device__ __forceinline__ Mat<R> link_rows12(const LinkRaw12<GF_FIX16> &L, R g) {
     Mat<R> U;
     const unsigned ws[6] = {L.w.x, L.w.y, L.w.z, L.w.w, L.t.x, L.t.y};
 #pragma unroll
@@ -246,22 +248,26 @@ template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw
         U.re[k] = (R)sext16(ws[k]) * g;
         U.im[k] = (R)sext16(ws[k] >> 16) * g;
     }
-    return complete_su3(U, c);
+    return U;
 }
-template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_FIX32> &L, R g, R c) {
+template <class R> __device__ __forceinline__ Mat<R> link_rows12(const LinkRaw12<GF_FIX32> &L, R g) {
     Mat<R> U;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         U.re[2 * k] = (R)(int)L.w[k].x * g; U.im[2 * k] = (R)(int)L.w[k].y * g;
         U.re[2 * k + 1] = (R)(int)L.w[k].z * g; U.im[2 * k + 1] = (R)(int)L.w[k].w * g;
     }
-    return complete_su3(U, c);
+    return U;
 }
-template <class R> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF_SX24> &L, R, R c) {
+template <class R> __device__ __forceinline__ Mat<R> link_rows12(const LinkRaw12<GF_SX24> &L, R) {
     Mat<R> U;
 #pragma unroll
     for (int r = 0; r < 2; r++) sx24_row(U, r, L.w[r], L.t[r]);
-    return complete_su3(U, c);
+    return U;
+}
+// the full long link c * U
+template <class R, int GF> __device__ __forceinline__ Mat<R> link_decode12(const LinkRaw12<GF> &L, R g, R c) {
+    return complete_su3(link_rows12<R>(L, g), c, c);
 }
 
 template <int SF> struct SpinRaw;
@@ -334,6 +340,60 @@ template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<
 template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT24> &P) {
     const unsigned w[SxFmt<24>::W] = {P.a.x, P.a.y, P.a.z, P.a.w, P.b};
     return SxCodec<24, R>::decode(w);
+}
+
+// Link scales folded into the spinor's site scale.  A hop adds link * v.  When
+// the spinor format carries a per-site scale, the link is decoded as M with
+// link = f * M (fixed-point links: the stored integers; two-row long links: the
+// SU(3) matrix without the long-link constant and the phase) and v with its
+// site scale times f, so the scales cost one multiply per right-hand side
+// instead of one per link element.  Other spinor formats use f = 1.
+template <int SF> constexpr bool spinor_scaled() {
+    return SF == SF_HALF16 || SF == SF_INT20 || SF == SF_INT30 || SF == SF_INT24;
+}
+template <int GF> constexpr bool gauge_fixed() { return GF == GF_FIX16 || GF == GF_FIX32; }
+
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_F64> &P, R) { return spin_decode<R>(P); }
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_F32> &P, R) { return spin_decode<R>(P); }
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_HALF16> &P, R f) {
+    return SpinorIO<SF_HALF16, R>::decode(P.w, (float)f);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT20> &P, R f) {
+    return SpinorIO<SF_INT20, R>::decode(P.w, (float)f);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT30> &P, R f) {
+    return SpinorIO<SF_INT30, R>::decode(P.a, P.b, f);
+}
+template <class R> __device__ __forceinline__ CVec<R> spin_decode(const SpinRaw<SF_INT24> &P, R f) {
+    const unsigned w[SxFmt<24>::W] = {P.a.x, P.a.y, P.a.z, P.a.w, P.b};
+    return SxCodec<24, R>::decode(w, f);
+}
+
+// a fat or 18-real long link with scale g: M and f
+template <int SF, class R, int GF> __device__ __forceinline__ Mat<R> hop_link(const LinkRaw<GF> &L, R g, R &f) {
+    if constexpr (spinor_scaled<SF>() && gauge_fixed<GF>()) {
+        f = g;
+        return link_decode<R>(L, R(1));
+    } else {
+        f = R(1);
+        return link_decode<R>(L, g);
+    }
+}
+// a two-row long link c * U (rows scaled by g when fixed point): M and f.  For
+// fixed point the rows are Q1 = U1/g, Q2 = U2/g and g conj(Q1 x Q2) = U3/g, so
+// c U = (c g) M.
+template <int SF, class R, int GF>
+__device__ __forceinline__ Mat<R> hop_link12(const LinkRaw12<GF> &L, R g, R c, R &f) {
+    if constexpr (spinor_scaled<SF>() && gauge_fixed<GF>()) {
+        f = c * g;
+        return complete_su3(link_rows12<R>(L, R(1)), R(1), g);
+    } else if constexpr (spinor_scaled<SF>()) {
+        f = c;
+        return complete_su3(link_rows12<R>(L, g), R(1), R(1));
+    } else {
+        f = R(1);
+        return link_decode12<R>(L, g, c);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -521,6 +581,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
             const int ls = (h & 1) ? ss : s;
             const int lpar = (h & 1) ? q : p;
             Mat<R> U;
+            R f;
             SpinRaw<SF> Pr[NR];
             if (LR == 12 && (h & 2)) {
                 const int mu = h >> 2;
@@ -528,22 +589,22 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
                 const LinkRaw12<GF> Lr = link_load12<GF>(A.lng + (size_t)(2 * mu + lpar) * lsub, vh, ls);
 #pragma unroll
                 for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
-                U = link_decode12<R>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T));
+                U = hop_link12<SF>(Lr, gl, lc * (R)long_phase(mu, c.x, c.y, c.z, tl, g.T), f);
             } else {
                 const char *field = (h & 2) ? A.lng : A.fat;
                 const LinkRaw<GF> Lr = link_load<GF>(field + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
                 for (int j = 0; j < NR; j++) Pr[j] = ((live >> j) & 1u) ? spin_load<SF>(in_col(j), vh, ss) : SpinRaw<SF>{};
-                U = link_decode<R>(Lr, (h & 2) ? gl : gf);
+                U = hop_link<SF>(Lr, (h & 2) ? gl : gf, f);
             }
             if (h & 1) {
 #pragma unroll
                 for (int j = 0; j < NR; j++)
-                    if ((live >> j) & 1u) mdv_sub(acc[j], U, spin_decode<R>(Pr[j]));
+                    if ((live >> j) & 1u) mdv_sub(acc[j], U, spin_decode<R>(Pr[j], f));
             } else {
 #pragma unroll
                 for (int j = 0; j < NR; j++)
-                    if ((live >> j) & 1u) mv_add(acc[j], U, spin_decode<R>(Pr[j]));
+                    if ((live >> j) & 1u) mv_add(acc[j], U, spin_decode<R>(Pr[j], f));
             }
         }
     }
@@ -589,13 +650,14 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
 #pragma unroll
         for (int i = 0; i < SB; i++) {
             const int h = h0 + i;
+            R f;
             const Mat<R> U = (LR == 12 && (h & 2))
-                                 ? link_decode12<R>(L12[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]))
-                                 : link_decode<R>(L[bf][i], (h & 2) ? gl : gf);
+                                 ? hop_link12<SF>(L12[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f)
+                                 : hop_link<SF>(L[bf][i], (h & 2) ? gl : gf, f);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 if (NR > 1 && !((live >> j) & 1u)) continue;
-                const CVec<R> v = spin_decode<R>(P[bf][i][j]);
+                const CVec<R> v = spin_decode<R>(P[bf][i][j], f);
                 if (h & 1)
                     mdv_sub(acc[j], U, v);
                 else
@@ -662,16 +724,17 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
         const int ls = (h & 1) ? ss : se;
         const int lpar = (h & 1) ? q : p;
         Mat<float> U;
+        float f;
         if (LR == 12 && (h & 2)) {
             const LinkRaw12<GF> L = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
-            U = link_decode12<float>(L, gl, lc * ((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]));
+            U = hop_link12<SF>(L, gl, lc * ((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f);
         } else {
             const LinkRaw<GF> L = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
-            U = link_decode<float>(L, (h & 2) ? gl : gf);
+            U = hop_link<SF>(L, (h & 2) ? gl : gf, f);
         }
         CVec<float> v[NR];
 #pragma unroll
-        for (int j = 0; j < NR; j++) v[j] = spin_decode<float>(spin_load<SF>(colp[j], vh, ss));
+        for (int j = 0; j < NR; j++) v[j] = spin_decode<float>(spin_load<SF>(colp[j], vh, ss), f);
         // this lane's entries of the real form: forward hops U (row li), backward
         // hops -U^dagger (column li of U); lane 3 pads with zeros
         float ur[3], ui[3];

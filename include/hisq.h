@@ -239,7 +239,7 @@ typedef struct {
                                                 refinement and of the shifted systems' refinement */
 } hisq_solver_stats;
 
-/* Default parameters: delta 0.1, maxiter 100000, grad_buffer 4, PR beta,
+/* Default parameters: delta 0.1, maxiter 100000, grad_buffer 8, PR beta,
  * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 1, ru_estimate 0. */
 void hisq_solver_params_default(hisq_solver_params *p);
 

@@ -7,6 +7,11 @@
 // the reductions are bitwise reproducible).  Reductions accumulate in FP64
 // and are taken on the values as stored (after packing), which is what the
 // next iteration will read.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "hisq_internal.h"
 
 namespace hisq {
@@ -403,18 +408,37 @@ __global__ void k_cg_pupdate(char *pd, const char *r, const char *ps, const Solv
     }
 }
 
+// Buffered-vector loops load a group of vectors before using the first, so that
+// a lane keeps that many loads in flight instead of one.  A short last group
+// repeats its last vector (the same addresses, a cache hit) with coefficient 0,
+// so that every load is used unconditionally and none is deferred to its use;
+// the sums keep their order (fma(0, v, x) = x), so results do not depend on
+// the grouping.
+// Four vectors per group; two for FP64 vectors (twice the registers each).
+template <int SF> constexpr int load_group() { return SF == SF_F64 ? 2 : 4; }
+
 template <int SF, class R>
 __global__ void k_flush_x(char *x64, SpinorList p, int count, const double *alpha_buf, size_t n, Guard gd) {
     if (!gd.pass()) return;
+    constexpr int LOAD_GROUP = load_group<SF>();
     for (size_t s = gtid(); s < n; s += gstride()) {
         CVec<double> x = SpinorIO<SF_F64, double>::load(x64, n, s);
-        for (int i = 0; i < count; i++) {
-            const double a = alpha_buf[i];
-            CVec<R> pv = SpinorIO<SF, R>::load(p.p[i], n, s);
+        for (int i0 = 0; i0 < count; i0 += LOAD_GROUP) {
+            CVec<R> pv[LOAD_GROUP];
+            double a[LOAD_GROUP];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                x.re[c] = fma(a, (double)pv.re[c], x.re[c]);
-                x.im[c] = fma(a, (double)pv.im[c], x.im[c]);
+            for (int k = 0; k < LOAD_GROUP; k++) {
+                const int i = min(i0 + k, count - 1);
+                pv[k] = SpinorIO<SF, R>::load(p.p[i], n, s);
+                a[k] = i0 + k < count ? alpha_buf[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < LOAD_GROUP; k++) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    x.re[c] = fma(a[k], (double)pv[k].re[c], x.re[c]);
+                    x.im[c] = fma(a[k], (double)pv[k].im[c], x.im[c]);
+                }
             }
         }
         SpinorIO<SF_F64, double>::store(x64, n, s, x);
@@ -472,14 +496,33 @@ __global__ void k_ru_convert(char *rs, const char *r64, const char *p, const cha
 template <int SF, class R>
 __device__ __forceinline__ void flush_shift(char *x64, const char *ring, size_t slot_bytes, const SolverCtrl *ctrl,
                                             int i, int last, const CVec<R> *cur, size_t n, size_t s) {
+    constexpr int LOAD_GROUP = load_group<SF>();
     CVec<double> xv = SpinorIO<SF_F64, double>::load(x64, n, s);
-    for (int q = 0; q <= last; q++) {
-        const double a = ctrl->ai_buf[q][i];
-        const CVec<R> pq = (cur && q == last) ? *cur : SpinorIO<SF, R>::load(ring + q * slot_bytes, n, s);
+    // slot `last` may already be in registers (*cur); slots are loaded up to lim
+    const int lim = cur ? (last > 0 ? last - 1 : 0) : last;
+    for (int q0 = 0; q0 <= last; q0 += LOAD_GROUP) {
+        CVec<R> pq[LOAD_GROUP];
+        double a[LOAD_GROUP];
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            xv.re[c] = fma(a, (double)pq.re[c], xv.re[c]);
-            xv.im[c] = fma(a, (double)pq.im[c], xv.im[c]);
+        for (int k = 0; k < LOAD_GROUP; k++) {
+            const int q = q0 + k;
+            const CVec<R> v = SpinorIO<SF, R>::load(ring + (size_t)min(q, lim) * slot_bytes, n, s);
+            const bool use_cur = cur && q == last;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                pq[k].re[c] = use_cur ? cur->re[c] : v.re[c];
+                pq[k].im[c] = use_cur ? cur->im[c] : v.im[c];
+            }
+            const double aq = ctrl->ai_buf[min(q, last)][i];
+            a[k] = q <= last ? aq : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < LOAD_GROUP; k++) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                xv.re[c] = fma(a[k], (double)pq[k].re[c], xv.re[c]);
+                xv.im[c] = fma(a[k], (double)pq[k].im[c], xv.im[c]);
+            }
         }
     }
     SpinorIO<SF_F64, double>::store(x64, n, s, xv);
@@ -493,24 +536,41 @@ template <int SF, class R>
 __global__ void k_shift_update(SpinorList x64, SpinorList p, const char *r, const SolverCtrl *ctrl, int nshift, size_t n,
                                size_t slot_bytes, int jb, int jn, int flush_all, Guard gd) {
     if (!gd.pass()) return;
-    const int mask = ctrl->e_mask, rm = ctrl->rm_mask;
+    const unsigned sel = (unsigned)ctrl->e_mask & ~1u & (nshift >= 32 ? ~0u : (1u << nshift) - 1u);
+    const int rm = ctrl->rm_mask;
+    constexpr int LOAD_GROUP = load_group<SF>();
     for (size_t s = gtid(); s < n; s += gstride()) {
         CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
-        for (int i = 1; i < nshift; i++) {
-            if (!((mask >> i) & 1)) continue;
-            const char *ring = p.p[i];
-            const CVec<R> pv = SpinorIO<SF, R>::load(ring + jb * slot_bytes, n, s);
-            const int stopped = (rm >> i) & 1;
-            if (flush_all || stopped) flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, &pv, n, s);
-            if (!stopped) {
-                const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
-                CVec<R> pn;
+        // the shifts being updated, a group at a time: their current gradient
+        // vectors are loaded together, then each is updated
+        for (unsigned m = sel; m;) {
+            int ids[LOAD_GROUP];
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    pn.re[c] = fma(zi, rv.re[c], bi * pv.re[c]);
-                    pn.im[c] = fma(zi, rv.im[c], bi * pv.im[c]);
+            for (int k = 0; k < LOAD_GROUP; k++) {
+                ids[k] = m ? __builtin_ctz(m) : -1;
+                m &= m - 1u;
+            }
+            CVec<R> pv[LOAD_GROUP];
+#pragma unroll
+            for (int k = 0; k < LOAD_GROUP; k++)
+                pv[k] = SpinorIO<SF, R>::load(p.p[ids[k] >= 0 ? ids[k] : ids[0]] + jb * slot_bytes, n, s);
+#pragma unroll
+            for (int k = 0; k < LOAD_GROUP; k++) {
+                const int i = ids[k];
+                if (i < 0) break;
+                const char *ring = p.p[i];
+                const int stopped = (rm >> i) & 1;
+                if (flush_all || stopped) flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, &pv[k], n, s);
+                if (!stopped) {
+                    const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
+                    CVec<R> pn;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        pn.re[c] = fma(zi, rv.re[c], bi * pv[k].re[c]);
+                        pn.im[c] = fma(zi, rv.im[c], bi * pv[k].im[c]);
+                    }
+                    SpinorIO<SF, R>::store(p.p[i] + jn * slot_bytes, n, s, pn);
                 }
-                SpinorIO<SF, R>::store(p.p[i] + jn * slot_bytes, n, s, pn);
             }
         }
     }
@@ -805,7 +865,8 @@ hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, cons
 hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const double *alpha_buf, size_t n, int sf,
                           int compute, Guard gd, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_flush_x<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, count, alpha_buf, n, gd));
+    const int nb = flush_x_grid(n, sf, compute);
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_flush_x<SFc, Rc>), dim3(nb), dim3(BLAS_BLOCK), 0, st, x64, p, count, alpha_buf, n, gd));
     return hipGetLastError();
 }
 
@@ -815,10 +876,54 @@ hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const ch
     return hipGetLastError();
 }
 
+namespace {
+// blas_blocks(n) capped at the blocks of kernel `fn` the device holds at once
+// (queried once per device and kernel)
+int resident_grid(const void *fn, size_t n) {
+    const int nb = blas_blocks(n);
+    int dev = 0;
+    if (!fn || hipGetDevice(&dev) != hipSuccess) return nb;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> resident;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = resident.find(std::make_pair(dev, fn));
+    if (it == resident.end()) {
+        int per_cu = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLAS_BLOCK, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+            ncu < 1) {
+            (void)hipGetLastError();
+            return nb;
+        }
+        it = resident.emplace(std::make_pair(dev, fn), per_cu * ncu).first;
+    }
+    return std::min(nb, it->second);
+}
+hipError_t shift_update_kernel(int sf, int compute, const void **fn) {
+    HISQ_DISPATCH_SC(sf, compute, *fn = reinterpret_cast<const void *>(&k_shift_update<SFc, Rc>));
+    return hipSuccess;
+}
+hipError_t flush_x_kernel(int sf, int compute, const void **fn) {
+    HISQ_DISPATCH_SC(sf, compute, *fn = reinterpret_cast<const void *>(&k_flush_x<SFc, Rc>));
+    return hipSuccess;
+}
+}  // namespace
+
+int shift_update_grid(size_t n, int sf, int compute) {
+    const void *fn = nullptr;
+    return resident_grid(shift_update_kernel(sf, compute, &fn) == hipSuccess ? fn : nullptr, n);
+}
+
+int flush_x_grid(size_t n, int sf, int compute) {
+    const void *fn = nullptr;
+    return resident_grid(flush_x_kernel(sf, compute, &fn) == hipSuccess ? fn : nullptr, n);
+}
+
 hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
                                int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
                                int compute, Guard gd, hipStream_t st) {
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, slot_bytes, jb, jn, flush_all, gd));
+    const int nb = shift_update_grid(n, sf, compute);
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(nb), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, slot_bytes, jb, jn, flush_all, gd));
     return hipGetLastError();
 }
 

@@ -233,6 +233,13 @@ hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const ch
 hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
                                int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
                                int compute, Guard gd, hipStream_t st);
+// grids of launch_shift_update and launch_flush_x: blas_blocks(n) capped at
+// the blocks of that kernel the device holds at once (a larger grid leaves
+// blocks that start only after the first ones finish, on a device that is then
+// mostly idle).  The occupancy is queried once per device and triplet; the
+// solvers call these before they capture a graph.
+int shift_update_grid(size_t n, int sf, int compute);
+int flush_x_grid(size_t n, int sf, int compute);
 // multi-shift, shifts of ctrl->active_mask: flush slots 0..jb into x_i and move slot jb+1 to slot 0
 hipError_t launch_shift_realign(const SpinorList &x64, const SpinorList &p, const SolverCtrl *ctrl, int nshift,
                                 size_t n, size_t slot_bytes, int jb, int sf, int compute, hipStream_t st);

@@ -357,6 +357,9 @@ struct Run {
         DslashArgs p64 = dargs(g64, B->t64, B->x64, 1);
         plan_64 = dslash_plan(f64, g, 1, &p64, st);
         nb_64 = dslash_tile_blocks(g.vh, plan_64.tile[0]);
+        // occupancy queries of the capped-grid kernels, before any capture
+        (void)flush_x_grid(vh, fmt.spinor, fmt.compute);
+        if (multishift) (void)shift_update_grid(vh, fmt.spinor, fmt.compute);
     }
 
     DslashArgs dargs(const hisq_gauge *gg, char *out, const char *in, int parity) const {

@@ -397,8 +397,8 @@ def main():
         return 8 * hisq.GAUGE_BYTES[gf] + 8 * (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12 else hisq.GAUGE_BYTES[gf])
 
     stream = torch.cuda.current_stream()
-    table = [(n, 18) for n in ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24")]
-    table += [(n, 12) for n in ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24")]
+    names = ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30")
+    table = [(n, 18) for n in names] + [(n, 12) for n in names]
     for name, recon in table:
         key = name if recon == 18 else f"{name}_r12"
         f = hisq.fmt(name)

@@ -79,7 +79,7 @@ enum {
 /* Precision triplet gauge / fermion / compute of one stencil application
  * (Sec. 4).  compute is 32 (FP32) or 64 (FP64).  Supported triplets:
  *   F64/F64/64, F32/F32/32, FIX16/HALF16/32, FIX16/INT20/32,
- *   FIX32/INT30/64, FIX32/INT30/32, FIX32/INT24/32, SX24/INT24/32. */
+ *   FIX32/INT30/64, FIX32/INT30/32, FIX32/INT24/32, SX24/INT24/32, SX24/INT30/64. */
 typedef struct {
     int gauge;
     int spinor;

@@ -70,7 +70,8 @@ bool triplet_ok(const hisq_fmt &f) {
     case GF_FIX32 * 100 + SF_INT30 * 10 + 1:
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0:
     case GF_FIX32 * 100 + SF_INT24 * 10 + 0:
-    case GF_SX24 * 100 + SF_INT24 * 10 + 0: return true;
+    case GF_SX24 * 100 + SF_INT24 * 10 + 0:
+    case GF_SX24 * 100 + SF_INT30 * 10 + 1: return true;
     default: return false;
     }
 }

@@ -28,6 +28,7 @@ HISQ_DECL_TRIPLET(int30)
 HISQ_DECL_TRIPLET(int30_fp32)
 HISQ_DECL_TRIPLET(int24)
 HISQ_DECL_TRIPLET(sx24)
+HISQ_DECL_TRIPLET(sx24_int30)
 
 namespace {
 
@@ -43,6 +44,7 @@ hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const Ds
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_launch_int30_fp32(a, rhs0, t, st, nb);
     case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return dslash_launch_int24(a, rhs0, t, st, nb);
     case GF_SX24 * 100 + SF_INT24 * 10 + 0: return dslash_launch_sx24(a, rhs0, t, st, nb);
+    case GF_SX24 * 100 + SF_INT30 * 10 + 1: return dslash_launch_sx24_int30(a, rhs0, t, st, nb);
     default: return hipErrorInvalidValue;
     }
 }
@@ -174,6 +176,7 @@ hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_r
     case GF_FIX32 * 100 + SF_INT30 * 10 + 0: return dslash_multi_int30_fp32(m, long_recon, st);
     case GF_FIX32 * 100 + SF_INT24 * 10 + 0: return dslash_multi_int24(m, long_recon, st);
     case GF_SX24 * 100 + SF_INT24 * 10 + 0: return dslash_multi_sx24(m, long_recon, st);
+    case GF_SX24 * 100 + SF_INT30 * 10 + 1: return dslash_multi_sx24_int30(m, long_recon, st);
     default: return hipErrorInvalidValue;
     }
 }

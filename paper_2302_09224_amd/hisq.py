@@ -96,6 +96,7 @@ TRIPLETS = {
     "int30_fp32": (GAUGE_FIX32, SPINOR_INT30, 32),
     "int24": (GAUGE_FIX32, SPINOR_INT24, 32),      # generated shared-exponent member
     "sx24": (GAUGE_SX24, SPINOR_INT24, 32),        # links and spinors both 24-bit shared-exponent records
+    "sx24_int30": (GAUGE_SX24, SPINOR_INT30, 64),  # 24-bit shared-exponent links, 30-bit spinors, FP64
 }
 
 

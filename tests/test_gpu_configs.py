@@ -87,7 +87,7 @@ def test_config_16():
 # triplet: FP64 rounding; FP32 rounding; the fixed-point links (2^-31 or 2^-15
 # of the field maximum) and the spinor quantum of each format
 DSLASH_TOL = {"double": 1e-13, "single": 1e-6, "int30": 1e-8, "int30_fp32": 2e-6, "int24": 2e-6, "sx24": 2e-6,
-              "int20": 3e-4, "half": 3e-4}
+              "sx24_int30": 2e-6, "int20": 3e-4, "half": 3e-4}
 
 
 def test_config_32_formats():
@@ -104,7 +104,7 @@ def test_config_32_formats():
     bd, bfull = torch.from_numpy(b).cuda(), full_even(dims, ev, b)
     g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
     err, iters = {}, {}
-    for name in ("double", "single", "int30", "int30_fp32", "int24", "sx24", "int20", "half"):
+    for name in ("double", "single", "int30", "int30_fp32", "int24", "sx24", "sx24_int30", "int20", "half"):
         f = hisq.fmt(name)
         pg = g64 if f.gauge == hisq.GAUGE_F64 else hisq.pack_gauge(fat, lng, dims, f.gauge)
         pin = hisq.pack_spinor(torch.from_numpy(psi[od]).cuda(), f.spinor)

@@ -22,7 +22,7 @@ from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"]
+TRIPLETS = ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30"]
 SF_NAME = {0: "f64", 1: "f32", 2: "half16", 3: "int20", 4: "int30", 5: "int24"}
 GF_NAME = {0: "f64", 1: "f32", 2: "fix16", 3: "fix32", 4: "sx24"}
 # 4^4: x+3mu and x-mu coincide; (6,8,10,12): Vh = 2880, a ragged last block;

@@ -56,7 +56,8 @@ def test_cg_config0_dense():
     assert oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass) <= 1e-10
 
 
-@pytest.mark.parametrize("sloppy", ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"])
+@pytest.mark.parametrize("sloppy", ["double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24",
+                                    "sx24_int30"])
 @pytest.mark.parametrize("dims,kind,mass", [((8, 8, 8, 8), "near_unit", 0.05), ((6, 8, 10, 12), "haar", 0.2)])
 def test_cg_mixed(sloppy, dims, kind, mass):
     hisq = need_gpu()

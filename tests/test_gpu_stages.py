@@ -23,7 +23,7 @@ def test_stage_schedules_bit_identical(recon):
     vh = oracle.volume(DIMS) // 2
     psi = inputs.gaussian_spinor(vh, 81, device="cuda")
     try:
-        for name in ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24"):
+        for name in ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30"):
             f = hisq.fmt(name)
             pg = hisq.pack_gauge(fat, lng, DIMS, f.gauge, long_recon=recon)
             pin = hisq.pack_spinor(psi, f.spinor)

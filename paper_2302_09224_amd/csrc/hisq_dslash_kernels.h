@@ -622,8 +622,9 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     SpinRaw<SF> P[NBUF][SB][NR];
     // input column of each of the lane's right-hand sides, computed once per
     // site; a column the lane does not compute reads its first live column
-    // (valid memory, result discarded by the epilogue), so the hops carry no
-    // per-column branches: the other lanes of the wave compute that column anyway
+    // (valid memory, a cache hit, never used), so the loads carry no branches
+    // and no zero fill; the arithmetic of a column is skipped when no lane of
+    // the wave computes it
     const char *colp[NR];
     {
         const char *first = in_col(NR == 1 ? 0 : __builtin_ctz(live));
@@ -642,8 +643,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
             else
                 L[bf][i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
 #pragma unroll
-            for (int j = 0; j < NR; j++)
-                P[bf][i][j] = (NR == 1 || ((live >> j) & 1u)) ? spin_load<SF>(colp[j], vh, ss) : SpinRaw<SF>{};
+            for (int j = 0; j < NR; j++) P[bf][i][j] = spin_load<SF>(colp[j], vh, ss);
         }
     };
     auto apply_stage = [&](int h0, int bf) __attribute__((always_inline)) {

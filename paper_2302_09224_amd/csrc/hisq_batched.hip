@@ -245,11 +245,13 @@ struct BRun {
     // to a power of two and the column map that deals the columns round-robin
     // over the lane groups (column i of the set -> group i % rg, slot i / rg),
     // so that the lanes of a site share the work of the longest-running systems.
+    // Launches with a fused reduction have their own tile, hence their own map;
+    // they write the partials that nl describes.
     struct Mapped {
         DslashPlan plan{};
         unsigned mask = 0;            // field columns in the launch
-        unsigned cvalid = 0;
-        unsigned long long cmap = 0;
+        unsigned cvalid = 0, cvalid_red = 0;
+        unsigned long long cmap = 0, cmap_red = 0;
         NbList nl{};
     };
     Mapped ms_{}, m64_{};
@@ -268,22 +270,27 @@ struct BRun {
         probe.cmap = 0;
         for (int k = 0; k < n; k++) probe.cmap |= (unsigned long long)cols[k] << (4 * k);
         m.plan = dslash_plan(f, g, n, &probe, st);
-        const DslashTile &t = m.plan.tile[0];
+        const DslashTile &t = m.plan.tile[0], &tr = m.plan.tile_red[0];
         for (int i = 0; i < n; i++) {
             const int k = (i % t.rg) * t.nr + i / t.rg;
             m.cmap |= (unsigned long long)cols[i] << (4 * k);
             m.cvalid |= 1u << k;
+            const int kr = (i % tr.rg) * tr.nr + i / tr.rg;
+            m.cmap_red |= (unsigned long long)cols[i] << (4 * kr);
+            m.cvalid_red |= 1u << kr;
         }
         m.nl.pstride = dslash_max_blocks(g.vh);
-        for (int j = 0; j < 16; j++) m.nl.nb[j] = dslash_tile_blocks(g.vh, t);
+        for (int j = 0; j < 16; j++) m.nl.nb[j] = dslash_tile_blocks(g.vh, tr);
         return m;
     }
 
+    // the column map of plan m for launch a (set a.red first)
     void apply(DslashArgs &a, const Mapped &m) const {
+        const bool red = a.red != RED_NONE;
         a.nrhs = __builtin_popcount(m.mask);
         a.cmapped = 1;
-        a.cvalid = m.cvalid;
-        a.cmap = m.cmap;
+        a.cvalid = red ? m.cvalid_red : m.cvalid;
+        a.cmap = red ? m.cmap_red : m.cmap;
     }
 
     // the sloppy launches cover the systems still iterating; a change of that set
@@ -332,12 +339,12 @@ struct BRun {
         A.cactive = c->bactive;   // stopped systems cost no Dslash work
         HISQ_TRY_HIP(launch_dslash(A, fmt, ms_.plan, st, nullptr));
         DslashArgs Bk = dargs(gs, fmt, B->aps, B->ts, 0);
+        Bk.red = RED_DOT_X;
         apply(Bk, ms_);
         Bk.b = -1.0;
         Bk.x = B->p[jb];
         Bk.acol = c->bc;
         Bk.cactive = c->bactive;
-        Bk.red = RED_DOT_X;
         Bk.partial = B->partial;
         Bk.pstride = ms_.nl.pstride;
         Bk.guard = gns;
@@ -374,13 +381,13 @@ struct BRun {
         A.cactive = c->bru;
         HISQ_TRY_HIP(launch_dslash(A, f64, m64_.plan, st, nullptr));
         DslashArgs Bk = dargs(g64, f64, B->r64, B->t64, 0);
+        Bk.red = RED_NORM;
         apply(Bk, m64_);
         Bk.cactive = c->bru;
         Bk.x = B->x64;
         Bk.acol = c->bnc;
         Bk.y = B->b64;
         Bk.c = 1.0;
-        Bk.red = RED_NORM;
         Bk.partial = B->partial;
         Bk.pstride = m64_.nl.pstride;
         HISQ_TRY_HIP(launch_dslash(Bk, f64, m64_.plan, st, nullptr));

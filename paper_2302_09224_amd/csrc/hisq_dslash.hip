@@ -49,7 +49,8 @@ hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const Ds
     }
 }
 
-typedef std::tuple<int, int, int, int, int, int> TuneKey;  // triplet + long-link storage, X, Y, Z, T, rhs block
+// triplet + long-link storage, X, Y, Z, T, rhs block, fused reduction (0 or 1)
+typedef std::tuple<int, int, int, int, int, int, int> TuneKey;
 
 inline int tune_id(const hisq_fmt &f, int long_recon) { return triplet_key(f) * 100 + (long_recon == 12 ? 12 : 18); }
 std::mutex g_tune_mu;
@@ -118,8 +119,11 @@ float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t,
     return best;
 }
 
-DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *probe, hipStream_t st) {
-    const TuneKey key{tune_id(f, probe ? probe->long_recon : 18), g.X, g.Y, g.Z, g.T, c};
+// red: the shape for launches with a fused reduction (timed with RED_NORM into
+// a scratch partial buffer: the per-RHS FP64 sums hold registers that can
+// lower the occupancy of the widest shapes)
+DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *probe, hipStream_t st, bool red) {
+    const TuneKey key{tune_id(f, probe ? probe->long_recon : 18), g.X, g.Y, g.Z, g.T, c, red ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second.first;
@@ -133,6 +137,17 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     p.red = RED_NONE;
     p.guard = Guard{nullptr, 0, 0};
     p.nrhs = std::max(1, std::min(c, probe->nrhs));   // only the columns the probe's buffers hold
+    double *scratch = nullptr;
+    if (red) {
+        // partials of up to 16 field columns, one per block of the largest launch
+        p.pstride = dslash_max_blocks(g.vh);
+        if (hipMalloc((void **)&scratch, 16 * p.pstride * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return best;
+        }
+        p.red = RED_NORM;
+        p.partial = scratch;
+    }
     float tbest = -1.f;
     for (const DslashTile &t : candidates(c, batched_ok, f.compute == 32)) {
         const float ms = time_tile(p, f, t, st);
@@ -140,6 +155,10 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
             tbest = ms;
             best = t;
         }
+    }
+    if (scratch) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(scratch);
     }
     g_tuned[key] = std::make_pair(best, tbest);
     return best;
@@ -162,7 +181,8 @@ DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashA
     while (c < nrhs && c < 16) c <<= 1;
     plan.n = 1;
     plan.rhs0[0] = 0;
-    plan.tile[0] = tile_for(f, g, c, probe, st);
+    plan.tile[0] = tile_for(f, g, c, probe, st, false);
+    plan.tile_red[0] = c > 1 ? tile_for(f, g, c, probe, st, true) : plan.tile[0];
     return plan;
 }
 
@@ -184,7 +204,7 @@ hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_r
 hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPlan &plan, hipStream_t st, int *nblocks) {
     for (int i = 0; i < plan.n; i++) {
         int nb = 0;
-        const DslashTile &t = plan.tile[i];
+        const DslashTile &t = a.red != RED_NONE ? plan.tile_red[i] : plan.tile[i];
         hipError_t e = launch_one(a, f, plan.rhs0[i], t, st, &nb);
         if (e != hipSuccess) return e;
         if (nblocks)
@@ -214,9 +234,12 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
     if (!ok)
         return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d",
                          nr, rg, stage, block, grid, sweep);
-    const TuneKey key{tune_id(fmt, long_recon), dims[0], dims[1], dims[2], dims[3], rhs_block};
+    // the shape serves the launches with and without a fused reduction
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid, sweep}, -1.f);
+    for (int red = 0; red < (rhs_block > 1 ? 2 : 1); red++) {
+        const TuneKey key{tune_id(fmt, long_recon), dims[0], dims[1], dims[2], dims[3], rhs_block, red};
+        g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid, sweep}, -1.f);
+    }
     return HISQ_OK;
 }
 
@@ -234,10 +257,10 @@ extern "C" size_t hisq_tune_report(char *buf, size_t len) {
             const auto &k = kv.first;
             const auto &t = kv.second.first;
             snprintf(line, sizeof(line),
-                     "triplet %03d recon %d lattice %dx%dx%dx%d rhs-block %d: nr %d rg %d stage %d block %d grid %d "
+                     "triplet %03d recon %d lattice %dx%dx%dx%d rhs-block %d%s: nr %d rg %d stage %d block %d grid %d "
                      "sweep %d (%.1f us)\n",
                      std::get<0>(k) / 100, std::get<0>(k) % 100, std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                     std::get<4>(k), std::get<5>(k),
+                     std::get<4>(k), std::get<5>(k), std::get<6>(k) ? " reduction" : "",
                      t.nr, t.rg, t.stage, t.block, t.grid, t.sweep, kv.second.second * 1e3);
             s += line;
         }

@@ -95,10 +95,13 @@ struct DslashTile {
 };
 
 // A whole application: launches covering right-hand sides [rhs0[i], rhs0[i]+nr*rg)
+// with tile[i], or tile_red[i] when the launch fuses a reduction (tuned apart
+// for blocks of right-hand sides; the same tile for one right-hand side)
 struct DslashPlan {
     int n;
     int rhs0[5];
     DslashTile tile[5];
+    DslashTile tile_red[5];
 };
 
 // link pointers, fixed-point steps and long-link storage of a packed gauge

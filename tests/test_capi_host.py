@@ -51,6 +51,9 @@ def test_sizes(hisq):
     assert hisq.hisq_gauge_bytes(dims, 5) == 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("sx24"), hisq.hisq_solver_params_default()) > 0
     assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(4, 3, 32), hisq.hisq_solver_params_default()) == 0
+    # SX24 links with 30-bit spinors: FP64 arithmetic only
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.fmt("sx24_int30"), hisq.hisq_solver_params_default()) > 0
+    assert hisq.hisq_cg_workspace_bytes(dims, hisq.hisq_fmt(4, 4, 32), hisq.hisq_solver_params_default()) == 0
     assert hisq.hisq_gauge_bytes((5, 4, 4, 4), 0) == 0          # odd extent
     assert hisq.hisq_gauge_bytes((2, 4, 4, 4), 0) == 0          # extent below 4
     assert hisq.hisq_spinor_bytes(10, 9) == 0                   # unknown format

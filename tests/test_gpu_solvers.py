@@ -114,7 +114,8 @@ def test_cg_maxiter_reports_noconv():
 
 @pytest.mark.parametrize("ms,ref,batch", [("single", "half", 1), ("int30", "int20", 1), ("double", "double", 1),
                                           ("single", "single", 1), ("int30", "int20", 0), ("single", "half", 0),
-                                          ("int30", "int30_fp32", 1), ("int30", "int24", 1)])
+                                          ("int30", "int30_fp32", 1), ("int30", "int24", 1),
+                                          ("sx24_int30", "int20", 1)])
 def test_multishift(ms, ref, batch):
     """batch: refine the shifted systems together (1) or one after another (0);
     int30_fp32 has no batched form, so it refines one after another either way"""

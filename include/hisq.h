@@ -403,8 +403,10 @@ hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size
  * a persistent grid when smaller than the tile count) and sweep, the order in
  * which the blocks take the tiles of lanes (0: the blocks of XCD k, b % 8 ==
  * k, take the k-th eighth of the lattice; 1: consecutive tiles on consecutive
- * blocks, so all XCDs work on neighbouring sites).  For reproducible launch
- * shapes and for tests.  HISQ_EINVAL for an unsupported shape. */
+ * blocks, so all XCDs work on neighbouring sites).  For rhs_block > 1 the
+ * shape serves both the plain launches and those that fuse a reduction (which
+ * the autotuner otherwise tunes apart).  For reproducible launch shapes and
+ * for tests.  HISQ_EINVAL for an unsupported shape. */
 hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
                           int stage, int block, int grid, int sweep);
 

@@ -410,6 +410,15 @@ hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size
 hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
                           int stage, int block, int grid, int sweep);
 
+/* As hisq_tune_set, but only for the launches that fuse a reduction (the
+ * second Dslash of a batched solver's normal operator, the reliable-update
+ * residual norms), which the autotuner otherwise tunes apart from the plain
+ * launches of the same block; rhs_block 2..16.  Call it after hisq_tune_set
+ * for the same key (hisq_tune_set pins both).  HISQ_EINVAL for an unsupported
+ * shape or rhs_block 1. */
+hisq_status hisq_tune_set_fused(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
+                                int stage, int block, int grid, int sweep);
+
 /* Forget every tuned or fixed launch shape (the next application tunes again). */
 void hisq_tune_clear(void);
 

@@ -215,16 +215,19 @@ hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPla
 
 }  // namespace hisq
 
-extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
-                                     int stage, int block, int grid, int sweep) {
-    using namespace hisq;
-    if (!dims || !dims_ok(dims) || !triplet_ok(fmt)) return set_error(HISQ_EINVAL, "hisq_tune_set: bad dims or triplet");
+namespace hisq {
+namespace {
+// fused: 0 = the plain and the fused-reduction shape, 1 = the fused-reduction shape only
+hisq_status tune_set_impl(const char *who, hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr,
+                          int rg, int stage, int block, int grid, int sweep, int fused) {
+    if (!dims || !dims_ok(dims) || !triplet_ok(fmt)) return set_error(HISQ_EINVAL, "%s: bad dims or triplet", who);
     if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
-        return set_error(HISQ_EINVAL, "hisq_tune_set: long_recon must be 18 or 12");
+        return set_error(HISQ_EINVAL, "%s: long_recon must be 18 or 12", who);
     const bool pow2 = rhs_block >= 1 && rhs_block <= 16 && (rhs_block & (rhs_block - 1)) == 0;
-    if (!pow2) return set_error(HISQ_EINVAL, "hisq_tune_set: rhs_block must be 1, 2, 4, 8 or 16");
-    if (rhs_block > 1 && !has_batched_form(fmt))
-        return set_error(HISQ_EINVAL, "hisq_tune_set: this triplet has no batched Dslash");
+    if (!pow2) return set_error(HISQ_EINVAL, "%s: rhs_block must be 1, 2, 4, 8 or 16", who);
+    if (fused && rhs_block == 1)
+        return set_error(HISQ_EINVAL, "%s: one right-hand side has a single shape (use hisq_tune_set)", who);
+    if (rhs_block > 1 && !has_batched_form(fmt)) return set_error(HISQ_EINVAL, "%s: this triplet has no batched Dslash", who);
     bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
     ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);
     const bool mfma = stage == 5 && rg == 4 && nr <= 4 && fmt.compute == 32;   // the matrix-core path
@@ -232,15 +235,27 @@ extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_r
                                     stage == -2)
                                  : stage == 1));
     if (!ok)
-        return set_error(HISQ_EINVAL, "hisq_tune_set: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d",
-                         nr, rg, stage, block, grid, sweep);
-    // the shape serves the launches with and without a fused reduction
+        return set_error(HISQ_EINVAL, "%s: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d", who, nr,
+                         rg, stage, block, grid, sweep);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (int red = 0; red < (rhs_block > 1 ? 2 : 1); red++) {
+    for (int red = fused ? 1 : 0; red < (rhs_block > 1 ? 2 : 1); red++) {
         const TuneKey key{tune_id(fmt, long_recon), dims[0], dims[1], dims[2], dims[3], rhs_block, red};
         g_tuned[key] = std::make_pair(DslashTile{nr, rg, stage, block, grid, sweep}, -1.f);
     }
     return HISQ_OK;
+}
+}  // namespace
+}  // namespace hisq
+
+extern "C" hisq_status hisq_tune_set(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr, int rg,
+                                     int stage, int block, int grid, int sweep) {
+    return hisq::tune_set_impl("hisq_tune_set", fmt, dims, long_recon, rhs_block, nr, rg, stage, block, grid, sweep, 0);
+}
+
+extern "C" hisq_status hisq_tune_set_fused(hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr,
+                                           int rg, int stage, int block, int grid, int sweep) {
+    return hisq::tune_set_impl("hisq_tune_set_fused", fmt, dims, long_recon, rhs_block, nr, rg, stage, block, grid,
+                               sweep, 1);
 }
 
 extern "C" void hisq_tune_clear(void) {

@@ -154,6 +154,7 @@ def load():
         "hisq_version": (ctypes.c_char_p, []),
         "hisq_tune_report": (sz, [ctypes.c_char_p, sz]),
         "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
+        "hisq_tune_set_fused": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
         "hisq_tune_clear": (None, []),
         "hisq_field_info": (i, [ctypes.c_char_p, ctypes.POINTER(hisq_field_header)]),
         "hisq_spinor_save": (i, [ctypes.c_char_p, vp, ctypes.c_long, i, vp]),
@@ -325,6 +326,12 @@ def hisq_tune_set(f, dims, rhs_block, nr, rg, stage, block, grid, sweep=0, long_
     f = fmt(f) if isinstance(f, (str, tuple)) else f
     _check(load().hisq_tune_set(f, _dims(dims), int(long_recon), int(rhs_block), int(nr), int(rg), int(stage),
                                 int(block), int(grid), int(sweep)), "hisq_tune_set")
+
+
+def hisq_tune_set_fused(f, dims, rhs_block, nr, rg, stage, block, grid, sweep=0, long_recon=RECON_18):
+    f = fmt(f) if isinstance(f, (str, tuple)) else f
+    _check(load().hisq_tune_set_fused(f, _dims(dims), int(long_recon), int(rhs_block), int(nr), int(rg),
+                                      int(stage), int(block), int(grid), int(sweep)), "hisq_tune_set_fused")
 
 
 def hisq_tune_clear():

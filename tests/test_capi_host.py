@@ -158,6 +158,20 @@ def test_tune_set_validation(hisq):
     for args in bad:
         with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
             hisq.hisq_tune_set(*args)
+    # blocks of right-hand sides: hisq_tune_set pins the fused-reduction shape too,
+    # hisq_tune_set_fused only that one
+    rep = hisq.hisq_tune_report()
+    assert "recon 18 lattice 8x8x8x16 rhs-block 4 reduction: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
+    assert "rhs-block 1 reduction" not in rep
+    hisq.hisq_tune_set_fused("double", dims, 4, 4, 1, 1, 128, 0)
+    rep = hisq.hisq_tune_report()
+    assert "recon 18 lattice 8x8x8x16 rhs-block 4 reduction: nr 4 rg 1 stage 1 block 128 grid 0 sweep 0" in rep
+    assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
+    for args in [("half", dims, 1, 1, 1, 1, 256, 0),       # one right-hand side has a single shape
+                 ("half", dims, 4, 2, 1, 1, 256, 0),       # nr*rg != block
+                 ("int30_fp32", dims, 2, 1, 2, 1, 256, 0)]:  # no batched form
+        with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
+            hisq.hisq_tune_set_fused(*args)
     hisq.hisq_tune_clear()
     assert hisq.hisq_tune_report() == ""
 

@@ -202,6 +202,32 @@ def test_batched_cg(sloppy, nrhs):
         assert res <= 1e-10 * (1 + 1e-6), (j, res)
 
 
+@pytest.mark.parametrize("plain,fused", [((4, 4), (8, 2)), ((16, 1), (2, 8)), ((8, 2), (4, 4))])
+def test_batched_cg_fused_shape_differs(plain, fused):
+    """the launches that fuse a reduction on another nr x rg than the plain ones:
+    each has its own column map, and the partial sums follow the fused shape"""
+    hisq = need_gpu()
+    dims, mass, nrhs, sloppy = (6, 8, 10, 12), 0.1, 11, "int20"
+    fat, lng, ev, _ = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", sloppy])
+    bs = inputs.gaussian_spinor(ev.size, inputs.RHS_SEED + 5, nrhs=nrhs).numpy()
+    bs[3] *= 1e-3
+    hisq.hisq_tune_clear()
+    try:
+        for f, recon in ((sloppy, 18), ("double", 18)):
+            hisq.hisq_tune_set(f, dims, 16, plain[0], plain[1], 1, 256, 0, long_recon=recon)
+            hisq.hisq_tune_set_fused(f, dims, 16, fused[0], fused[1], 1, 256, 0, long_recon=recon)
+        x, st = hisq.cg_solve_batched(torch.from_numpy(bs).cuda(), pg[0], pg[hisq.fmt(sloppy).gauge], mass,
+                                      tol=1e-10, sloppy=sloppy)
+    finally:
+        hisq.hisq_tune_clear()
+    assert st["status"] == "HISQ_OK", st
+    x = x.cpu().numpy()
+    for j in range(nrhs):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x[j]), full(dims, ev, bs[j]), dims, mass)
+        assert res <= 1e-10 * (1 + 1e-6), (j, res)
+
+
 @pytest.mark.parametrize("sloppy", ["half", "int20", "single", "int30", "int24"])
 def test_cg_error_estimate_reliable_updates(sloppy):
     """reliable updates triggered by the residual-deviation estimate instead of delta"""

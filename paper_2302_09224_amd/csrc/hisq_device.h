@@ -399,7 +399,9 @@ template <int B, class R> struct SxCodec {
     static __device__ __forceinline__ CVec<R> decode(const unsigned (&w)[F::W], R f = R(1)) {
         const unsigned e = F::get(w, 6);
         CVec<R> v;
-        if (B <= 24) {
+        // FP32 products for B <= 24 in FP32 arithmetic; FP64 otherwise (B-bit
+        // integers times a power of two are exact in both, so the values agree)
+        if (B <= 24 && sizeof(R) == sizeof(float)) {
             const float sc = pow2_f32(e) * (float)f;
 #pragma unroll
             for (int c = 0; c < 3; c++) {

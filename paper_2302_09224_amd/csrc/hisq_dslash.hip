@@ -95,7 +95,7 @@ DslashTile default_tile(int c) {
 }
 
 // time one shape on the probe arguments (pure Dslash, idempotent: no xpay, no reduction)
-float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t, hipStream_t st) {
+float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t, hipStream_t st, int reps = 3) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.f;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -105,7 +105,6 @@ float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t,
     float best = -1.f;
     int nb = 0;
     if (launch_one(probe, f, 0, t, st, &nb) == hipSuccess) {
-        const int reps = 3;
         hipError_t e = hipEventRecord(e0, st);
         for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_one(probe, f, 0, t, st, &nb);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
@@ -148,12 +147,21 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
         p.red = RED_NORM;
         p.partial = scratch;
     }
-    float tbest = -1.f;
+    // every candidate three times, then the three fastest ten times each (a
+    // single noisy sample does not decide between shapes a few per cent apart)
+    std::vector<std::pair<float, DslashTile>> timed;
     for (const DslashTile &t : candidates(c, batched_ok, f.compute == 32)) {
         const float ms = time_tile(p, f, t, st);
+        if (ms > 0.f) timed.emplace_back(ms, t);
+    }
+    std::sort(timed.begin(), timed.end(),
+              [](const std::pair<float, DslashTile> &a, const std::pair<float, DslashTile> &b) { return a.first < b.first; });
+    float tbest = -1.f;
+    for (size_t k = 0; k < timed.size() && k < 3; k++) {
+        const float ms = time_tile(p, f, timed[k].second, st, 10);
         if (ms > 0.f && (tbest < 0.f || ms < tbest)) {
             tbest = ms;
-            best = t;
+            best = timed[k].second;
         }
     }
     if (scratch) {

@@ -273,7 +273,7 @@ def bench_formats(hisq, inputs, torch, dev, reps, dims=(32, 32, 32, 32), mass=0.
     g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
     stream = torch.cuda.current_stream()
     out = {}
-    for name in ("double", "single", "int30", "int30_fp32", "int24", "sx24", "int20", "half"):
+    for name in ("double", "single", "int30", "int30_fp32", "int24", "sx24", "sx24_int30", "int20", "half"):
         f = hisq.fmt(name)
         pg = g64 if f.gauge == hisq.GAUGE_F64 else hisq.pack_gauge(fat, lng, dims, f.gauge)
         pin = hisq.pack_spinor(psi, f.spinor)

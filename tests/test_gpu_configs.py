@@ -85,9 +85,10 @@ def test_config_16():
 
 # max-norm relative Dslash error against the unquantised FP64 oracle, per
 # triplet: FP64 rounding; FP32 rounding; the fixed-point links (2^-31 or 2^-15
-# of the field maximum) and the spinor quantum of each format
+# of the field maximum), the shared-exponent link rows (2^-23 of the row
+# maximum) and the spinor quantum of each format
 DSLASH_TOL = {"double": 1e-13, "single": 1e-6, "int30": 1e-8, "int30_fp32": 2e-6, "int24": 2e-6, "sx24": 2e-6,
-              "sx24_int30": 2e-6, "int20": 3e-4, "half": 3e-4}
+              "sx24_int30": 5e-7, "int20": 3e-4, "half": 3e-4}
 
 
 def test_config_32_formats():

@@ -144,7 +144,7 @@ def test_normal_op(name, tol):
     assert rel_inf(y, ref) <= tol
 
 
-@pytest.mark.parametrize("name", ["double", "single", "half", "int20", "int30", "int24", "sx24"])
+@pytest.mark.parametrize("name", ["double", "single", "half", "int20", "int30", "int24", "sx24", "sx24_int30"])
 @pytest.mark.parametrize("nrhs", [1, 3, 16])
 def test_batched_matches_single(name, nrhs):
     """one link load for a block of right-hand sides gives every right-hand
@@ -169,6 +169,40 @@ def test_batched_matches_single(name, nrhs):
         q = oracle.spinor_quantum(ys, SF_NAME[f.spinor])[:, None]
         d = yb - ys
         assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= q + eps_c(f.compute) * np.abs(ys).max()).all()
+
+
+@pytest.mark.parametrize("name,shape", [("int20", (1, 16, 1)), ("int20", (4, 4, 1)), ("int20", (16, 1, 1)),
+                                        ("int20", (4, 4, 5)), ("half", (2, 8, 1)), ("sx24_int30", (4, 4, 1))])
+def test_batched_padding_columns_untouched(name, shape):
+    """11 right-hand sides in a block of 16: the five padding columns are
+    neither written (a sentinel after the last field survives) nor change the
+    live ones, for several lane layouts (nr, rg, stage; stage 5 = matrix cores)"""
+    hisq = need_gpu()
+    dims, nrhs = (6, 8, 10, 12), 11
+    f = hisq.fmt(name)
+    fat, lng, _ = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    vh = oracle.parity_sites(dims, 1).size
+    srcs = inputs.gaussian_spinor(vh, 510, nrhs=nrhs).numpy()
+    packed = [hisq.pack_spinor(torch.from_numpy(srcs[j]).cuda(), f.spinor) for j in range(nrhs)]
+    nb = hisq.hisq_spinor_bytes(vh, f.spinor)
+    pin = torch.cat([pk[:nb] for pk in packed]).contiguous()
+    pout = torch.full((16 * nb,), 0xA5, dtype=torch.uint8, device="cuda")
+    hisq.hisq_tune_clear()
+    try:
+        hisq.hisq_tune_set(name, dims, 16, shape[0], shape[1], shape[2], 256, 0)
+        hisq.hisq_dslash_batched(pout, pin, pg.desc, 0, f, nrhs)
+        torch.cuda.synchronize()
+    finally:
+        hisq.hisq_tune_clear()
+    assert bool((pout[nrhs * nb:] == 0xA5).all()), "a padding column was written"
+    for j in range(nrhs):
+        single = hisq.dslash(packed[j], pg, 0, f)
+        yb = hisq.unpack_spinor(pout[j * nb:(j + 1) * nb].contiguous(), vh, f.spinor).cpu().numpy()
+        ys = hisq.unpack_spinor(single, vh, f.spinor).cpu().numpy()
+        q = oracle.spinor_quantum(ys, SF_NAME[f.spinor])[:, None]
+        d = yb - ys
+        assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= q + eps_c(f.compute) * np.abs(ys).max()).all(), j
 
 
 @pytest.mark.parametrize("recon", [18, 12])

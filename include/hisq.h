@@ -11,9 +11,24 @@
  *    library never frees or reallocates them.  Pointers marked (host) are
  *    ordinary host memory.  Device pointers must be 16-byte aligned
  *    (HISQ_EALIGN otherwise).
- *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
- *    device work is enqueued on it.  Calls that must return a host value
- *    (gauge packing, solvers) synchronise that stream before returning.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Packing, unpacking and the Dslash calls (hisq_dslash, _xpay, _batched,
+ *    _multi, hisq_normal_op) enqueue their device work on `stream` and return
+ *    without waiting for it, with one exception: the first application of a
+ *    launch-shape key (triplet, long-link storage, lattice, right-hand-side
+ *    block) runs the autotuner, which times candidate shapes on `stream` into
+ *    library-allocated scratch memory (hipMalloc/hipFree, so the device is
+ *    synchronised) and waits for each timing before the real launch is
+ *    enqueued.  HISQ_TUNE=0, hisq_tune_set and hisq_tune_load avoid it.
+ *    Gauge packing synchronises `stream` (the scales are returned on the host).
+ *    The CG solvers (hisq_cg_solve, hisq_multishift_cg_solve,
+ *    hisq_cg_solve_batched) run on a library-owned non-blocking stream of the
+ *    current device (default priority), ordered after the work enqueued on
+ *    `stream` before the call by an event (graphs cannot be captured on the
+ *    null stream), and return after that stream has drained: the results are
+ *    complete on return.  Solver calls on one device are serialised by a
+ *    lock.  hisq_bicgstab_solve enqueues on `stream` and synchronises it for
+ *    every scalar.
  *  - Errors are returned as hisq_status; no C++ exception crosses the ABI.
  *    hisq_last_error() gives a message for the calling thread's last error.
  *  - Lattice: dims = {X, Y, Z, T}, each even and >= 4; site index
@@ -421,6 +436,24 @@ hisq_status hisq_tune_set_fused(hisq_fmt fmt, const int dims[4], int long_recon,
 
 /* Forget every tuned or fixed launch shape (the next application tunes again). */
 void hisq_tune_clear(void);
+
+/* Tune cache files.  hisq_tune_save writes every launch shape of the table
+ * (tuned, fixed or loaded) to `path` (host string), one text line per key:
+ *   hisq-tune 1 <arch> <HIP runtime version> <key: gauge*10000 + spinor*1000 +
+ *   (compute == 64)*100 + long_recon> X Y Z T <rhs block> <fused 0|1> :
+ *   nr rg stage block grid sweep <microseconds, -1000 if not timed>
+ * hisq_tune_load reads such a file and enters the lines whose architecture
+ * and HIP runtime version match the current device (others are skipped) into
+ * the table, replacing entries of the same key; *nloaded (may be NULL)
+ * receives their count.  Both need a current HIP device (HISQ_EHIP
+ * otherwise); HISQ_EIO for a file that cannot be read or written, a
+ * malformed line or a shape the kernels do not have (then nothing is loaded).
+ * With the environment variable HISQ_TUNE_CACHE=<path>, the file is loaded at
+ * the first shape lookup of the process (if it exists) and every shape the
+ * autotuner chooses afterwards is appended to it, so later processes on the
+ * same device and runtime do not tune again. */
+hisq_status hisq_tune_save(const char *path);
+hisq_status hisq_tune_load(const char *path, int *nloaded);
 
 /* Thread-local message of the calling thread's last non-OK status. */
 const char *hisq_last_error(void);

@@ -337,10 +337,9 @@ static int64_t sign_extend(uint64_t u, int bits)
 }
 
 /* QUDA half spinor (Sec. 2, Listing 1): six int16 and the site max |component|.
- * q = round-to-nearest-even(v * (32767/max)); decode v = q * (max * (1/32767))
- * with 1/32767 rounded to FP32 once (the paper fixes the scale, not the
- * rounding of the decode product: one step per site, then one product per
- * component).  A site whose max is zero, or whose 32767/max overflows FP32,
+ * q = round-to-nearest-even(v * (32767/max)); decode v = q * (max/32767), the
+ * quotient max/32767 rounded to FP32 once per site, then one FP32 product per
+ * component.  A site whose max is zero, or whose 32767/max overflows FP32,
  * stores zeros with max 0.  Inputs are FP32 (the format's compute precision). */
 void hisq_oracle_half16_encode(const float *v, int16_t *q, float *norm, long nsites)
 {
@@ -362,7 +361,7 @@ void hisq_oracle_half16_encode(const float *v, int16_t *q, float *norm, long nsi
 void hisq_oracle_half16_decode(const int16_t *q, const float *norm, float *v, long nsites)
 {
     for (long s = 0; s < nsites; s++) {
-        float d = norm[s] * (1.0f / 32767.0f);
+        float d = norm[s] / 32767.0f;
         for (int k = 0; k < 6; k++) v[6 * s + k] = (float)q[6 * s + k] * d;
     }
 }

@@ -171,13 +171,22 @@ template <class R> struct SpinorIO<SF_F32, R> {
     }
 };
 
-// QUDA half: q = rint(v * (32767/M)) with M the FP32 site max; v = q * (M * (1/32767)).
-// A site whose M is zero or whose 32767/M overflows stores zeros with M = 0.
+// QUDA half: q = rint(v * (32767/M)) with M the FP32 site max; v = q * (M/32767),
+// the quotient rounded to FP32 once per site (an IEEE division), then one FP32
+// product per component.  A site whose M is zero or whose 32767/M overflows
+// stores zeros with M = 0.
 template <class R> struct SpinorIO<SF_HALF16, R> {
-    // f: an extra factor folded into the site scale (the Dslash folds link
-    // scales there, one multiply per site instead of one per link element)
-    static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f = 1.0f) {
-        float d = __uint_as_float(w.w) * (1.0f / 32767.0f) * f;
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w) {
+        return scaled(w, __uint_as_float(w.w) / 32767.0f);
+    }
+    // The stencil's decode: f, a factor folded into the site scale (the Dslash
+    // folds link scales there, one multiply per site instead of one per link
+    // element), and M * fl(1/32767) in place of the division: each component
+    // differs from f times the exact decode above by a few FP32 roundings.
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f) {
+        return scaled(w, __uint_as_float(w.w) * (1.0f / 32767.0f) * f);
+    }
+    static __device__ __forceinline__ CVec<R> scaled(u32x4 w, float d) {
         CVec<R> v;
         v.re[0] = (float)sext16(w.x) * d; v.im[0] = (float)sext16(w.x >> 16) * d;
         v.re[1] = (float)sext16(w.y) * d; v.im[1] = (float)sext16(w.y >> 16) * d;

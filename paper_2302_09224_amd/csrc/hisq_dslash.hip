@@ -61,6 +61,122 @@ bool tuning_enabled() {
     return !(e && e[0] == '0');
 }
 
+// a launch shape the kernels are instantiated for, for a block of c right-hand sides
+bool shape_ok(const hisq_fmt &f, int c, const DslashTile &t) {
+    bool ok = t.nr >= 1 && t.rg >= 1 && t.nr * t.rg == c && (t.nr & (t.nr - 1)) == 0 && (t.rg & (t.rg - 1)) == 0;
+    ok = ok && (t.block == 128 || t.block == 256) && t.grid >= 0 && t.grid % 8 == 0 && (t.sweep == 0 || t.sweep == 1);
+    const bool mfma = t.stage == 5 && t.rg == 4 && t.nr <= 4 && f.compute == 32;   // the matrix-core path
+    return ok && (mfma || (t.nr == 1 ? (t.stage == 1 || t.stage == 2 || t.stage == 4 || t.stage == 8 ||
+                                        t.stage == -1 || t.stage == -2)
+                                     : t.stage == 1));
+}
+
+// ---------------------------------------------------------------------------
+// Tune cache files.  One text line per shape key:
+//   hisq-tune <version> <arch> <hip runtime> <triplet*100+recon> X Y Z T <rhs block> <fused> :
+//       nr rg stage block grid sweep <microseconds>
+// Lines of another format version, device architecture or HIP runtime
+// version are skipped on reading (their timings say nothing about this one).
+// ---------------------------------------------------------------------------
+constexpr int kTuneFileVersion = 1;
+
+// "gfx950 <runtime version>" of the current device, or "" without one
+std::string device_tag() {
+    int dev = 0, rv = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipRuntimeGetVersion(&rv) != hipSuccess) {
+        (void)hipGetLastError();
+        return std::string();
+    }
+    std::string arch(prop.gcnArchName);
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + " " + std::to_string(rv);
+}
+
+std::string tune_line(const std::string &tag, const TuneKey &k, const DslashTile &t, float ms) {
+    char line[320];
+    snprintf(line, sizeof(line), "hisq-tune %d %s %d %d %d %d %d %d %d : %d %d %d %d %d %d %.3f\n", kTuneFileVersion,
+             tag.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+             std::get<5>(k), std::get<6>(k), t.nr, t.rg, t.stage, t.block, t.grid, t.sweep, ms * 1e3);
+    return std::string(line);
+}
+
+// Parse `path` into entries for device `tag` (g_tune_mu held by the caller when
+// `apply`).  Returns HISQ_EIO for an unreadable file or a malformed line.
+hisq_status read_tune_file(const char *path, const std::string &tag, bool apply, int *nloaded) {
+    FILE *fp = fopen(path, "r");
+    if (!fp) return set_error(HISQ_EIO, "tune cache %s: cannot open", path);
+    std::vector<std::pair<TuneKey, DslashTile>> got;
+    char line[512];
+    int lineno = 0;
+    hisq_status st = HISQ_OK;
+    while (fgets(line, sizeof(line), fp)) {
+        lineno++;
+        if (line[0] == '\n' || line[0] == '#') continue;
+        int ver = 0, rv = 0, tid = 0, X, Y, Z, T, c, red, nr, rg, stage, block, grid, sweep;
+        char arch[64];
+        float us = 0.f;
+        const int n = sscanf(line, "hisq-tune %d %63s %d %d %d %d %d %d %d %d : %d %d %d %d %d %d %f", &ver, arch, &rv,
+                             &tid, &X, &Y, &Z, &T, &c, &red, &nr, &rg, &stage, &block, &grid, &sweep, &us);
+        if (n != 17) {
+            st = set_error(HISQ_EIO, "tune cache %s: malformed line %d", path, lineno);
+            break;
+        }
+        if (ver != kTuneFileVersion || tag != std::string(arch) + " " + std::to_string(rv)) continue;
+        const hisq_fmt f{tid / 10000, (tid / 1000) % 10, (tid / 100) % 10 ? 64 : 32};
+        const int recon = tid % 100;
+        const int dims[4] = {X, Y, Z, T};
+        const DslashTile t{nr, rg, stage, block, grid, sweep};
+        const bool pow2 = c >= 1 && c <= 16 && (c & (c - 1)) == 0;
+        if (!dims_ok(dims) || !triplet_ok(f) || (recon != 12 && recon != 18) || !pow2 || (red != 0 && red != 1) ||
+            (c > 1 && !has_batched_form(f)) || !shape_ok(f, c, t)) {
+            st = set_error(HISQ_EIO, "tune cache %s: line %d names an unsupported key or shape", path, lineno);
+            break;
+        }
+        got.emplace_back(TuneKey{tid, X, Y, Z, T, c, red}, t);
+    }
+    fclose(fp);
+    if (st != HISQ_OK) return st;
+    if (apply)
+        for (const auto &e : got) g_tuned[e.first] = std::make_pair(e.second, -1.f);
+    if (nloaded) *nloaded = (int)got.size();
+    return HISQ_OK;
+}
+
+// HISQ_TUNE_CACHE=<path>: shapes read from the file at the first lookup of the
+// process, and every shape tuned afterwards appended to it
+const char *cache_path() {
+    const char *p = getenv("HISQ_TUNE_CACHE");
+    return (p && p[0]) ? p : nullptr;
+}
+bool g_cache_read = false;
+
+void cache_read_once() {
+    if (g_cache_read) return;
+    g_cache_read = true;
+    const char *path = cache_path();
+    if (!path) return;
+    const std::string tag = device_tag();
+    FILE *probe = fopen(path, "r");
+    if (!probe) return;   // no file yet: it is created by the first append
+    fclose(probe);
+    if (!tag.empty()) (void)read_tune_file(path, tag, true, nullptr);
+}
+
+void cache_append(const TuneKey &k, const DslashTile &t, float ms) {
+    const char *path = cache_path();
+    if (!path) return;
+    const std::string tag = device_tag();
+    if (tag.empty()) return;
+    FILE *fp = fopen(path, "a");
+    if (!fp) return;
+    const std::string l = tune_line(tag, k, t, ms);
+    fputs(l.c_str(), fp);
+    fclose(fp);
+}
+
 // candidate shapes for a block of c right-hand sides (c a power of two <= 16)
 // grids: 0 = one tile per block; 256*k = a persistent grid of k blocks per CU
 std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32) {
@@ -124,6 +240,7 @@ float time_tile(const DslashArgs &probe, const hisq_fmt &f, const DslashTile &t,
 DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *probe, hipStream_t st, bool red) {
     const TuneKey key{tune_id(f, probe ? probe->long_recon : 18), g.X, g.Y, g.Z, g.T, c, red ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    cache_read_once();
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second.first;
     const bool batched_ok = has_batched_form(f);
@@ -136,12 +253,29 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     p.red = RED_NONE;
     p.guard = Guard{nullptr, 0, 0};
     p.nrhs = std::max(1, std::min(c, probe->nrhs));   // only the columns the probe's buffers hold
+    // The candidates write a library-owned output, never the caller's: the
+    // caller's output may alias an operand of the real launch (out == x in
+    // an in-place xpay) or hold data the caller still needs.
+    int cols = p.nrhs;
+    if (p.cmapped) {
+        cols = 1;
+        for (int k = 0; k < 16; k++)
+            if ((p.cvalid >> k) & 1u) cols = std::max(cols, (int)((p.cmap >> (4 * k)) & 15ull) + 1);
+    }
+    const size_t out_bytes = (size_t)(cols - 1) * p.field_stride + spinor_field_bytes((size_t)g.vh, f.spinor);
+    char *scratch_out = nullptr;
+    if (hipMalloc((void **)&scratch_out, out_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return best;
+    }
+    p.out = scratch_out;
     double *scratch = nullptr;
     if (red) {
         // partials of up to 16 field columns, one per block of the largest launch
         p.pstride = dslash_max_blocks(g.vh);
         if (hipMalloc((void **)&scratch, 16 * p.pstride * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
+            (void)hipFree(scratch_out);
             return best;
         }
         p.red = RED_NORM;
@@ -164,11 +298,11 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
             best = timed[k].second;
         }
     }
-    if (scratch) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(scratch);
-    }
+    (void)hipStreamSynchronize(st);
+    if (scratch) (void)hipFree(scratch);
+    (void)hipFree(scratch_out);
     g_tuned[key] = std::make_pair(best, tbest);
+    if (tbest > 0.f) cache_append(key, best, tbest);
     return best;
 }
 
@@ -236,13 +370,7 @@ hisq_status tune_set_impl(const char *who, hisq_fmt fmt, const int dims[4], int 
     if (fused && rhs_block == 1)
         return set_error(HISQ_EINVAL, "%s: one right-hand side has a single shape (use hisq_tune_set)", who);
     if (rhs_block > 1 && !has_batched_form(fmt)) return set_error(HISQ_EINVAL, "%s: this triplet has no batched Dslash", who);
-    bool ok = nr >= 1 && rg >= 1 && nr * rg == rhs_block && (nr & (nr - 1)) == 0 && (rg & (rg - 1)) == 0;
-    ok = ok && (block == 128 || block == 256) && grid >= 0 && grid % 8 == 0 && (sweep == 0 || sweep == 1);
-    const bool mfma = stage == 5 && rg == 4 && nr <= 4 && fmt.compute == 32;   // the matrix-core path
-    ok = ok && (mfma || (nr == 1 ? (stage == 1 || stage == 2 || stage == 4 || stage == 8 || stage == -1 ||
-                                    stage == -2)
-                                 : stage == 1));
-    if (!ok)
+    if (!shape_ok(fmt, rhs_block, DslashTile{nr, rg, stage, block, grid, sweep}))
         return set_error(HISQ_EINVAL, "%s: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d", who, nr,
                          rg, stage, block, grid, sweep);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -269,6 +397,36 @@ extern "C" hisq_status hisq_tune_set_fused(hisq_fmt fmt, const int dims[4], int 
 extern "C" void hisq_tune_clear(void) {
     std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
     hisq::g_tuned.clear();
+    hisq::g_cache_read = true;   // a cleared table is not refilled from HISQ_TUNE_CACHE
+}
+
+extern "C" hisq_status hisq_tune_save(const char *path) {
+    if (!path) return hisq::set_error(HISQ_EINVAL, "hisq_tune_save: null path");
+    const std::string tag = hisq::device_tag();
+    if (tag.empty()) return hisq::set_error(HISQ_EHIP, "hisq_tune_save: no current HIP device");
+    std::string body = "# libhisq launch shapes (hisq_tune_save)\n";
+    {
+        std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
+        for (const auto &kv : hisq::g_tuned) body += hisq::tune_line(tag, kv.first, kv.second.first, kv.second.second);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *fp = fopen(tmp.c_str(), "w");
+    if (!fp) return hisq::set_error(HISQ_EIO, "hisq_tune_save: cannot write %s", tmp.c_str());
+    const bool ok = fwrite(body.data(), 1, body.size(), fp) == body.size();
+    if (fclose(fp) != 0 || !ok || rename(tmp.c_str(), path) != 0) {
+        (void)remove(tmp.c_str());
+        return hisq::set_error(HISQ_EIO, "hisq_tune_save: cannot write %s", path);
+    }
+    return HISQ_OK;
+}
+
+extern "C" hisq_status hisq_tune_load(const char *path, int *nloaded) {
+    if (nloaded) *nloaded = 0;
+    if (!path) return hisq::set_error(HISQ_EINVAL, "hisq_tune_load: null path");
+    const std::string tag = hisq::device_tag();
+    if (tag.empty()) return hisq::set_error(HISQ_EHIP, "hisq_tune_load: no current HIP device");
+    std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
+    return hisq::read_tune_file(path, tag, true, nloaded);
 }
 
 extern "C" size_t hisq_tune_report(char *buf, size_t len) {

@@ -156,6 +156,8 @@ def load():
         "hisq_tune_set": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
         "hisq_tune_set_fused": (i, [hisq_fmt, ip, i, i, i, i, i, i, i, i]),
         "hisq_tune_clear": (None, []),
+        "hisq_tune_save": (i, [ctypes.c_char_p]),
+        "hisq_tune_load": (i, [ctypes.c_char_p, ip]),
         "hisq_field_info": (i, [ctypes.c_char_p, ctypes.POINTER(hisq_field_header)]),
         "hisq_spinor_save": (i, [ctypes.c_char_p, vp, ctypes.c_long, i, vp]),
         "hisq_spinor_load": (i, [ctypes.c_char_p, vp, ctypes.c_long, i, vp]),
@@ -336,6 +338,17 @@ def hisq_tune_set_fused(f, dims, rhs_block, nr, rg, stage, block, grid, sweep=0,
 
 def hisq_tune_clear():
     load().hisq_tune_clear()
+
+
+def hisq_tune_save(path):
+    _check(load().hisq_tune_save(os.fsencode(path)), "hisq_tune_save")
+
+
+def hisq_tune_load(path):
+    """enter the launch shapes of a tune cache file; returns how many"""
+    n = ctypes.c_int(0)
+    _check(load().hisq_tune_load(os.fsencode(path), ctypes.byref(n)), "hisq_tune_load")
+    return n.value
 
 
 def hisq_tune_report():

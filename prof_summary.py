@@ -1,6 +1,6 @@
 """Condense rocprofv3 CSV output into a short text summary.
 
-    python -m paper_2302_09224_amd.prof_summary DIR [--match SUBSTR] [--block B --grid G] [--top N] [--delete]
+    python3 prof_summary.py DIR [--match SUBSTR] [--block B --grid G] [--top N] [--delete]
 
 DIR is a rocprofv3 ``-d`` output directory written with ``--output-format csv``.
 Prints the per-kernel statistics (``*kernel_stats.csv``: calls, total, average),

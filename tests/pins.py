@@ -10,6 +10,7 @@ hand-derived storage-format vectors.
 from __future__ import annotations
 
 import os
+from fractions import Fraction
 
 import numpy as np
 import torch
@@ -293,6 +294,43 @@ def check_half16_golden(lib):
     return not bad, f"half16 golden mismatches: {bad}"
 
 
+def _rn_f32(x):
+    """round a Fraction to the nearest FP32 value, ties to even (normal range)"""
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    m = a / Fraction(2) ** (e - 23)          # a in [2^e, 2^(e+1)): 24 significant bits
+    fl = m.numerator // m.denominator
+    r = m - fl
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return s * fl * Fraction(2) ** (e - 23)
+
+
+def check_half16_decode_exact(lib):
+    """Sec. 2, Listing 1: a stored component q with site max M stands for
+    q * (M/32767); in FP32 the quotient M/32767 is rounded once per site and
+    the product once per component.  Derived in exact rational arithmetic.
+    M = 513 is a site max where M * fl(1/32767) differs from fl(M/32767)."""
+    rng = np.random.default_rng(11)
+    nm = np.concatenate([np.array([513.0, 1.0, 7.25, 32767.0], dtype=np.float32),
+                         (rng.uniform(0.5, 2.0, 60) * 2.0 ** rng.integers(-40, 40, 60)).astype(np.float32)])
+    q = rng.integers(-32767, 32768, size=(nm.size, 6)).astype(np.int16)
+    q[:, 0] = 32767
+    got = oracle.half16_decode(q, nm, lib=lib)
+    bad = []
+    for s in range(nm.size):
+        d = _rn_f32(Fraction(float(nm[s])) / 32767)
+        for k in range(6):
+            if Fraction(float(got[s, k])) != _rn_f32(int(q[s, k]) * d):
+                bad.append((float(nm[s]), int(q[s, k]), float(got[s, k])))
+    return not bad, f"half16 decode mismatches: {bad[:5]}"
+
+
 def check_fixed_golden(lib):
     bad = []
     for (bits, absmax, u), (qs,) in _read_golden("fixed_gauge.txt"):
@@ -306,5 +344,6 @@ ALL_OPERATOR = [check_antihermitian, check_parity_structure, check_gauge_covaria
                 check_free_field_dslash, check_free_field_normal, check_normal_hpd]
 ALL_SOLVER = [check_cg_dense, check_multishift_dense, check_multishift_single_is_cg,
               check_multishift_colinear]
-ALL_CODEC = [check_int20_golden, check_int30_golden, check_half16_golden, check_fixed_golden]
+ALL_CODEC = [check_int20_golden, check_int30_golden, check_half16_golden, check_half16_decode_exact,
+             check_fixed_golden]
 ALL = ALL_OPERATOR + ALL_SOLVER + ALL_CODEC

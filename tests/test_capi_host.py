@@ -176,6 +176,20 @@ def test_tune_set_validation(hisq):
     assert hisq.hisq_tune_report() == ""
 
 
+def test_tune_cache_needs_a_device(hisq, tmp_path):
+    """without a HIP device the tune cache calls report HISQ_EHIP and touch no file"""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(hisq.HisqError, match="HISQ_EHIP"):
+        hisq.hisq_tune_save(tmp_path / "t.txt")
+    with pytest.raises(hisq.HisqError, match="HISQ_EHIP"):
+        hisq.hisq_tune_load(tmp_path / "t.txt")
+    assert not (tmp_path / "t.txt").exists()
+    assert hisq.load().hisq_tune_save(None) == -1
+    assert hisq.load().hisq_tune_load(None, None) == -1
+
+
 def test_workspace_too_small_is_reported_before_any_device_work(hisq):
     """every solver checks its workspace before touching the device (pointers
     here are never dereferenced)"""

@@ -98,3 +98,25 @@ def test_shared_exponent_tiny_sites_bit_exact(fmt):
     back = hisq.unpack_spinor(packed, n, fmt).cpu().numpy()
     assert np.array_equal(back.view(np.float64), oracle.spinor_decode_records(rec, name).view(np.float64))
     assert (((rec[:, 3] >> 24) if fmt == 3 else ((rec[:, 4] >> 16) & 0xFF)) < 13).any()
+
+
+def test_half16_decode_mantissa_sweep():
+    """HALF16 unpack is q * fl(M/32767) bit for bit over 2^20 site maxima M
+    (every 8th FP32 mantissa of a binade, in three binades, M = 513 included),
+    the sites where a reciprocal-then-multiply decode would round differently"""
+    hisq = need_gpu()
+    n = 1 << 20
+    mant = (np.arange(n, dtype=np.uint32) * 8) & 0x7FFFFF
+    expo = np.array([127, 127 + 40, 127 - 60], dtype=np.uint32)[np.arange(n) % 3]
+    m = ((expo << 23) | mant).view(np.float32)
+    m[0] = np.float32(513.0)
+    rng = np.random.default_rng(42)
+    v = (rng.uniform(-1, 1, size=(n, 6)).astype(np.float32) * m[:, None]).astype(np.float64)
+    v[:, rng.integers(0, 6)] = m                    # the site max, exactly M
+    cv = v[:, 0::2] + 1j * v[:, 1::2]
+    packed = hisq.pack_spinor(torch.from_numpy(cv).cuda(), hisq.SPINOR_HALF16)
+    rec = spinor_records(packed.cpu().numpy(), n, 2)
+    assert np.array_equal(rec[1], m)
+    back = hisq.unpack_spinor(packed, n, hisq.SPINOR_HALF16).cpu().numpy()
+    want = oracle.spinor_decode_records(rec, "half16")
+    assert np.array_equal(back.view(np.float64), want.view(np.float64))

@@ -120,6 +120,78 @@ def test_xpay(name):
     assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= bound).all()
 
 
+@pytest.mark.parametrize("name", ["single", "int20"])
+def test_xpay_in_place_on_first_application(name):
+    """out = a*out + b*D(in) with out == x, on the first application of its
+    launch-shape key (the autotuner times its candidates then; they must not
+    write the caller's output, which is also the x operand)"""
+    hisq = need_gpu()
+    dims = (6, 8, 10, 12)
+    f = hisq.fmt(name)
+    fat, lng, psi = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    src, dst = oracle.parity_sites(dims, 1), oracle.parity_sites(dims, 0)
+    xv = inputs.gaussian_spinor(dst.size, 98).numpy()
+    pin = hisq.pack_spinor(torch.from_numpy(psi[src]).cuda(), f.spinor)
+    px = hisq.pack_spinor(torch.from_numpy(xv).cuda(), f.spinor)
+    a, b = -0.61, 0.83
+    hisq.hisq_tune_clear()
+    hisq.hisq_dslash_xpay(px, pin, pg.desc, 0, f, a, px, b)
+    assert "lattice 6x8x10x12 rhs-block 1" in hisq.hisq_tune_report()
+    y = hisq.unpack_spinor(px, dst.size, f.spinor).cpu().numpy()
+    full = np.zeros_like(psi)
+    full[src] = psi[src]
+    ref = a * oracle.spinor_roundtrip(xv, SF_NAME[f.spinor]) + b * oracle.emulated_dslash(
+        fat.numpy(), lng.numpy(), full, dims, 0, GF_NAME[f.gauge], SF_NAME[f.spinor], f.compute)[dst]
+    q = oracle.spinor_quantum(ref, SF_NAME[f.spinor])[:, None]
+    bound = 0.5 * q * (1 + 1e-3) + 2 * eps_c(f.compute) * np.abs(ref).max()
+    d = y - ref
+    assert (np.maximum(np.abs(d.real), np.abs(d.imag)) <= bound).all()
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """shapes saved, cleared and loaded again give the same table and the same
+    results; HISQ_TUNE_CACHE appends every newly tuned shape"""
+    import os
+    hisq = need_gpu()
+    dims = (8, 8, 8, 8)
+    f = hisq.fmt("int20")
+    fat, lng, psi = fields(dims, "near_unit")
+    pg = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, f.gauge)
+    src = oracle.parity_sites(dims, 1)
+    pin = hisq.pack_spinor(torch.from_numpy(psi[src]).cuda(), f.spinor)
+    cache = tmp_path / "tune.txt"
+    hisq.hisq_tune_clear()
+    os.environ["HISQ_TUNE_CACHE"] = str(cache)
+    try:
+        y0 = hisq.dslash(pin, pg, 0, f).cpu()
+    finally:
+        del os.environ["HISQ_TUNE_CACHE"]
+    lines = [ln for ln in cache.read_text().splitlines() if ln.startswith("hisq-tune")]
+    assert len(lines) == 1 and " 8 8 8 8 1 0 : " in lines[0]
+    rep = hisq.hisq_tune_report()
+    saved = tmp_path / "saved.txt"
+    hisq.hisq_tune_save(saved)
+    hisq.hisq_tune_clear()
+    assert hisq.hisq_tune_report() == ""
+    assert hisq.hisq_tune_load(saved) == 1
+    shape = lambda r: r.split(": ", 1)[1].split(" (")[0]          # noqa: E731
+    assert shape(hisq.hisq_tune_report()) == shape(rep)
+    y1 = hisq.dslash(pin, pg, 0, f).cpu()
+    assert torch.equal(y0, y1)
+    # a line for another architecture is skipped; a malformed line loads nothing
+    other = tmp_path / "other.txt"
+    other.write_text(lines[0].replace("hisq-tune 1 gfx950", "hisq-tune 1 gfx000") + "\n")
+    assert hisq.hisq_tune_load(other) == 0
+    bad = tmp_path / "bad.txt"
+    bad.write_text(lines[0] + "\nhisq-tune 1 gfx950 garbage\n")
+    hisq.hisq_tune_clear()
+    with pytest.raises(hisq.HisqError, match="HISQ_EIO"):
+        hisq.hisq_tune_load(bad)
+    assert hisq.hisq_tune_report() == ""
+    hisq.hisq_tune_clear()
+
+
 @pytest.mark.parametrize("name,tol", [("double", 1e-13), ("single", 2e-6), ("int30", 1e-8), ("int20", 2e-4),
                                       ("half", 2e-4), ("int24", 4e-6), ("sx24", 4e-6)])
 def test_normal_op(name, tol):

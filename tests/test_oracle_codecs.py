@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import oracle
+import pins
 
 
 def rand6(n, seed, dtype, spread=True):
@@ -90,3 +91,12 @@ def test_fixed_gauge_bound(bits, oracle_lib):
     d = back - u
     err = max(np.abs(d.real).max(), np.abs(d.imag).max())
     assert err <= 0.5 * absmax / Q * (1 + 1e-12) + absmax * 2.0 ** -52
+
+
+
+def test_half16_decode_exact_definition(oracle_lib):
+    ok, detail = pins.check_half16_decode_exact(oracle_lib)
+    assert ok, detail
+    # the rounding order the definition excludes differs at M = 513
+    r = np.float32(1.0) / np.float32(32767.0)
+    assert np.float32(513.0) * r != np.float32(np.float32(513.0) / np.float32(32767.0))

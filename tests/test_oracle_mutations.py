@@ -29,6 +29,7 @@ MUTATIONS = {
                                       "uint32_t e = ((f32_bits(t) >> 23) & 0xffu) + 0u;"),
     "int30_scale_2_30": ("double t = m / 536870911.0;", "double t = m / 1073741823.0;"),
     "half16_scale_2_15": ("float c = 32767.0f / m;", "float c = 32768.0f / m;"),
+    "half16_decode_reciprocal": ("float d = norm[s] / 32767.0f;", "float d = norm[s] * (1.0f / 32767.0f);"),
     "fix16_truncate": ("q[k] = (int16_t)llrint(u[k] * c);", "q[k] = (int16_t)(u[k] * c);"),
 }
 

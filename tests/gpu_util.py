@@ -91,3 +91,18 @@ def make_fields(dims, kind="near_unit", seed=inputs.GAUGE_SEED, device="cuda"):
 
 def rel_inf(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def format_bounds():
+    """{triplet: (Dslash bound, normal-operator bound)}: max-norm relative
+    errors against the unquantised FP64 operator, written by
+    golden/make_format_bounds.py from the oracle alone"""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "format_bounds.txt")
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, d, n = [part.split() for part in line.split("|")]
+        out[name[0]] = (float(d[1]), float(n[1]))
+    return out

@@ -1,6 +1,5 @@
 """The workloads the method is measured on, each as a parity case at its own
-size (the oracle checks what it can compute: whole fields at 16^4 and 32^4,
-sampled sites of the 48^3x96 solve):
+size, the oracle checking whole fields:
 
 * 16^4, near-unit links: the FP64 and FP32 Dslash (18-real links) against the
   FP64 oracle; double-single CG with reliable updates (delta = 0.1, m = 0.05)
@@ -10,9 +9,10 @@ sampled sites of the 48^3x96 solve):
   a 1e-10 true residual (measured by the oracle's FP64 operator).
 * 48^3x96, near-unit links, m = 0.005: the mixed 12-shift solve (shifts
   log-spaced 1e-5..10, two-row long links, multi-shift in FIX32/INT30/FP64,
-  refinement in FIX16/INT20/FP32): every shift's true residual <= 1e-10, the
-  residual vector checked against the oracle at sampled sites, and each
-  shift's solution against a lone CG solve of that shift.
+  refinement in FIX16/INT20/FP32): every shift's true residual <= 1e-10 from
+  the oracle's FP64 operator over the whole lattice, the largest shift's
+  solution against the oracle's FP64 CG, and each shift's solution against a
+  lone CG solve of that shift.
 * 32^3x64, near-unit links, m = 0.01: 16 right-hand sides solved together
   in INT20 storage, each to a 1e-10 true residual (oracle), and the uneven
   batch of lattices 8^4, 12^4, 16^4, 24^4 in one Dslash launch.
@@ -22,7 +22,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import need_gpu, rel_inf
+from gpu_util import format_bounds, need_gpu, rel_inf
 from paper_2302_09224_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -84,11 +84,12 @@ def test_config_16():
 
 
 # max-norm relative Dslash error against the unquantised FP64 oracle, per
-# triplet: FP64 rounding; FP32 rounding; the fixed-point links (2^-31 or 2^-15
-# of the field maximum), the shared-exponent link rows (2^-23 of the row
-# maximum) and the spinor quantum of each format
-DSLASH_TOL = {"double": 1e-13, "single": 1e-6, "int30": 1e-8, "int30_fp32": 2e-6, "int24": 2e-6, "sx24": 2e-6,
-              "sx24_int30": 5e-7, "int20": 3e-4, "half": 3e-4}
+# triplet: FP64 and FP32 rounding for the IEEE triplets (1e-13, 1e-6); for the
+# others 4x the largest format error the oracle's emulation of the storage
+# formats shows over five seeds at 16^4, plus the compute allowance
+# (golden/format_bounds.txt, written by golden/make_format_bounds.py)
+DSLASH_TOL = {name: b[0] for name, b in format_bounds().items()}
+DSLASH_TOL.update({"double": 1e-13, "single": 1e-6})
 
 
 def test_config_32_formats():
@@ -127,97 +128,80 @@ def test_config_32_formats():
     assert iters["int20"] <= 1.02 * iters["half"], iters
 
 
-def _neighbours(sites, dims):
-    """lexicographic sites at +-1, +-3 hops of each site, per (mu, hop)"""
-    X, Y, Z, T = dims
-    c = [sites % X, (sites // X) % Y, (sites // (X * Y)) % Z, sites // (X * Y * Z)]
-    out = []
-    for mu in range(4):
-        for h in (1, -1, 3, -3):
-            cc = [v.copy() for v in c]
-            cc[mu] = (cc[mu] + h) % dims[mu]
-            out.append((mu, h, ((cc[3] * Z + cc[2]) * Y + cc[1]) * X + cc[0]))
-    return out
-
-
-class SampledOperator:
-    """the oracle's (4m^2 + s - D_eo D_oe) x at a few even sites of a large
-    lattice: only the links and solution entries those sites reach are
-    copied from the device into lazily allocated full-size arrays"""
-
-    def __init__(self, fat, lng, dims, samp_cb):
-        V = oracle.volume(dims)
-        self.dims, self.V = dims, V
-        self.ev = oracle.parity_sites(dims, 0)
-        self.S = self.ev[samp_cb]
-        self.samp_cb = samp_cb
-        n1 = np.unique(np.concatenate([nb for _, _, nb in _neighbours(self.S, dims)]))
-        n2 = np.unique(np.concatenate([nb for _, _, nb in _neighbours(n1, dims)]))
-        self.n1, self.n2 = n1, n2
-        links = set()
-        for sites in (self.S, n1):
-            for mu, h, nb in _neighbours(sites, dims):
-                links.update((mu * V + (sites if h > 0 else nb)).tolist())
-        lidx = np.array(sorted(links))
-        li = torch.from_numpy(lidx).cuda()
-        self.fat = np.zeros((4 * V, 3, 3), dtype=np.complex128)
-        self.lng = np.zeros((4 * V, 3, 3), dtype=np.complex128)
-        self.fat[lidx] = fat.reshape(4 * V, 3, 3)[li].cpu().numpy()
-        self.lng[lidx] = lng.reshape(4 * V, 3, 3)[li].cpu().numpy()
-        self.n2_cb = torch.from_numpy(np.searchsorted(self.ev, n2)).cuda()
-        self.x = np.zeros((V, 3), dtype=np.complex128)
-        self.y = np.zeros((V, 3), dtype=np.complex128)
-
-    def apply(self, x_dev, c):
-        self.x[self.n2] = x_dev[self.n2_cb].cpu().numpy()
-        f4 = (self.fat.reshape(4, self.V, 3, 3), self.lng.reshape(4, self.V, 3, 3))
-        self.y[self.n1] = oracle.dslash_sites(*f4, self.x, self.dims, self.n1)
-        return c * self.x[self.S] - oracle.dslash_sites(*f4, self.y, self.dims, self.S)
-
-
 def test_config_48_multishift():
+    """the benchmark solve: every shift's true residual from the oracle's FP64
+    operator over the whole 48^3x96 lattice (the residual bounds the solution
+    error by the condition number), the largest shift's solution against the
+    oracle's own FP64 CG, and every shift's solution against a lone CG solve"""
     hisq = need_gpu()
     dims, mass = (48, 48, 48, 96), 0.005
     shifts = list(np.logspace(-5, 1, 12))
     fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED, device="cuda")
     vh = oracle.volume(dims) // 2
+    ev = oracle.parity_sites(dims, 0)
     b = inputs.gaussian_spinor(vh, inputs.SOURCE_SEED, device="cuda")
     g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=12)
     gms = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_FIX32, long_recon=12)
     gref = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_FIX16, long_recon=12)
     xs, st = hisq.multishift_cg_solve(b, shifts, 1e-10, g64, gms, gref, mass, ms_fmt="int30", ref_fmt="int20")
     assert st["status"] == "HISQ_OK", st
-    samp_cb = np.unique(np.concatenate([np.random.default_rng(7).integers(0, vh, 400), [0, vh - 1]]))
-    op = SampledOperator(fat, lng, dims, samp_cb)
+    fat_h, lng_h = fat.cpu().numpy(), lng.cpu().numpy()
     del fat, lng
     torch.cuda.empty_cache()
-    f64 = hisq.fmt("double")
-    bp = hisq.pack_spinor(b, hisq.SPINOR_F64)
-    b_s = b[torch.from_numpy(samp_cb).cuda()].cpu().numpy()
-    bn = float(b.norm())
+    bfull = full_even(dims, ev, b.cpu().numpy())
     for i, (s, x) in enumerate(zip(shifts, xs)):
-        c = 4 * mass * mass + s
-        # the whole residual with the library's FP64 operator ...
-        xp = hisq.pack_spinor(x, hisq.SPINOR_F64)
-        ax, tmp = torch.empty_like(xp), torch.empty_like(xp)
-        hisq.hisq_normal_op(ax, xp, tmp, g64.desc, mass, s, f64)
-        r = b - hisq.unpack_spinor(ax, vh, hisq.SPINOR_F64)
-        res = float(r.norm()) / bn
+        xfull = full_even(dims, ev, x.cpu().numpy())
+        res = oracle.true_residual(fat_h, lng_h, xfull, bfull, dims, mass, shift=s)
+        print(f"shift {s:.3e}: oracle true residual {res:.3e}, library {st['shift_resid'][i]:.3e}", flush=True)
         assert res <= 1e-10 * (1 + 1e-6), (i, s, res)
         assert abs(res - st["shift_resid"][i]) <= 1e-3 * res, (i, res, st["shift_resid"][i])
-        # ... is the oracle's at the sampled sites, up to FP64 rounding of b - A x
-        r_or = b_s - op.apply(x, c)
-        r_gpu = r[torch.from_numpy(samp_cb).cuda()].cpu().numpy()
-        scale = np.abs(b_s).max() + (c + LAMBDA_D) * float(x.abs().max())
-        assert np.abs(r_or - r_gpu).max() <= 1e-13 * scale, (i, np.abs(r_or - r_gpu).max(), scale)
-        # the sampled sites carry no more than their share of the residual
-        assert np.sqrt(np.mean(np.abs(r_or) ** 2) * vh) <= 4 * 1e-10 * bn, i
         # a lone CG on this shift reaches the same solution, to what the condition number allows
         xc, sc = hisq.cg_solve(b, g64, gref, mass, shift=s, tol=1e-10, sloppy="int20")
         assert sc["status"] == "HISQ_OK", (i, sc)
         d = float((xc - x).norm() / xc.norm())
         assert d <= 2e-10 * kappa(mass, s), (i, s, d)
-        del xp, ax, tmp, r, xc
+        del xc
+    # the oracle's own FP64 CG on the largest shift (the fewest iterations)
+    s = shifts[-1]
+    xo, it, res_o, status = oracle.cg(fat_h, lng_h, bfull, dims, mass, shift=s, tol=1e-11)
+    assert res_o <= 2e-11, (it, res_o, status)
+    xg = full_even(dims, ev, xs[-1].cpu().numpy())
+    d = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    print(f"shift {s:.3e}: oracle CG {it} iterations, |x - x_oracle|/|x_oracle| = {d:.3e}", flush=True)
+    assert d <= (1e-10 + 2e-11) * kappa(mass, s), d
+
+
+def test_config_32x64_batched_dslash_vs_emulation():
+    """the batched Dslash of the 32^3x64 workload (16 right-hand sides,
+    FIX16/INT20/FP32, two-row long links) in the launch shape the autotuner
+    picks, every column against the oracle's format emulation at every site"""
+    hisq = need_gpu()
+    dims, nrhs = (32, 32, 32, 64), 16
+    f = hisq.fmt("int20")
+    fat, lng, fat_h, lng_h = host_links(dims, inputs.GAUGE_SEED + 16)
+    pg = hisq.pack_gauge(fat, lng, dims, f.gauge, long_recon=12)
+    ev, od = oracle.parity_sites(dims, 0), oracle.parity_sites(dims, 1)
+    srcs = inputs.gaussian_spinor(od.size, inputs.RHS_SEED + 40, nrhs=nrhs).numpy()
+    nb = hisq.hisq_spinor_bytes(od.size, f.spinor)
+    pin = torch.cat([hisq.pack_spinor(torch.from_numpy(srcs[j]).cuda(), f.spinor)[:nb] for j in range(nrhs)])
+    pout = torch.empty_like(pin)
+    hisq.hisq_dslash_batched(pout, pin.contiguous(), pg.desc, 0, f, nrhs)
+    print("\n" + "".join(ln for ln in hisq.hisq_tune_report().splitlines(True) if "32x32x32x64 rhs-block 16" in ln))
+    fq = oracle.gauge_roundtrip(fat_h, "fix16", 32)
+    lq = oracle.long_recon_roundtrip(lng_h, dims, "fix16", 32)
+    del fat, lng
+    worst = 0.0
+    for j in range(nrhs):
+        y = hisq.unpack_spinor(pout[j * nb:(j + 1) * nb].contiguous(), ev.size, f.spinor).cpu().numpy()
+        src = oracle.to_full(oracle.spinor_roundtrip(srcs[j], "int20"), dims, 1)
+        ref = oracle.dslash(fq, lq, src, dims, 0)[ev]
+        q = oracle.spinor_quantum(ref, "int20")[:, None]
+        bound = 0.5 * q * (1 + 1e-3) + 1e-6 * np.abs(ref).max()
+        d = y - ref
+        r = float((np.maximum(np.abs(d.real), np.abs(d.imag)) / bound).max())
+        worst = max(worst, r)
+        assert r <= 1.0, (j, r)
+    print(f"max error / bound over 16 columns: {worst:.3f}")
 
 
 def test_config_32x64_batched():

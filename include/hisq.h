@@ -187,6 +187,26 @@ hisq_status hisq_dslash_xpay(void *out, const void *in, const hisq_gauge *g, int
 hisq_status hisq_normal_op(void *out, const void *in, void *tmp, const hisq_gauge *g,
                            double mass, double shift, hisq_fmt fmt, void *stream);
 
+/* hisq_normal_op for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operator without the tmp argument.  The odd-parity intermediate
+ * D_oe in is kept in a library-owned device array of
+ * HISQ_NOALLOC_SCRATCH_BYTES, which each device holds from the loading of the
+ * library's device code until the process ends.  The call allocates nothing
+ * (no hipMalloc/hipFree, no host memory), never runs the autotuner (launch
+ * shapes already chosen by an earlier call, hisq_tune_set or hisq_tune_load,
+ * else the default shapes) and reads no tune cache file.  Requires
+ * hisq_spinor_bytes(Vh, fmt.spinor) <= HISQ_NOALLOC_SCRATCH_BYTES, which every
+ * format of at most 24 B/site meets up to 48^3x96; HISQ_EINVAL otherwise,
+ * before any device work.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (other streams, other
+ * threads) race and give wrong results, so serialise them.  Results equal
+ * those of hisq_normal_op with the same launch shapes.  out, in: as for
+ * hisq_normal_op (out must not alias in). */
+#define HISQ_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+hisq_status hisq_normal_op_noalloc(void *out, const void *in, const hisq_gauge *g, double mass, double shift,
+                                   hisq_fmt fmt, void *stream);
+
 /* Batched Dslash (block of right-hand sides, Sec. 1 "Block solvers"): nrhs
  * consecutive packed fields in `in` and `out` (each hisq_spinor_bytes(Vh))
  * share one pass over the links.  1 <= nrhs <= 16.  Every triplet but

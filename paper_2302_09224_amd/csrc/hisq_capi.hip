@@ -351,3 +351,58 @@ extern "C" hisq_status hisq_dslash_batched(void *out, const void *in, const hisq
     HISQ_TRY_HIP(launch_dslash(a, fmt, plan, (hipStream_t)stream, nullptr));
     return HISQ_OK;
 }
+
+// ---------------------------------------------------------------------------
+// The normal operator without allocation.  Its odd-parity intermediate lives
+// in `scratch`, a file-scope device array that every device holds from the
+// loading of this code object until the process ends.  In host code the name
+// `scratch` is only a host-side stand-in: its device address on the current
+// device is looked up once per device and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) char scratch[HISQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_dev_mu;
+void *g_scratch_dev[64];   // address of `scratch` on device d, nullptr until looked up
+
+hisq_status noalloc_scratch(void **ptr) {
+    int d = 0;
+    HISQ_TRY_HIP(hipGetDevice(&d));
+    if (d < 0 || d >= 64) return set_error(HISQ_EINVAL, "device index %d out of range", d);
+    std::lock_guard<std::mutex> lk(g_scratch_dev_mu);
+    if (!g_scratch_dev[d]) {
+        void *p = nullptr;
+        HISQ_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(HISQ_EHIP, "hisq_normal_op_noalloc: no device address for the scratch array");
+        g_scratch_dev[d] = p;
+    }
+    *ptr = g_scratch_dev[d];
+    return HISQ_OK;
+}
+
+}  // namespace
+
+extern "C" hisq_status hisq_normal_op_noalloc(void *out, const void *in, const hisq_gauge *g, double mass,
+                                              double shift, hisq_fmt fmt, void *stream) {
+    HISQ_TRY(dslash_common(out, in, g, 0, fmt, "hisq_normal_op_noalloc"));
+    const Geom geo = make_geom(g->dims);
+    const size_t need = spinor_field_bytes((size_t)geo.vh, fmt.spinor);
+    if (need > HISQ_NOALLOC_SCRATCH_BYTES)
+        return set_error(HISQ_EINVAL,
+                         "hisq_normal_op_noalloc: the odd-parity intermediate needs %zu bytes, more than the "
+                         "%zu-byte scratch array (use hisq_normal_op with a tmp field)",
+                         need, (size_t)HISQ_NOALLOC_SCRATCH_BYTES);
+    void *tmp = nullptr;
+    HISQ_TRY(noalloc_scratch(&tmp));
+    DslashArgs d1 = base_args(g, tmp, in, 1);
+    const DslashPlan plan = dslash_plan_lookup(fmt, geo, 1, d1.long_recon);
+    HISQ_TRY_HIP(launch_dslash(d1, fmt, plan, (hipStream_t)stream, nullptr));
+    DslashArgs d2 = base_args(g, out, tmp, 0);
+    d2.b = -1.0;
+    d2.x = (const char *)in;
+    d2.a = 4.0 * mass * mass + shift;
+    HISQ_TRY_HIP(launch_dslash(d2, fmt, plan, (hipStream_t)stream, nullptr));
+    return HISQ_OK;
+}

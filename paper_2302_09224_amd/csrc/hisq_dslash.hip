@@ -328,6 +328,23 @@ DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashA
     return plan;
 }
 
+DslashPlan dslash_plan_lookup(const hisq_fmt &f, const Geom &g, int nrhs, int long_recon) {
+    DslashPlan plan;
+    int c = 1;
+    while (c < nrhs && c < 16) c <<= 1;
+    plan.n = 1;
+    plan.rhs0[0] = 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int red = 0; red < 2; red++) {
+        const TuneKey key{tune_id(f, long_recon), g.X, g.Y, g.Z, g.T, c, red};
+        auto it = g_tuned.find(key);
+        const DslashTile t = it != g_tuned.end() ? it->second.first : default_tile(c);
+        if (red) plan.tile_red[0] = c > 1 ? t : plan.tile[0];
+        else plan.tile[0] = t;
+    }
+    return plan;
+}
+
 hipError_t launch_dslash_multi(const MultiArgs &m, const hisq_fmt &f, int long_recon, hipStream_t st) {
     switch (triplet_key(f)) {
     case GF_F64 * 100 + SF_F64 * 10 + 1: return dslash_multi_double(m, long_recon, st);

@@ -135,6 +135,9 @@ inline int dslash_tile_blocks(int vh, const DslashTile &t) {
 size_t dslash_max_blocks(int vh);
 // plan (autotuned on first use when a probe is given and the stream is not capturing)
 DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st);
+// the plan from the shapes already in the table (tuned, fixed or loaded), else
+// the default shapes: never tunes, reads no file, allocates nothing
+DslashPlan dslash_plan_lookup(const hisq_fmt &f, const Geom &g, int nrhs, int long_recon);
 // launch a plan; nblocks[j] receives the block count used for right-hand side j
 hipError_t launch_dslash(const DslashArgs &a, const hisq_fmt &f, const DslashPlan &plan, hipStream_t st,
                          int *nblocks);

@@ -138,6 +138,7 @@ def load():
         "hisq_dslash": (i, [vp, vp, G, i, hisq_fmt, vp]),
         "hisq_dslash_xpay": (i, [vp, vp, G, i, hisq_fmt, d, vp, d, vp]),
         "hisq_normal_op": (i, [vp, vp, vp, G, d, d, hisq_fmt, vp]),
+        "hisq_normal_op_noalloc": (i, [vp, vp, G, d, d, hisq_fmt, vp]),
         "hisq_dslash_batched": (i, [vp, vp, G, i, hisq_fmt, i, vp]),
         "hisq_dslash_multi": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(G), i, hisq_fmt, vp]),
         "hisq_solver_params_default": (None, [P]),
@@ -253,6 +254,11 @@ def hisq_dslash_xpay(out, inp, gauge, parity, f, a, x, b, stream=None):
 def hisq_normal_op(out, inp, tmp, gauge, mass, shift, f, stream=None):
     _check(load().hisq_normal_op(_ptr(out), _ptr(inp), _ptr(tmp), ctypes.byref(gauge), float(mass), float(shift), f,
                                  _stream(stream)), "hisq_normal_op")
+
+
+def hisq_normal_op_noalloc(out, inp, gauge, mass, shift, f, stream=None):
+    _check(load().hisq_normal_op_noalloc(_ptr(out), _ptr(inp), ctypes.byref(gauge), float(mass), float(shift), f,
+                                         _stream(stream)), "hisq_normal_op_noalloc")
 
 
 def hisq_dslash_multi(outs, ins, gauges, parity, f, stream=None):

@@ -190,6 +190,25 @@ def test_tune_cache_needs_a_device(hisq, tmp_path):
     assert hisq.load().hisq_tune_load(None, None) == -1
 
 
+def test_noalloc_rejects_oversize_before_device_work(hisq):
+    """the allocation-free normal operator refuses a lattice whose odd-parity
+    intermediate exceeds its scratch array, before any device call (the
+    pointers here are never dereferenced)"""
+    import ctypes
+    lib = hisq.load()
+    g = hisq.hisq_gauge()
+    for k, v in enumerate((48, 48, 48, 96)):          # F64 intermediate: 255 MB > 128 MiB
+        g.dims[k] = v
+    g.fmt, g.fat, g.lng, g.fat_max, g.long_max, g.long_recon, g.long_coeff = hisq.GAUGE_F64, 4096, 8192, 1, 1, 18, 1
+    st = lib.hisq_normal_op_noalloc(ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.byref(g), 0.1, 0.0,
+                                    hisq.fmt("double"), None)
+    assert st == -1 and "scratch" in hisq.hisq_last_error()
+    g.dims[3] = 48                                     # 127 MB: within the array, but unaligned pointers
+    st = lib.hisq_normal_op_noalloc(ctypes.c_void_p((1 << 20) + 8), ctypes.c_void_p(2 << 20), ctypes.byref(g), 0.1,
+                                    0.0, hisq.fmt("double"), None)
+    assert st == -2
+
+
 def test_workspace_too_small_is_reported_before_any_device_work(hisq):
     """every solver checks its workspace before touching the device (pointers
     here are never dereferenced)"""

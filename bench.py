@@ -307,6 +307,85 @@ def bench_formats(hisq, inputs, torch, dev, reps, dims=(32, 32, 32, 32), mass=0.
     return dict(lattice=list(dims), mass=mass, tol=tol, triplets=out)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(np, dims, fat, lng, b, shifts, tols, mass, kernels, fp64_iters, gpu_seconds):
+    """The FP64 oracle on the host cores, on bounded samples of the benchmark's
+    own lattice and fields (about 25 s in all):
+    * its Dslash at 2^20 random output sites, repeated for ~6 s, with all the
+      threads the oracle uses, and at 2^16 sites for ~3 s on one thread;
+    * its FP64 multi-shift CG of the same 12-shift system for one and for two
+      iterations (final residuals skipped), the difference being the time of
+      one iteration; times the FP64 multi-shift's iteration count on the GPU
+      (the same algorithm) it gives the oracle's extrapolated time to solution."""
+    import oracle
+    olib = oracle.load()
+    nthr = oracle.threads(olib)
+    log(f"[bench] CPU oracle baseline ({nthr} threads, {cpu_model()})")
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    fat_h = fat.cpu().numpy()
+    lng_h = lng.cpu().numpy()
+    i = np.arange(V)
+    par = ((i % dims[0]) + (i // dims[0]) % dims[1] + (i // (dims[0] * dims[1])) % dims[2]
+           + i // (dims[0] * dims[1] * dims[2])) % 2
+    odd, even = np.nonzero(par == 1)[0], np.nonzero(par == 0)[0]
+    full = np.zeros((V, 3), dtype=np.complex128)
+    full[odd] = b.cpu().numpy()
+    rng = np.random.default_rng(0)
+
+    def dslash_rate(nsites, seconds):
+        sample = np.sort(rng.choice(even, size=min(even.size, nsites), replace=False))
+        done, tc = 0, 0.0
+        while tc < seconds:
+            t2 = time.perf_counter()
+            oracle.dslash_sites(fat_h, lng_h, full, dims, sample, lib=olib)
+            tc += time.perf_counter() - t2
+            done += sample.size
+        return done * (16 * 144 + 2 * 48) / tc / 1e9, sample.size, done // sample.size, tc
+
+    gbs, n_s, reps, tc = dslash_rate(1 << 20, 6.0)
+    oracle.set_threads(1, olib)
+    try:
+        gbs1, n_s1, reps1, tc1 = dslash_rate(1 << 16, 3.0)
+    finally:
+        oracle.set_threads(nthr, olib)
+    log(f"[bench]   oracle Dslash {gbs:.2f} GB/s on {nthr} threads, {gbs1:.2f} GB/s on 1 thread")
+    # one iteration of the oracle's FP64 multi-shift CG on the whole lattice
+    bfull = np.zeros((V, 3), dtype=np.complex128)
+    bfull[even] = full[odd]
+    tms = []
+    for k in (1, 2):
+        t2 = time.perf_counter()
+        oracle.multishift_cg(fat_h, lng_h, bfull, dims, mass, shifts, tols, maxiter=k, lib=olib, residuals=False)
+        tms.append(time.perf_counter() - t2)
+    t_iter = tms[1] - tms[0]
+    extrap = t_iter * fp64_iters if fp64_iters else None
+    log(f"[bench]   oracle multi-shift: {t_iter:.2f} s per iteration"
+        + (f", x {fp64_iters} iterations = {extrap:.0f} s (extrapolated)" if extrap else ""))
+    del fat_h, lng_h, full, bfull
+    return dict(value=round(gbs, 3), unit="GB/s", cores=nthr, kind="oracle", cpu_model=cpu_model(),
+                sample=f"FP64 oracle Dslash at {n_s} random even sites of the {dims} lattice, repeated {reps}x "
+                       f"({tc:.1f}s); algorithmic bytes 2400/site",
+                value_1thread=round(gbs1, 3),
+                sample_1thread=f"{n_s1} random even sites, repeated {reps1}x ({tc1:.1f}s), one thread",
+                vs_gpu_fp64_dslash=round(kernels["double"]["gbs"] / gbs, 1),
+                multishift_seconds_per_iteration=round(t_iter, 3),
+                multishift_iterations=fp64_iters,
+                multishift_seconds_extrapolated=round(extrap, 1) if extrap else None,
+                multishift_sample=("oracle FP64 multi-shift CG of the same 12-shift system: 2 minus 1 iterations "
+                                   "timed (final residuals skipped), times the FP64 multi-shift iteration count "
+                                   "(extrapolated; the oracle's vector updates are single-threaded)"),
+                vs_gpu_mixed_solve=round(extrap / gpu_seconds, 1) if extrap else None)
+
+
 def _pack_like(hisq, inputs, dims, gf, dev, kind):
     fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
     return hisq.pack_gauge(fat, lng, dims, gf, long_recon=12)
@@ -558,34 +637,8 @@ def main():
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
-        import oracle
-        olib = oracle.load()
-        nthr = oracle.threads(olib)
-        log(f"[bench] CPU oracle baseline ({nthr} threads)")
-        # bounded sample: the oracle's FP64 Dslash at a fixed random sample of
-        # output sites of the same lattice and fields, repeated for ~10 s
-        fat_h = fat.cpu().numpy()
-        lng_h = lng.cpu().numpy()
-        full = np.zeros((V, 3), dtype=np.complex128)
-        odd = np.nonzero(((np.arange(V) % dims[0]) + (np.arange(V) // dims[0]) % dims[1]
-                          + (np.arange(V) // (dims[0] * dims[1])) % dims[2]
-                          + np.arange(V) // (dims[0] * dims[1] * dims[2])) % 2 == 1)[0]
-        full[odd] = b.cpu().numpy()
-        rng = np.random.default_rng(0)
-        even = np.setdiff1d(np.arange(V), odd, assume_unique=True)
-        sample = np.sort(rng.choice(even, size=min(even.size, 1 << 20), replace=False))
-        done_sites, tc = 0, 0.0
-        while tc < 10.0:
-            t2 = time.perf_counter()
-            oracle.dslash_sites(fat_h, lng_h, full, dims, sample, lib=olib)
-            tc += time.perf_counter() - t2
-            done_sites += sample.size
-        gbs_cpu = done_sites * (16 * 144 + 2 * 48) / tc / 1e9
-        cpu = dict(value=round(gbs_cpu, 3), unit="GB/s", cores=nthr, kind="oracle",
-                   sample=f"FP64 oracle Dslash at {sample.size} random even sites of the {dims} lattice, "
-                          f"repeated {done_sites // sample.size}x ({tc:.1f}s); algorithmic bytes 2400/site",
-                   vs_gpu_fp64_dslash=round(kernels["double"]["gbs"] / gbs_cpu, 1))
-        del fat_h, lng_h, full
+        cpu = cpu_baseline(np, dims, fat, lng, b, shifts, tols, args.mass, kernels,
+                           fp64["iters"] if fp64 else None, ms_per_step / 1e3)
 
     line = {
         "metric": "HISQ Dslash GB/s (% HBM peak); multi-shift CG s to 1e-10 vs FP64 CG",

@@ -55,6 +55,8 @@ def _declare(lib):
     lib.hisq_oracle_multishift_cg.restype = ctypes.c_int
     lib.hisq_oracle_threads.argtypes = []
     lib.hisq_oracle_threads.restype = ctypes.c_int
+    lib.hisq_oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.hisq_oracle_set_threads.restype = None
     for name in ("half16_encode",):
         getattr(lib, "hisq_oracle_" + name).argtypes = [vp, vp, vp, ctypes.c_long]
     lib.hisq_oracle_half16_decode.argtypes = [vp, vp, vp, ctypes.c_long]
@@ -134,6 +136,11 @@ def threads(lib=None):
     return (lib or load()).hisq_oracle_threads()
 
 
+def set_threads(n, lib=None):
+    """use n OpenMP threads in the oracle's site loops from now on"""
+    (lib or load()).hisq_oracle_set_threads(int(n))
+
+
 def dslash(fat, lng, psi, dims, parity=-1, out=None, lib=None):
     """(D psi) on the sites of `parity` (all sites for -1); other sites of
     `out` are left as they were (zeros for a fresh output)."""
@@ -201,8 +208,9 @@ def cg(fat, lng, b, dims, mass, shift=0.0, tol=1e-10, maxiter=100000, x0=None, p
     return x, it.value, res.value, st
 
 
-def multishift_cg(fat, lng, b, dims, mass, shifts, tol, maxiter=100000, parity=0, lib=None):
-    """FP64 multi-shift CG; returns dict(x=[...], iters, resid, zeta, r, status)"""
+def multishift_cg(fat, lng, b, dims, mass, shifts, tol, maxiter=100000, parity=0, lib=None, residuals=True):
+    """FP64 multi-shift CG; returns dict(x=[...], iters, resid, zeta, r, status)
+    (residuals=False: the final true residuals are not computed, resid is zero)"""
     lib = lib or load()
     fat = _arr(fat, np.complex128)
     lng = _arr(lng, np.complex128)
@@ -218,7 +226,8 @@ def multishift_cg(fat, lng, b, dims, mass, shifts, tol, maxiter=100000, parity=0
     r = np.zeros_like(b)
     st = lib.hisq_oracle_multishift_cg(ctypes.cast(xp, ctypes.c_void_p), _ptr(b), _ptr(fat), _ptr(lng),
                                        _dims(dims), int(parity), float(mass), _ptr(shifts), n, _ptr(tol),
-                                       int(maxiter), _ptr(iters), _ptr(resid), _ptr(zeta), _ptr(r))
+                                       int(maxiter), _ptr(iters), _ptr(resid) if residuals else None, _ptr(zeta),
+                                       _ptr(r))
     return dict(x=xs, iters=iters, resid=resid, zeta=zeta, r=r, status=st)
 
 
@@ -651,13 +660,83 @@ def long_recon_roundtrip(lng, dims, fmt, compute_bits, lib=None):
     return c * long_phases(dims)[..., None, None] * full
 
 
+def su3_eight_params(u):
+    """special unitary u [..., 3, 3] -> its eight stored reals [..., 8]:
+    Re/Im of u[0,1], u[0,2] and u[1,0], then tan(arg(u[0,0])/4) and
+    tan(arg(u[2,0])/4) (each in [-1, 1] for an argument in [-pi, pi])"""
+    u = np.asarray(u, dtype=np.complex128)
+    p = np.empty(u.shape[:-2] + (8,))
+    for k, z in enumerate((u[..., 0, 1], u[..., 0, 2], u[..., 1, 0])):
+        p[..., 2 * k], p[..., 2 * k + 1] = z.real, z.imag
+    p[..., 6] = np.tan(np.angle(u[..., 0, 0]) / 4)
+    p[..., 7] = np.tan(np.angle(u[..., 2, 0]) / 4)
+    return p
+
+
+def su3_from_eight(p):
+    """the special unitary matrix with the given eight parameters (Sec. 1,
+    "Compression": 8 of the 18 reals fix a special unitary matrix).  Row 1
+    has unit norm, which fixes |u00|; column 1 has unit norm, which fixes
+    |u20|; their phases are e^{i theta} with tan(theta/4) = v.  The rest of
+    row 2 follows from two linear conditions, orthogonality to row 1 and
+    u20 = conj(u01 u12 - u02 u11) (row 3 = conj(row 1 x row 2)), solved as a
+    2x2 linear system; row 3 is then that cross product."""
+    p = np.asarray(p, dtype=np.float64)
+    shape = p.shape[:-1]
+    p = p.reshape(-1, 8)
+    a2, a3, b1 = p[:, 0] + 1j * p[:, 1], p[:, 2] + 1j * p[:, 3], p[:, 4] + 1j * p[:, 5]
+
+    def unit(v):                       # e^{i theta}, v = tan(theta/4): e^{i theta/2} = (1 + iv)^2 / (1 + v^2)
+        h = (1 + 1j * v) ** 2 / (1 + v * v)
+        return h * h
+    a1 = np.sqrt(np.maximum(1 - np.abs(a2) ** 2 - np.abs(a3) ** 2, 0.0)) * unit(p[:, 6])
+    c1 = np.sqrt(np.maximum(1 - np.abs(a1) ** 2 - np.abs(b1) ** 2, 0.0)) * unit(p[:, 7])
+    # [conj(a2) conj(a3); -a3 a2] (b2, b3) = (-conj(a1) b1, conj(c1))
+    m = np.empty((p.shape[0], 2, 2), dtype=np.complex128)
+    m[:, 0, 0], m[:, 0, 1], m[:, 1, 0], m[:, 1, 1] = np.conj(a2), np.conj(a3), -a3, a2
+    rhs = np.stack([-np.conj(a1) * b1, np.conj(c1)], axis=-1)
+    b23 = np.linalg.solve(m, rhs[..., None])[..., 0]
+    row1 = np.stack([a1, a2, a3], axis=-1)
+    row2 = np.stack([b1, b23[:, 0], b23[:, 1]], axis=-1)
+    row3 = np.conj(np.cross(row1, row2))
+    return np.stack([row1, row2, row3], axis=-2).reshape(shape + (3, 3))
+
+
+def long_recon8_roundtrip(lng, dims, fmt, compute_bits, lib=None):
+    """long links as a Dslash sees them when U is stored as its eight
+    parameters (su3_eight_params) in `fmt` and rebuilt (su3_from_eight, FP64
+    here: the kernel's own rounding of the rebuild is covered by the compute
+    precision's tolerance).  Fixed point: the six entries scaled by the max
+    |real component| of the whole of U, the two phase parameters by 1."""
+    c, u = long_link_split(lng, dims)
+    p = su3_eight_params(u)
+    if fmt in ("fix16", "fix32"):
+        bits = 16 if fmt == "fix16" else 32
+        scale = max(np.abs(u.real).max(), np.abs(u.imag).max())
+        # the real pairs as complex numbers: (a2, a3, b1) and (v_a + i v_c)
+        z = np.ascontiguousarray(p).view(np.complex128)
+        q, _ = fix_encode(z[..., :3], bits, absmax=scale, lib=lib)
+        qv, _ = fix_encode(z[..., 3], bits, absmax=1.0, lib=lib)
+        z = np.concatenate([fix_decode(q, scale, compute_bits, shape=z[..., :3].shape, lib=lib),
+                            fix_decode(qv, 1.0, compute_bits, shape=z[..., 3].shape, lib=lib)[..., None]], axis=-1)
+        p = z.view(np.float64)
+    elif fmt == "f32" or compute_bits == 32:
+        p = p.astype(np.float32).astype(np.float64)
+    elif fmt != "f64":
+        raise ValueError(f"eight-parameter long links in {fmt}")
+    return c * long_phases(dims)[..., None, None] * su3_from_eight(p)
+
+
 def emulated_dslash(fat, lng, psi, dims, parity, gauge_fmt, spinor_fmt, compute_bits, lib=None, long_recon=18):
     """FP64 Dslash of the inputs as the storage formats hold them (links and
     spinor after a round trip), before the output is stored.  long_recon=12:
-    the long links kept as two rows (long_recon_roundtrip)."""
+    the long links kept as two rows (long_recon_roundtrip); 8: as eight
+    parameters (long_recon8_roundtrip)."""
     f = gauge_roundtrip(fat, gauge_fmt, compute_bits, lib)
     if long_recon == 12:
         l = long_recon_roundtrip(lng, dims, gauge_fmt, compute_bits, lib)
+    elif long_recon == 8:
+        l = long_recon8_roundtrip(lng, dims, gauge_fmt, compute_bits, lib)
     else:
         l = gauge_roundtrip(lng, gauge_fmt, compute_bits, lib)
     p = spinor_roundtrip(psi, spinor_fmt, lib)

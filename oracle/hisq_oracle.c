@@ -83,6 +83,12 @@ int hisq_oracle_threads(void)
     return n;
 }
 
+/* set the number of threads of the site loops (n >= 1) */
+void hisq_oracle_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
 /* link matrix of direction mu at site i: row-major 3x3 */
 static const cplx *link(const cplx *field, int mu, long i, long V)
 {

@@ -84,3 +84,68 @@ def test_recon_dslash_equals_full_dslash():
     a = oracle.emulated_dslash(fat.numpy(), lng.numpy(), psi, dims, 0, "fix16", "f64", 64, long_recon=12)
     b = oracle.emulated_dslash(fat.numpy(), lng.numpy(), psi, dims, 0, "fix16", "f64", 64)
     assert 0 < np.abs(a - b).max() < 1e-4 * np.abs(b).max()
+
+
+# ---------------------------------------------------------------------------
+# eight-parameter storage
+# ---------------------------------------------------------------------------
+
+def test_eight_params_rebuild_random_su3():
+    """parameters taken from random special unitary matrices rebuild them:
+    Haar (rough) and near-unit ones, to within FP64 rounding amplified by the
+    conditioning, 1/min(N, |u20|^2) with N = |u01|^2 + |u02|^2 (the 2x2
+    system's determinant) and |u20| the root of a difference of norms"""
+    for u in (inputs.haar_su3(4000, torch.Generator().manual_seed(8)).numpy(),
+              oracle.long_link_split(inputs.make_links((4, 4, 4, 4), "near_unit", seed=19)[1].numpy(),
+                                     (4, 4, 4, 4))[1].reshape(-1, 3, 3)):
+        back = oracle.su3_from_eight(oracle.su3_eight_params(u))
+        n = np.minimum(np.abs(u[:, 0, 1]) ** 2 + np.abs(u[:, 0, 2]) ** 2, np.abs(u[:, 2, 0]) ** 2)
+        err = np.abs(back - u).max(axis=(1, 2))
+        assert (err <= 1e-13 / n).all(), float((err * n).max())
+        assert np.median(err) < 1e-14
+        assert np.abs(np.linalg.det(back) - 1).max() < 1e-12
+
+
+def test_eight_params_closed_forms():
+    """the rotation in the (1,3) plane, a1 = cos(a), a3 = u20 = i sin(a):
+    parameters (0, 0, 0, sin(a), 0, 0, 0, tan(pi/8)) and back; a phase of
+    pi on a1 is v = tan(pi/4) = 1"""
+    a = 0.4
+    w = np.array([[np.cos(a), 0, 1j * np.sin(a)], [0, 1, 0], [1j * np.sin(a), 0, np.cos(a)]], dtype=np.complex128)
+    assert abs(np.linalg.det(w) - 1) < 1e-15
+    pw = oracle.su3_eight_params(w)
+    assert np.allclose(pw, [0, 0, 0, np.sin(a), 0, 0, 0, np.tan(np.pi / 8)], atol=1e-16)
+    assert np.abs(oracle.su3_from_eight(pw) - w).max() < 1e-15
+    d = np.diag([-1.0, -1.0, 1.0]).astype(np.complex128) @ w
+    pd = oracle.su3_eight_params(d)
+    assert pd[6] == pytest.approx(1.0, abs=1e-15)
+    assert np.abs(oracle.su3_from_eight(pd) - d).max() < 1e-15
+
+
+def test_eight_params_degenerate_column():
+    """u20 = 0: |u20| is the root of a difference of norms that rounding
+    leaves at about 1e-16, so the rebuild is only good to about sqrt(eps)
+    there (the known weak point of eight-parameter storage)"""
+    a = 0.4
+    u = np.array([[np.cos(a), np.sin(a), 0], [-np.sin(a), np.cos(a), 0], [0, 0, 1]], dtype=np.complex128)
+    p = oracle.su3_eight_params(u)
+    assert np.allclose(p, [np.sin(a), 0, 0, 0, -np.sin(a), 0, 0, 0], atol=1e-16)
+    err = np.abs(oracle.su3_from_eight(p) - u).max()
+    assert err < 4 * np.sqrt(np.finfo(float).eps), err
+
+
+def test_eight_param_long_links_round_trip():
+    """FP64 storage of the eight parameters gives the long links back; fixed
+    point stays within the stored quantum amplified by 1/N (measured)"""
+    dims = (4, 4, 4, 6)
+    _, lng = inputs.make_links(dims, "near_unit", seed=23)
+    lng = lng.numpy()
+    back = oracle.long_recon8_roundtrip(lng, dims, "f64", 64)
+    _, u = oracle.long_link_split(lng, dims)
+    n = np.minimum(np.abs(u[..., 0, 1]) ** 2 + np.abs(u[..., 0, 2]) ** 2, np.abs(u[..., 2, 0]) ** 2)[..., None, None]
+    assert (np.abs(back - lng) <= 1e-13 / n).all()
+    for fmt, q in (("fix32", 2.0 ** -31), ("fix16", 2.0 ** -15)):
+        back = oracle.long_recon8_roundtrip(lng, dims, fmt, 64)
+        rel = np.abs(back - lng) / (np.abs(lng).max())
+        assert (rel <= 64 * q / n).all(), fmt
+        assert np.median(rel) <= 4 * q, fmt

@@ -6,8 +6,9 @@ solved to a 1e-10 true relative residual.  A step packs the FP64 links (already
 resident in HBM) into the solver's storage formats and runs the multi-shift
 solve: multi-shift phase in 32-bit links / 30-bit fermions / FP64 compute with
 FP64 reliable updates, then CG refinement in 16-bit links / 20-bit fermions /
-FP32 compute (the paper's improved variant, Sec. 6.2).  The low-precision
-operators keep the long links as two rows of an SU(3) matrix (--recon 12).
+FP32 compute (the paper's improved variant, Sec. 6.2).  The multi-shift
+operator keeps each long link as the eight parameters of its SU(3) matrix
+(--ms-recon 8), the refinement and FP64 operators as two rows (--recon 12).
 
 Printed (one JSON line): whole-step algorithmic HBM GB/s (value), the
 per-triplet Dslash GB/s and GFLOP/s measured with HIP events (the Fig. 3
@@ -65,18 +66,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, reps=10):
-    """Block of 16 right-hand sides (one link load per site for the block)
-    against 16 single-right-hand-side applications, 32^3x64."""
+def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, reps=10,
+                  names=("half", "int20", "single"), recon=18):
+    """Block of nrhs right-hand sides (one link load per site for the block)
+    against nrhs single-right-hand-side applications (default 16 on 32^3x64)."""
     V = dims[0] * dims[1] * dims[2] * dims[3]
     vh = V // 2
     fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 4, device=dev)
     srcs = inputs.gaussian_spinor(vh, inputs.RHS_SEED, device=dev, nrhs=nrhs)
     out = {}
     stream = torch.cuda.current_stream()
-    for name in ("half", "int20", "single"):
+    for name in names:
         f = hisq.fmt(name)
-        pg = hisq.pack_gauge(fat, lng, dims, f.gauge)
+        pg = hisq.pack_gauge(fat, lng, dims, f.gauge, long_recon=recon)
         nb = hisq.hisq_spinor_bytes(vh, f.spinor)
         pin = torch.cat([hisq.pack_spinor(srcs[j], f.spinor)[:nb] for j in range(nrhs)]).contiguous()
         pout = torch.empty_like(pin)
@@ -98,8 +100,10 @@ def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16
         e1.record(stream)
         torch.cuda.synchronize()
         ts = e0.elapsed_time(e1) / (reps * 4) * nrhs
-        nbytes = vh * (16 * hisq.GAUGE_BYTES[f.gauge] + nrhs * 2 * hisq.SPINOR_BYTES[f.spinor])
-        out[name] = dict(dims=list(dims), nrhs=nrhs, us_batched=round(tb * 1e3, 1), us_16_single=round(ts * 1e3, 1),
+        nbytes = vh * (8 * hisq.GAUGE_BYTES[f.gauge] + 8 * long_link_bytes(hisq, f.gauge, recon)
+                       + nrhs * 2 * hisq.SPINOR_BYTES[f.spinor])
+        out[name] = dict(dims=list(dims), nrhs=nrhs, long_recon=recon, us_batched=round(tb * 1e3, 1),
+                         us_single_x_nrhs=round(ts * 1e3, 1),
                          speedup=round(ts / tb, 2), gbs=round(nbytes / tb / 1e6, 1),
                          gflops=round(nrhs * FLOP_PER_SITE * vh / tb / 1e6, 1))
         log(f"[bench] batched {name:6s} {out[name]}")
@@ -307,6 +311,13 @@ def bench_formats(hisq, inputs, torch, dev, reps, dims=(32, 32, 32, 32), mass=0.
     return dict(lattice=list(dims), mass=mass, tol=tol, triplets=out)
 
 
+def long_link_bytes(hisq, gf, recon):
+    """bytes of one stored long link: 18 reals, two rows, or eight parameters"""
+    if recon == 8:
+        return {hisq.GAUGE_F64: 64, hisq.GAUGE_FIX32: 32}[gf]
+    return hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12 else hisq.GAUGE_BYTES[gf]
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -403,9 +414,12 @@ def main():
     ap.add_argument("--ms", type=str, default="int30")
     ap.add_argument("--ref", type=str, default="int20")
     ap.add_argument("--recon", type=int, default=12, choices=(12, 18),
-                    help="long-link storage of the solver's low-precision operators (12: two rows)")
-    ap.add_argument("--batch-refine", type=int, default=1, choices=(0, 1),
-                    help="refine the shifted systems together (1) or one after another (0)")
+                    help="long-link storage of the solver's operators (12: two rows)")
+    ap.add_argument("--ms-recon", type=int, default=8, choices=(8, 12, 18),
+                    help="long-link storage of the multi-shift operator (8: eight parameters)")
+    ap.add_argument("--batch-refine", type=int, default=1, choices=(0, 1, 2),
+                    help="refine the shifted systems together (1), together while the base is refined "
+                         "concurrently (2), or one after another (0)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the 16^4 CG-stability table (not part of the timed step)")
@@ -421,10 +435,15 @@ def main():
                     help="per-triplet Dslash GB/s and mixed CG iterations/time on 32^4, m = 0.01")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
+    ap.add_argument("--kernel", type=str, default=None,
+                    help="only these rows of the Dslash table (comma-separated keys, e.g. int30_r8)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--batched", action="store_true",
                     help="also time the 16-right-hand-side Dslash on 32^3x64 against 16 single applications")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched FIX16/INT20 Dslash with two-row long links: 16 right-hand sides on "
+                         "32^3x64 and 11 (a block of 16) on 48^3x96, as the refinement runs it (for counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -453,6 +472,14 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
 
+    if args.batched_only:
+        res = [bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, names=("int20",),
+                             recon=12),
+               bench_batched(args, hisq, inputs, torch, dev, dims=(48, 48, 48, 96), nrhs=11, names=("int20",),
+                             recon=12)]
+        print(json.dumps(dict(batched=res, tuning=hisq.hisq_tune_report().strip().splitlines())))
+        return
+
     t0 = time.time()
     log(f"[bench] generating near-unit links on {dims} (seed {inputs.GAUGE_SEED + 3})")
     fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 3, device=dev)
@@ -473,13 +500,16 @@ def main():
         return gauges[(gf, recon)]
 
     def link_bytes(gf, recon):
-        return 8 * hisq.GAUGE_BYTES[gf] + 8 * (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12 else hisq.GAUGE_BYTES[gf])
+        return 8 * hisq.GAUGE_BYTES[gf] + 8 * long_link_bytes(hisq, gf, recon)
 
     stream = torch.cuda.current_stream()
     names = ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30")
-    table = [(n, 18) for n in names] + [(n, 12) for n in names]
+    table = [(n, 18) for n in names] + [(n, 12) for n in names] + [("double", 8), ("int30", 8)]
+    if args.kernel:
+        want = set(args.kernel.split(","))
+        table = [(n, r) for n, r in table if (n if r == 18 else f"{n}_r{r}") in want]
     for name, recon in table:
-        key = name if recon == 18 else f"{name}_r12"
+        key = name if recon == 18 else f"{name}_r{recon}"
         f = hisq.fmt(name)
         pg = gauge(f.gauge, recon)
         pin = hisq.pack_spinor(b, f.spinor)
@@ -520,19 +550,23 @@ def main():
     torch.cuda.empty_cache()
 
     # ---------------- the timed step ----------------
-    def solve_once(ms, ref, **kw):
-        """pack the links the solve needs (FP64 + its two triplets) and run it"""
+    ms_recon = args.ms_recon if hisq.fmt(args.ms).compute == 64 else args.recon   # eight parameters: FP64 only
+
+    def solve_once(ms, ref, ms_long=None, **kw):
+        """pack the links the solve needs (FP64 + its two triplets) and run it;
+        ms_long: long-link storage of the multi-shift operator (default --recon)"""
         f_ms, f_ref = hisq.fmt(ms), hisq.fmt(ref)
         # the FP64 operator of the reliable updates and true residuals: FP64 links, the
         # long ones as two rows when --recon 12 (rebuilt to within FP64 rounding)
         g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64, long_recon=args.recon)
-        gms = hisq.pack_gauge(fat, lng, dims, f_ms.gauge, long_recon=args.recon)
-        gref = gms if f_ref.gauge == f_ms.gauge else hisq.pack_gauge(fat, lng, dims, f_ref.gauge,
-                                                                     long_recon=args.recon)
+        rms = ms_long or args.recon
+        gms = hisq.pack_gauge(fat, lng, dims, f_ms.gauge, long_recon=rms)
+        gref = gms if (f_ref.gauge == f_ms.gauge and rms == args.recon) else hisq.pack_gauge(
+            fat, lng, dims, f_ref.gauge, long_recon=args.recon)
         return hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=ms, ref_fmt=ref, **kw)
 
     def step():
-        return solve_once(args.ms, args.ref, batch_refine=args.batch_refine)
+        return solve_once(args.ms, args.ref, ms_long=ms_recon, batch_refine=args.batch_refine)
 
     def timed_once(ms, ref, **kw):
         """one warm-up solve (launch shapes of new keys are tuned there), then one timed"""
@@ -569,10 +603,10 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
-        return 4 * V * (2 * 144 + hisq.GAUGE_BYTES[gf] + (hisq.GAUGE_BYTES[gf] * 2 // 3 if recon == 12
-                                                           else hisq.GAUGE_BYTES[gf]))
-    pack_bytes = pack_field_bytes(hisq.GAUGE_F64, args.recon) + pack_field_bytes(fms.gauge, args.recon)
-    if fref.gauge != fms.gauge:
+        return 4 * V * (2 * 144 + hisq.GAUGE_BYTES[gf] + long_link_bytes(hisq, gf, recon))
+    rms = ms_recon
+    pack_bytes = pack_field_bytes(hisq.GAUGE_F64, args.recon) + pack_field_bytes(fms.gauge, rms)
+    if fref.gauge != fms.gauge or rms != args.recon:
         pack_bytes += pack_field_bytes(fref.gauge, args.recon)
     step_bytes = float(np.mean([s["alg_bytes"] for s in stats])) + pack_bytes
     value = step_bytes / (ms_per_step / 1e3) / 1e9
@@ -625,9 +659,9 @@ def main():
         log(f"[bench]   double-single-half: {ta:.2f}s, ms iters {sa['iters']}, refine {sa['refine_iters']}")
 
     # ---------------- roofline of the dominant kernel ----------------
-    dom = args.ms if args.recon == 18 else f"{args.ms}_r12"
+    dom = args.ms if rms == 18 else f"{args.ms}_r{rms}"
     kd = kernels[dom]
-    traffic = counter_traffic(f"k_dslash<{kd['triplet']}>", dims, args.recon)
+    traffic = counter_traffic(f"k_dslash<{kd['triplet']}>", dims, rms)
     roofline = dict(bound="hbm", achieved=kd["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(kd["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
                     traffic_over_alg=round(traffic / kd["alg_bytes"], 3) if traffic else None,
@@ -656,6 +690,7 @@ def main():
         "config": {"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "lattice": list(dims),
                    "mass": args.mass, "shifts": [float(f"{s:.4g}") for s in shifts], "tol": args.tol,
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
+                   "ms_long_recon": rms,
                    "batch_refine": args.batch_refine,
                    "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],

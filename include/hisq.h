@@ -101,10 +101,12 @@ typedef struct {
     int compute;
 } hisq_fmt;
 
-/* Storage of the long (Naik) links: all 18 reals, or two rows (12 reals) from
- * which the third is rebuilt (Sec. 1, "Compression": special unitary matrices). */
+/* Storage of the long (Naik) links: all 18 reals, two rows (12 reals) from
+ * which the third is rebuilt, or eight parameters (Sec. 1, "Compression":
+ * special unitary matrices have eight real degrees of freedom). */
 #define HISQ_RECON_18 18
 #define HISQ_RECON_12 12
+#define HISQ_RECON_8 8
 
 /* A packed pair of link fields, filled by hisq_gauge_pack / hisq_gauge_pack_recon. */
 typedef struct {
@@ -114,14 +116,15 @@ typedef struct {
     const void *lng;      /* (device) packed three-link (Naik) field */
     double fat_max;       /* global max |real component| of the fat field (fixed-point scale) */
     double long_max;      /* same for the long field (two-row storage: max |component| of U) */
-    int long_recon;       /* HISQ_RECON_18 or HISQ_RECON_12 */
+    int long_recon;       /* HISQ_RECON_18, HISQ_RECON_12 or HISQ_RECON_8 */
     double long_coeff;    /* two-row storage: L_mu(x) = long_coeff * phase_mu(x) * U, U in SU(3) */
 } hisq_gauge;
 
 /* Bytes of ONE packed link field (fat or long): 4*V matrices. */
 size_t hisq_gauge_bytes(const int dims[4], int gauge_fmt);
 
-/* Bytes of the packed long field with HISQ_RECON_18 or HISQ_RECON_12 storage. */
+/* Bytes of the packed long field with HISQ_RECON_18, _12 or _8 storage (0 for
+ * a format that has no such storage). */
 size_t hisq_gauge_long_bytes(const int dims[4], int gauge_fmt, int long_recon);
 
 /* Bytes of one packed single-parity spinor of `nsites` sites (Vh for a field). */
@@ -148,7 +151,23 @@ hisq_status hisq_gauge_pack(hisq_gauge *g, void *fat_dst, void *long_dst,
  * boundary folded in have this form.  The pack step verifies it (relative
  * tolerance: 1e-13 for F64, 1e-7 for F32, 1e-5 for FIX16, 1e-9 for FIX32 storage)
  * and returns HISQ_EINVAL otherwise.  The Dslash rebuilds row 3 = conj(row 1 x
- * row 2) in its compute precision, cutting the long-link traffic by a third. */
+ * row 2) in its compute precision, cutting the long-link traffic by a third.
+ * long_recon == HISQ_RECON_8 (gauge_fmt F64 or FIX32 only, for the triplets
+ * with FP64 arithmetic, F64/F64/64 and FIX32/INT30/64, and one right-hand side
+ * per launch: hisq_dslash, _xpay, hisq_normal_op, the CG, multi-shift and
+ * BiCGStab operators; batched and multi-lattice calls give HISQ_EINVAL): each
+ * link keeps eight parameters of W = sigma * phase * L = lambda * U: Re/Im of
+ * W01, W02, W10, then tan(arg(W00)/4) and tan(arg(W20)/4), each phase
+ * parameter computed by a fixed sequence of correctly rounded operations
+ * (cos = x/|z|, sin = y/|z|; cos >= 0: c2 = sqrt((1+cos)/2), s2 = sin/(2 c2);
+ * else s2 = +-sqrt((1-cos)/2) with the sign of sin, c2 = |sin|/(2|s2|);
+ * result s2/(1+c2)); FIX32 scales the entries by the long field's max |real
+ * component| (long_max) and the phase parameters by 1.  F64: 64 B per link,
+ * FIX32: 32 B (two 16-B planes: W01, W02 | W10, phases).  The Dslash rebuilds
+ * U in FP64: |U00|^2 = 1 - N (N = |U01|^2 + |U02|^2), |U20|^2 = N - |U10|^2,
+ * and the other four entries from the unitarity conditions divided by N, so
+ * links with small N or small |U20| amplify the storage rounding (about 1/N
+ * and 1/|U20|^2). */
 hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void *long_dst,
                                   const double *fat_src, const double *long_src,
                                   const int dims[4], int gauge_fmt, int long_recon, void *stream);
@@ -210,8 +229,8 @@ hisq_status hisq_normal_op_noalloc(void *out, const void *in, const hisq_gauge *
 /* Batched Dslash (block of right-hand sides, Sec. 1 "Block solvers"): nrhs
  * consecutive packed fields in `in` and `out` (each hisq_spinor_bytes(Vh))
  * share one pass over the links.  1 <= nrhs <= 16.  Every triplet but
- * FIX32/INT30/32 (a refinement option only) has this form; that one gives
- * HISQ_EINVAL. */
+ * FIX32/INT30/32 (a refinement option only) has this form; that one, and
+ * links with HISQ_RECON_8 long links, give HISQ_EINVAL. */
 hisq_status hisq_dslash_batched(void *out, const void *in, const hisq_gauge *g, int parity,
                                 hisq_fmt fmt, int nrhs, void *stream);
 
@@ -248,7 +267,10 @@ typedef struct {
                             max(tol_i, shift_floor) (Sec. 3.2: "reach the limit of the sloppy precision");
                             <= 0 selects the sloppy format's epsilon */
     int batch_refine;    /* multi-shift: refine the shifted systems together, one Dslash per iteration shared
-                            by up to 16 of them (1), or one after another (0); the base is always refined first */
+                            by up to 16 of them (1), or one after another (0); the base is refined first.
+                            2: as 1, but the batch runs on a second library stream while a host thread refines
+                            the base concurrently on the first (every launch shape planned beforehand);
+                            phase_seconds[1] and [2] then overlap */
     int ru_estimate;     /* CG and the multi-shift base: 0 = reliable update when |r| drops below delta times its
                             maximum since the last one; 1 = when an estimate of |r_true - r_iterated| (each
                             iteration's sloppy roundoff, accumulated in quadrature: residual replacement in the
@@ -427,7 +449,7 @@ hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size
                             void *long_dst, size_t long_bytes, void *stream);
 
 /* Fix the launch shape of the Dslash for triplet fmt on lattice dims with long
- * links stored as long_recon (HISQ_RECON_18 or HISQ_RECON_12) and a block of
+ * links stored as long_recon (HISQ_RECON_18, _12 or _8; _8 with rhs_block 1) and a block of
  * rhs_block right-hand sides (1, 2, 4, 8 or 16), replacing what the
  * autotuner chose or would choose: nr right-hand sides per lane and rg lanes
  * per site (nr * rg == rhs_block, both powers of two), stage hops per load
@@ -438,7 +460,9 @@ hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size
  * a persistent grid when smaller than the tile count) and sweep, the order in
  * which the blocks take the tiles of lanes (0: the blocks of XCD k, b % 8 ==
  * k, take the k-th eighth of the lattice; 1: consecutive tiles on consecutive
- * blocks, so all XCDs work on neighbouring sites).  For rhs_block > 1 the
+ * blocks, so all XCDs work on neighbouring sites; 2: XCD k owns the z-slab
+ * [Z k/8, Z (k+1)/8) of every time slice and walks it slice by slice in t
+ * order).  For rhs_block > 1 the
  * shape serves both the plain launches and those that fuse a reduction (which
  * the autotuner otherwise tunes apart).  For reproducible launch shapes and
  * for tests.  HISQ_EINVAL for an unsupported shape. */

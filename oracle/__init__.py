@@ -33,7 +33,9 @@ def build(force: bool = True, out: str | None = None, src: str | None = None) ->
     """Compile the oracle with gcc (-O2, OpenMP over sites); returns the path."""
     out = out or _LIB_PATH
     src = src or _SRC
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", out + ".tmp", src, "-lm"]
+    # -ffp-contract=off: the oracle's arithmetic is exactly what its source writes
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", out + ".tmp", src,
+           "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
@@ -57,6 +59,8 @@ def _declare(lib):
     lib.hisq_oracle_threads.restype = ctypes.c_int
     lib.hisq_oracle_set_threads.argtypes = [ctypes.c_int]
     lib.hisq_oracle_set_threads.restype = None
+    lib.hisq_oracle_phase_params.argtypes = [vp, vp, vp, ctypes.c_long]
+    lib.hisq_oracle_phase_params.restype = None
     for name in ("half16_encode",):
         getattr(lib, "hisq_oracle_" + name).argtypes = [vp, vp, vp, ctypes.c_long]
     lib.hisq_oracle_half16_decode.argtypes = [vp, vp, vp, ctypes.c_long]
@@ -702,28 +706,64 @@ def su3_from_eight(p):
     return np.stack([row1, row2, row3], axis=-2).reshape(shape + (3, 3))
 
 
-def long_recon8_roundtrip(lng, dims, fmt, compute_bits, lib=None):
-    """long links as a Dslash sees them when U is stored as its eight
-    parameters (su3_eight_params) in `fmt` and rebuilt (su3_from_eight, FP64
-    here: the kernel's own rounding of the rebuild is covered by the compute
-    precision's tolerance).  Fixed point: the six entries scaled by the max
-    |real component| of the whole of U, the two phase parameters by 1."""
-    c, u = long_link_split(lng, dims)
-    p = su3_eight_params(u)
-    if fmt in ("fix16", "fix32"):
-        bits = 16 if fmt == "fix16" else 32
-        scale = max(np.abs(u.real).max(), np.abs(u.imag).max())
-        # the real pairs as complex numbers: (a2, a3, b1) and (v_a + i v_c)
-        z = np.ascontiguousarray(p).view(np.complex128)
-        q, _ = fix_encode(z[..., :3], bits, absmax=scale, lib=lib)
-        qv, _ = fix_encode(z[..., 3], bits, absmax=1.0, lib=lib)
-        z = np.concatenate([fix_decode(q, scale, compute_bits, shape=z[..., :3].shape, lib=lib),
-                            fix_decode(qv, 1.0, compute_bits, shape=z[..., 3].shape, lib=lib)[..., None]], axis=-1)
-        p = z.view(np.float64)
-    elif fmt == "f32" or compute_bits == 32:
-        p = p.astype(np.float32).astype(np.float64)
-    elif fmt != "f64":
+def phase_param(z, lib=None):
+    """tan(arg(z)/4) (0 for z = 0) by the fixed operation sequence of
+    hisq_oracle_phase_params (the half-angle identities with r = |z| =
+    sqrt(fma(x, x, y*y)); each branch free of cancellation), complex -> float64"""
+    lib = lib or load()
+    z = np.asarray(z, dtype=np.complex128)
+    x = np.ascontiguousarray(z.real, dtype=np.float64)
+    y = np.ascontiguousarray(z.imag, dtype=np.float64)
+    v = np.zeros(x.shape, dtype=np.float64)
+    lib.hisq_oracle_phase_params(_ptr(x), _ptr(y), _ptr(v), x.size)
+    return v
+
+
+LONG8_FORMATS = ("f64", "fix32")
+
+
+def long_recon8_encode(lng, dims, fmt, lib=None):
+    """long links L = c * phase * U (U special unitary) stored as eight
+    parameters per link, [4, V, 8]: Re/Im of the entries (0,1), (0,2) and
+    (1,0) of W = L * phase * sign(c) = |c| U (exact: sign flips only), then
+    phase_param of W[0,0] and of W[2,0].  f64: the values; fix32: int32,
+    q = rint(x * (2^31 - 1) / m) with m the long field's max |real
+    component| for the entries and m = 1 for the two phase parameters.
+    Only FP64-compute triplets use this storage (F64 or FIX32 links)."""
+    if fmt not in LONG8_FORMATS:
         raise ValueError(f"eight-parameter long links in {fmt}")
+    c, _ = long_link_split(lng, dims)
+    lng = np.asarray(lng, dtype=np.complex128)
+    w = lng * (long_phases(dims) * np.sign(c))[..., None, None]
+    z = np.stack([w[..., 0, 1], w[..., 0, 2], w[..., 1, 0],
+                  phase_param(w[..., 0, 0], lib) + 1j * phase_param(w[..., 2, 0], lib)], axis=-1)
+    if fmt == "f64":
+        return np.ascontiguousarray(z).view(np.float64)
+    q, _ = fix_encode(z[..., :3], 32, absmax=field_absmax(lng), lib=lib)
+    qv, _ = fix_encode(z[..., 3], 32, absmax=1.0, lib=lib)
+    out = np.empty(z.shape[:-1] + (8,), dtype=np.int32)
+    out[..., :6] = q.reshape(z.shape[:-1] + (6,))
+    out[..., 6:] = qv.reshape(z.shape[:-1] + (2,))
+    return out
+
+
+def long_recon8_roundtrip(lng, dims, fmt, compute_bits=64, lib=None):
+    """long links as a Dslash sees them when stored by long_recon8_encode and
+    rebuilt (su3_from_eight in FP64: the kernel's own FP64 rounding of the
+    rebuild is covered by the tests' compute-precision allowance, amplified
+    by the rebuild's conditioning)"""
+    c, _ = long_link_split(lng, dims)
+    rec = long_recon8_encode(lng, dims, fmt, lib)
+    if fmt == "f64":
+        p = rec.astype(np.float64).copy()
+    else:
+        m = field_absmax(lng)
+        p = np.empty(rec.shape, dtype=np.float64)
+        p[..., :6] = fix_decode(np.ascontiguousarray(rec[..., :6]), m, 64, lib=lib).view(np.float64).reshape(
+            rec.shape[:-1] + (6,))
+        p[..., 6:] = fix_decode(np.ascontiguousarray(rec[..., 6:]), 1.0, 64, lib=lib).view(np.float64).reshape(
+            rec.shape[:-1] + (2,))
+    p[..., :6] /= abs(c)
     return c * long_phases(dims)[..., None, None] * su3_from_eight(p)
 
 

@@ -83,6 +83,33 @@ int hisq_oracle_threads(void)
     return n;
 }
 
+/* tan(arg(x + iy)/4), 0 at the origin: the phase parameter of the
+ * eight-parameter long-link storage, by one fixed sequence of correctly
+ * rounded operations (r = sqrt(fma(x, x, y*y)), cos = x/r, sin = y/r; cos >= 0:
+ * c2 = sqrt((1 + cos)/2), s2 = sin/(2 c2); else s2 = sqrt((1 - cos)/2) with the
+ * sign of sin, c2 = |sin|/(2|s2|); result s2/(1 + c2)), from the half-angle
+ * identities, so that every implementation stores the same bits. */
+void hisq_oracle_phase_params(const double *x, const double *y, double *v, long n)
+{
+    for (long k = 0; k < n; k++) {
+        double r = sqrt(fma(x[k], x[k], y[k] * y[k]));
+        if (r == 0.0) {
+            v[k] = 0.0;
+            continue;
+        }
+        double c = x[k] / r, sn = y[k] / r, ch, sh;
+        if (c >= 0.0) {
+            ch = sqrt((1.0 + c) * 0.5);
+            sh = sn / (2.0 * ch);
+        } else {
+            double sa = sqrt((1.0 - c) * 0.5);
+            sh = copysign(sa, sn);
+            ch = fabs(sn) / (2.0 * sa);
+        }
+        v[k] = sh / (1.0 + ch);
+    }
+}
+
 /* set the number of threads of the site loops (n >= 1) */
 void hisq_oracle_set_threads(int n)
 {

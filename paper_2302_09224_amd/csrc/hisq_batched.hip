@@ -199,7 +199,7 @@ struct BBuf {
 };
 
 size_t partial_len(const Geom &g, int nrhs) {
-    const size_t a = dslash_max_blocks(g.vh) * nrhs;
+    const size_t a = dslash_max_blocks(g) * nrhs;
     const size_t b = (size_t)4096 * 4 * nrhs;
     return std::max(a, b);
 }
@@ -279,8 +279,8 @@ struct BRun {
             m.cmap_red |= (unsigned long long)cols[i] << (4 * kr);
             m.cvalid_red |= 1u << kr;
         }
-        m.nl.pstride = dslash_max_blocks(g.vh);
-        for (int j = 0; j < 16; j++) m.nl.nb[j] = dslash_tile_blocks(g.vh, tr);
+        m.nl.pstride = dslash_max_blocks(g);
+        for (int j = 0; j < 16; j++) m.nl.nb[j] = dslash_tile_blocks(g, tr);
         return m;
     }
 
@@ -291,6 +291,20 @@ struct BRun {
         a.cmapped = 1;
         a.cvalid = red ? m.cvalid_red : m.cvalid;
         a.cmap = red ? m.cmap_red : m.cmap;
+    }
+
+    // plan every block the solve can shrink to (a power of two of columns up to
+    // nrhs), for the sloppy and the FP64 operator: the autotuner runs here, not
+    // later while the solve shares the device with other work
+    void pretune() {
+        const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
+        for (int c = 1;; c <<= 1) {
+            const int n = std::min(c, nrhs);
+            const unsigned mask = n >= 16 ? 0xffffu : ((1u << n) - 1u);
+            (void)map_columns(fmt, gs, B->ts, B->rs, mask);
+            (void)map_columns(f64, g64, B->t64, B->x64, mask);
+            if (n == nrhs) break;
+        }
     }
 
     // the sloppy launches cover the systems still iterating; a change of that set
@@ -523,6 +537,11 @@ hisq_status batched_run(BatchedJob &J) {
         }
         HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
     }
+    if (J.after_setup) {
+        R.pretune();
+        HISQ_TRY_HIP(hipStreamSynchronize(s_));
+        J.after_setup(J.after_setup_ctx);
+    }
     unsigned m0 = 0;   // systems with b != 0: their initial true residuals
     for (int j = 0; j < nrhs; j++)
         if (h->bactive[j]) m0 |= 1u << j;
@@ -635,6 +654,8 @@ extern "C" hisq_status hisq_cg_solve_batched(double *x, const double *b, int nrh
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
     if (!gs->fat || !gs->lng || gs->fmt != sloppy.gauge || g64->fmt != HISQ_GAUGE_F64 || !g64->fat || !g64->lng)
         return set_error(HISQ_EINVAL, "gauge format mismatch or null gauge");
+    if (gs->long_recon == HISQ_RECON_8 || g64->long_recon == HISQ_RECON_8)
+        return set_error(HISQ_EINVAL, "hisq_cg_solve_batched: eight-parameter long links have no batched Dslash");
     for (int k = 0; k < 4; k++)
         if (gs->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "gauge dims differ");
     hisq_solver_params q;

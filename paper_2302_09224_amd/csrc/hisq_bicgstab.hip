@@ -362,7 +362,7 @@ BlLayout bl_layout(const Geom &g, int l, const hisq_fmt &f) {
     L.fb = al256(spinor_field_bytes(g.vh, f.spinor));
     L.fb64 = al256(spinor_field_bytes(g.vh, SF_F64));
     const size_t nbl = (size_t)blas_blocks(2 * (size_t)g.vh);
-    L.part_doubles = std::max(nbl * (2 * BL_MAXK + 1), 2 * dslash_max_blocks(g.vh));
+    L.part_doubles = std::max(nbl * (2 * BL_MAXK + 1), 2 * dslash_max_blocks(g));
     L.nvec = 2 * (l + 1) + 1;   // r_0..r_l, u_0..u_l, shadow
     size_t off = 0;
     L.off_part = off;
@@ -410,6 +410,9 @@ extern "C" hisq_status hisq_bicgstab_solve(double *x, const double *b, const his
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
     if (g64->fmt != HISQ_GAUGE_F64 || !g64->fat || !g64->lng) return set_error(HISQ_EINVAL, "g64 must hold FP64 links");
     if (gs->fmt != sloppy.gauge || !gs->fat || !gs->lng) return set_error(HISQ_EINVAL, "gs does not match the sloppy triplet");
+    if (!recon_ok(sloppy, gs->long_recon, false) ||
+        !recon_ok(hisq_fmt{HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64}, g64->long_recon, false))
+        return set_error(HISQ_EINVAL, "eight-parameter long links need FP64 arithmetic on F64 or FIX32 links");
     for (int k = 0; k < 4; k++)
         if (gs->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "gauge dims differ");
     hisq_solver_params q;
@@ -458,7 +461,7 @@ extern "C" hisq_status hisq_bicgstab_solve(double *x, const double *b, const his
         p64.out = r64;
         p64.in = x64 + L.fb64;
         B.plan_64 = dslash_plan(f64, g, 1, &p64, B.st);
-        B.nb64 = dslash_tile_blocks(g.vh, B.plan_64.tile[0]);
+        B.nb64 = dslash_tile_blocks(g, B.plan_64.tile[0]);
     }
 
     hipLaunchKernelGGL(k_bl_split, dim3(B.nbl), dim3(BL_BLOCK), 0, B.st, x64, x, g, L.fb64);

@@ -334,6 +334,70 @@ template <int GF> __global__ void k_gauge_pack12(char *dst, const double *src, G
     }
 }
 
+// tan(arg(x + iy)/4), 0 at the origin, by the operation sequence the
+// eight-parameter storage specifies (every operation correctly rounded; the
+// one product-sum is an explicit fma, the rest leaves the compiler nothing to
+// contract), so that the stored bits do not depend on the compiler
+__device__ __noinline__ double phase_param(double x, double y) {
+    const double r = sqrt(fma(x, x, y * y));
+    if (r == 0.0) return 0.0;
+    const double c = x / r, sn = y / r;
+    double ch, sh;
+    if (c >= 0.0) {
+        ch = sqrt((1.0 + c) * 0.5);
+        sh = sn / (2.0 * ch);
+    } else {
+        const double sa = sqrt((1.0 - c) * 0.5);
+        sh = copysign(sa, sn);
+        ch = fabs(sn) / (2.0 * sa);
+    }
+    return sh / (1.0 + ch);
+}
+
+// eight parameters of W = L * phase * sign (= |lambda| U): Re/Im of W01, W02,
+// W10, then phase_param of W00 and of W20.  F64: four 16-byte planes; FIX32:
+// two planes, the entries scaled by lmax, the phase parameters by 1.
+template <int GF> __global__ void k_gauge_pack8(char *dst, const double *src, Geom g, double sign, double lmax) {
+    const size_t V = 2 * (size_t)g.vh;
+    const size_t vh = g.vh;
+    const size_t sub = (size_t)gauge_matrix_bytes8(GF) * vh;
+    const double qs = 2147483647.0 / lmax;
+    for (size_t idx = gtid(); idx < 4 * V; idx += gstride()) {
+        const int mu = (int)(idx / V);
+        const size_t site = idx - (size_t)mu * V;
+        size_t r = site;
+        const int x = (int)(r % g.X); r /= g.X;
+        const int y = (int)(r % g.Y); r /= g.Y;
+        const int z = (int)(r % g.Z);
+        const int t = (int)(r / g.Z);
+        const int par = (x + y + z + t) & 1;
+        const size_t s = site >> 1;
+        char *base = dst + (size_t)(2 * mu + par) * sub;
+        const double *u = src + idx * 18;
+        const double ph = link_phase3(mu, x, y, z, t, g.T) * sign;    // +-1: the products are exact
+        double p[8];
+        for (int k = 0; k < 6; k++) p[k] = u[2 + k] * ph;             // W01, W02, W10 (reals 2..7)
+        p[6] = phase_param(u[0] * ph, u[1] * ph);                     // W00
+        p[7] = phase_param(u[12] * ph, u[13] * ph);                   // W20
+        if (GF == GF_F64) {
+            for (int k = 0; k < 4; k++) {
+                f64x2 v;
+                v.x = p[2 * k];
+                v.y = p[2 * k + 1];
+                st<f64x2>(base + k * 16 * vh + 16 * s, v);
+            }
+        } else {
+            unsigned q[8];
+            for (int k = 0; k < 8; k++) q[k] = (unsigned)(int)__builtin_rint(p[k] * (k < 6 ? qs : 2147483647.0));
+            for (int k = 0; k < 2; k++) {
+                u32x4 a;
+                a.x = q[4 * k]; a.y = q[4 * k + 1]; a.z = q[4 * k + 2]; a.w = q[4 * k + 3];
+                st<u32x4>(base + k * 16 * vh + 16 * s, a);
+            }
+        }
+    }
+}
+
 __global__ void k_norm2_f64(const char *v, size_t n, double *partial) {
     __shared__ double lds[16];
     double acc = 0.0;
@@ -825,6 +889,17 @@ hipError_t launch_long_check(const double *src, const Geom &g, double *partial, 
     const int nb = blas_blocks(8 * (size_t)g.vh);
     *nblocks = nb;
     hipLaunchKernelGGL(k_long_check, dim3(nb), dim3(BLAS_BLOCK), 0, st, src, g, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_pack8(char *dst, const double *src, const Geom &g, int gf, double sign, double lmax,
+                              hipStream_t st) {
+    const int nb = blas_blocks((size_t)8 * g.vh);
+    switch (gf) {
+    case GF_F64: hipLaunchKernelGGL((k_gauge_pack8<GF_F64>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, sign, lmax); break;
+    case GF_FIX32: hipLaunchKernelGGL((k_gauge_pack8<GF_FIX32>), dim3(nb), dim3(BLAS_BLOCK), 0, st, dst, src, g, sign, lmax); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

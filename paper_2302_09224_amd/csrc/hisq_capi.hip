@@ -86,8 +86,10 @@ void gauge_args(DslashArgs &a, const hisq_gauge *g) {
     const bool fixed = q > 0.0;
     a.gfat = fixed ? g->fat_max / q : 1.0;
     a.glong = fixed ? g->long_max / q : 1.0;
-    a.long_recon = g->long_recon == HISQ_RECON_12 ? 12 : 18;
+    a.long_recon = g->long_recon == HISQ_RECON_12 ? 12 : g->long_recon == HISQ_RECON_8 ? 8 : 18;
     a.lcoef = g->long_coeff;
+    // eight-parameter storage holds |c| U: its entries times glong / |c| are those of U
+    if (a.long_recon == 8 && g->long_coeff != 0.0) a.glong /= fabs(g->long_coeff);
 }
 
 namespace {
@@ -146,6 +148,8 @@ hisq_status dslash_common(void *out, const void *in, const hisq_gauge *g, int pa
     if (!aligned16(out) || !aligned16(in)) return set_error(HISQ_EALIGN, "%s: spinors must be 16-byte aligned", what);
     if (parity != 0 && parity != 1) return set_error(HISQ_EINVAL, "%s: parity must be 0 or 1", what);
     if (out == in) return set_error(HISQ_EINVAL, "%s: out and in must not alias", what);
+    if (!recon_ok(fmt, g->long_recon, false))
+        return set_error(HISQ_EINVAL, "%s: eight-parameter long links need FP64 arithmetic on F64 or FIX32 links", what);
     return HISQ_OK;
 }
 
@@ -168,6 +172,10 @@ extern "C" size_t hisq_spinor_bytes(long nsites, int spinor_fmt) {
 extern "C" size_t hisq_gauge_long_bytes(const int dims[4], int gauge_fmt, int long_recon) {
     if (!dims || !dims_ok(dims) || gauge_fmt < 0 || gauge_fmt > HISQ_GAUGE_SX24) return 0;
     if (long_recon == HISQ_RECON_18) return gauge_field_bytes(dims, gauge_fmt);
+    if (long_recon == HISQ_RECON_8) {
+        if (gauge_fmt != HISQ_GAUGE_F64 && gauge_fmt != HISQ_GAUGE_FIX32) return 0;
+        return (size_t)4 * dims[0] * dims[1] * dims[2] * dims[3] * gauge_matrix_bytes8(gauge_fmt);
+    }
     if (long_recon != HISQ_RECON_12) return 0;
     const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
     return 4 * V * (size_t)gauge_matrix_bytes12(gauge_fmt);
@@ -183,8 +191,10 @@ extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void 
                                              void *stream) {
     if (!g || !fat_dst || !long_dst || !fat_src || !long_src || !dims)
         return set_error(HISQ_EINVAL, "hisq_gauge_pack: null argument");
-    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
-        return set_error(HISQ_EINVAL, "hisq_gauge_pack: long_recon must be 18 or 12");
+    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12 && long_recon != HISQ_RECON_8)
+        return set_error(HISQ_EINVAL, "hisq_gauge_pack: long_recon must be 18, 12 or 8");
+    if (long_recon == HISQ_RECON_8 && gauge_fmt != HISQ_GAUGE_F64 && gauge_fmt != HISQ_GAUGE_FIX32)
+        return set_error(HISQ_EINVAL, "hisq_gauge_pack: eight-parameter long links are stored in F64 or FIX32 only");
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "hisq_gauge_pack: dims must be even and >= 4");
     if (gauge_fmt < 0 || gauge_fmt > HISQ_GAUGE_SX24) return set_error(HISQ_EINVAL, "hisq_gauge_pack: bad gauge format %d", gauge_fmt);
     if (!aligned16(fat_dst) || !aligned16(long_dst) || !aligned16(fat_src) || !aligned16(long_src))
@@ -240,8 +250,12 @@ extern "C" hisq_status hisq_gauge_pack_recon(hisq_gauge *g, void *fat_dst, void 
                              "(lambda in [%g,%g], unitarity defect %g, |Im det|/|det| %g, sign counts %g/%g)",
                              tol, mn, mxl, defect, imr, np, nn);
         coeff = np > 0 ? lam : -lam;
-        long_scale = umax;
-        HISQ_TRY_HIP(launch_gauge_pack12((char *)long_dst, long_src, geo, gauge_fmt, coeff, umax, st));
+        if (long_recon == HISQ_RECON_8) {
+            HISQ_TRY_HIP(launch_gauge_pack8((char *)long_dst, long_src, geo, gauge_fmt, np > 0 ? 1.0 : -1.0, lmax_, st));
+        } else {
+            long_scale = umax;
+            HISQ_TRY_HIP(launch_gauge_pack12((char *)long_dst, long_src, geo, gauge_fmt, coeff, umax, st));
+        }
     }
     HISQ_TRY_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < 4; k++) g->dims[k] = dims[k];
@@ -292,6 +306,8 @@ extern "C" hisq_status hisq_dslash_multi(int n, void *const *out, const void *co
     for (int i = 0; i < n; i++) {
         if (!g[i]) return set_error(HISQ_EINVAL, "hisq_dslash_multi: null gauge %d", i);
         HISQ_TRY(dslash_common(out[i], in[i], g[i], parity, fmt, "hisq_dslash_multi"));
+        if (g[i]->long_recon == HISQ_RECON_8)
+            return set_error(HISQ_EINVAL, "hisq_dslash_multi: eight-parameter long links have no multi-lattice form");
         const int r = g[i]->long_recon == HISQ_RECON_12 ? 12 : 18;
         if (lr >= 0 && r != lr) return set_error(HISQ_EINVAL, "hisq_dslash_multi: lattices differ in long-link storage");
         lr = r;
@@ -344,6 +360,8 @@ extern "C" hisq_status hisq_dslash_batched(void *out, const void *in, const hisq
     if (nrhs < 1 || nrhs > 16) return set_error(HISQ_EINVAL, "hisq_dslash_batched: nrhs must be in [1,16]");
     if (!has_batched_form(fmt))
         return set_error(HISQ_EINVAL, "hisq_dslash_batched: triplet FIX32/INT30/32 has no batched kernel");
+    if (!recon_ok(fmt, g->long_recon, true))
+        return set_error(HISQ_EINVAL, "hisq_dslash_batched: eight-parameter long links have no batched form");
     DslashArgs a = base_args(g, out, in, parity);
     a.nrhs = nrhs;
     a.field_stride = spinor_field_bytes((size_t)a.g.vh, fmt.spinor);

@@ -49,6 +49,10 @@ __host__ __device__ constexpr int gauge_matrix_bytes(int gf) {
 __host__ __device__ constexpr int gauge_matrix_bytes12(int gf) {
     return gf == GF_F64 ? 96 : gf == GF_FIX16 ? 24 : gf == GF_SX24 ? 40 : 48;
 }
+// eight parameters of a special unitary long link (F64 and FIX32 only)
+__host__ __device__ constexpr int gauge_matrix_bytes8(int gf) {
+    return gf == GF_F64 ? 64 : gf == GF_FIX32 ? 32 : 0;
+}
 
 // ---------------------------------------------------------------------------
 // register types

@@ -52,7 +52,9 @@ hipError_t launch_one(const DslashArgs &a, const hisq_fmt &f, int rhs0, const Ds
 // triplet + long-link storage, X, Y, Z, T, rhs block, fused reduction (0 or 1)
 typedef std::tuple<int, int, int, int, int, int, int> TuneKey;
 
-inline int tune_id(const hisq_fmt &f, int long_recon) { return triplet_key(f) * 100 + (long_recon == 12 ? 12 : 18); }
+inline int tune_id(const hisq_fmt &f, int long_recon) {
+    return triplet_key(f) * 100 + (long_recon == 12 ? 12 : long_recon == 8 ? 8 : 18);
+}
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<DslashTile, float>> g_tuned;
 
@@ -64,7 +66,7 @@ bool tuning_enabled() {
 // a launch shape the kernels are instantiated for, for a block of c right-hand sides
 bool shape_ok(const hisq_fmt &f, int c, const DslashTile &t) {
     bool ok = t.nr >= 1 && t.rg >= 1 && t.nr * t.rg == c && (t.nr & (t.nr - 1)) == 0 && (t.rg & (t.rg - 1)) == 0;
-    ok = ok && (t.block == 128 || t.block == 256) && t.grid >= 0 && t.grid % 8 == 0 && (t.sweep == 0 || t.sweep == 1);
+    ok = ok && (t.block == 128 || t.block == 256) && t.grid >= 0 && t.grid % 8 == 0 && t.sweep >= 0 && t.sweep <= 2;
     const bool mfma = t.stage == 5 && t.rg == 4 && t.nr <= 4 && f.compute == 32;   // the matrix-core path
     return ok && (mfma || (t.nr == 1 ? (t.stage == 1 || t.stage == 2 || t.stage == 4 || t.stage == 8 ||
                                         t.stage == -1 || t.stage == -2)
@@ -130,7 +132,8 @@ hisq_status read_tune_file(const char *path, const std::string &tag, bool apply,
         const int dims[4] = {X, Y, Z, T};
         const DslashTile t{nr, rg, stage, block, grid, sweep};
         const bool pow2 = c >= 1 && c <= 16 && (c & (c - 1)) == 0;
-        if (!dims_ok(dims) || !triplet_ok(f) || (recon != 12 && recon != 18) || !pow2 || (red != 0 && red != 1) ||
+        if (!dims_ok(dims) || !triplet_ok(f) || (recon != 8 && recon != 12 && recon != 18) ||
+            !recon_ok(f, recon, c > 1) || !pow2 || (red != 0 && red != 1) ||
             (c > 1 && !has_batched_form(f)) || !shape_ok(f, c, t)) {
             st = set_error(HISQ_EIO, "tune cache %s: line %d names an unsupported key or shape", path, lineno);
             break;
@@ -179,13 +182,16 @@ void cache_append(const TuneKey &k, const DslashTile &t, float ms) {
 
 // candidate shapes for a block of c right-hand sides (c a power of two <= 16)
 // grids: 0 = one tile per block; 256*k = a persistent grid of k blocks per CU
-std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32) {
+// slab_ok: the lattice is deep enough in z for the z-slab order (one plane per XCD at least)
+std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32, bool slab_ok) {
     std::vector<DslashTile> v;
+    const int nsweep = slab_ok ? 3 : 2;
     if (c == 1) {
         for (int st : {1, 2, 4, 8, -1, -2})
             for (int blk : {128, 256})
                 for (int per_cu : {0, 4, 8})
-                    for (int sw : {0, 1}) v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk), sw});
+                    for (int sw = 0; sw < nsweep; sw++)
+                        v.push_back(DslashTile{1, 1, st, blk, per_cu * 256 * (256 / blk), sw});
         return v;
     }
     if (!batched_ok) return v;
@@ -193,7 +199,7 @@ std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32) {
         if (nr > c) break;
         const int rg = c / nr;
         for (int grid : {0, 2048})
-            for (int sw : {0, 1}) {
+            for (int sw = 0; sw < nsweep; sw++) {
                 v.push_back(DslashTile{nr, rg, 1, 256, grid, sw});
                 if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid, sw});
             }
@@ -272,7 +278,7 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     double *scratch = nullptr;
     if (red) {
         // partials of up to 16 field columns, one per block of the largest launch
-        p.pstride = dslash_max_blocks(g.vh);
+        p.pstride = dslash_max_blocks(g);
         if (hipMalloc((void **)&scratch, 16 * p.pstride * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(scratch_out);
@@ -284,7 +290,7 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
     // every candidate three times, then the three fastest ten times each (a
     // single noisy sample does not decide between shapes a few per cent apart)
     std::vector<std::pair<float, DslashTile>> timed;
-    for (const DslashTile &t : candidates(c, batched_ok, f.compute == 32)) {
+    for (const DslashTile &t : candidates(c, batched_ok, f.compute == 32, g.Z >= 8)) {
         const float ms = time_tile(p, f, t, st);
         if (ms > 0.f) timed.emplace_back(ms, t);
     }
@@ -313,7 +319,9 @@ int dslash_blocks(int n, int block) {
     return (nb + 7) & ~7;
 }
 
-size_t dslash_max_blocks(int vh) { return (size_t)dslash_blocks(vh * 16, 128); }
+size_t dslash_max_blocks(const Geom &g) {
+    return std::max((size_t)dslash_blocks(g.vh * 16, 128), (size_t)8 * g.T * slab_tiles(g, 16, 128));
+}
 
 DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st) {
     // one launch: the block of right-hand sides padded to a power of two (the
@@ -380,13 +388,16 @@ namespace {
 hisq_status tune_set_impl(const char *who, hisq_fmt fmt, const int dims[4], int long_recon, int rhs_block, int nr,
                           int rg, int stage, int block, int grid, int sweep, int fused) {
     if (!dims || !dims_ok(dims) || !triplet_ok(fmt)) return set_error(HISQ_EINVAL, "%s: bad dims or triplet", who);
-    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12)
-        return set_error(HISQ_EINVAL, "%s: long_recon must be 18 or 12", who);
+    if (long_recon != HISQ_RECON_18 && long_recon != HISQ_RECON_12 && long_recon != HISQ_RECON_8)
+        return set_error(HISQ_EINVAL, "%s: long_recon must be 18, 12 or 8", who);
     const bool pow2 = rhs_block >= 1 && rhs_block <= 16 && (rhs_block & (rhs_block - 1)) == 0;
     if (!pow2) return set_error(HISQ_EINVAL, "%s: rhs_block must be 1, 2, 4, 8 or 16", who);
     if (fused && rhs_block == 1)
         return set_error(HISQ_EINVAL, "%s: one right-hand side has a single shape (use hisq_tune_set)", who);
     if (rhs_block > 1 && !has_batched_form(fmt)) return set_error(HISQ_EINVAL, "%s: this triplet has no batched Dslash", who);
+    if (!recon_ok(fmt, long_recon, rhs_block > 1))
+        return set_error(HISQ_EINVAL, "%s: eight-parameter long links: FP64 triplets with F64 or FIX32 links, one "
+                                      "right-hand side", who);
     if (!shape_ok(fmt, rhs_block, DslashTile{nr, rg, stage, block, grid, sweep}))
         return set_error(HISQ_EINVAL, "%s: unsupported shape nr %d rg %d stage %d block %d grid %d sweep %d", who, nr,
                          rg, stage, block, grid, sweep);

@@ -270,6 +270,114 @@ template <class R, int GF> __device__ __forceinline__ Mat<R> link_decode12(const
     return complete_su3(link_rows12<R>(L, g), c, c);
 }
 
+// Long links stored as eight parameters (Sec. 1 "Compression": a special
+// unitary matrix has eight real degrees of freedom) of W = |c| U: Re/Im of
+// W01, W02, W10, then v_a = tan(arg(W00)/4) and v_c = tan(arg(W20)/4).
+// Planes of 16 bytes: F64 four (two parameters each), FIX32 two (four each;
+// the entries scaled by the long field's max |real component|, the phase
+// parameters by 1).  Only the FP64-arithmetic triplets use this storage.
+template <int GF> struct LinkRaw8 { unsigned unused; };   // formats without this storage: never loaded
+template <> struct LinkRaw8<GF_F64> { f64x2 w[4]; };
+template <> struct LinkRaw8<GF_FIX32> { u32x4 w[2]; };
+
+template <int GF> __device__ __forceinline__ LinkRaw8<GF> link_load8(const char *sub, size_t vh, size_t s);
+template <> __device__ __forceinline__ LinkRaw8<GF_F64> link_load8<GF_F64>(const char *sub, size_t vh, size_t s) {
+    LinkRaw8<GF_F64> L;
+#pragma unroll
+    for (int k = 0; k < 4; k++) L.w[k] = ld_nt<f64x2>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+template <> __device__ __forceinline__ LinkRaw8<GF_FIX32> link_load8<GF_FIX32>(const char *sub, size_t vh, size_t s) {
+    LinkRaw8<GF_FIX32> L;
+#pragma unroll
+    for (int k = 0; k < 2; k++) L.w[k] = ld_nt<u32x4>(sub + k * 16 * vh + 16 * s);
+    return L;
+}
+
+// the eight parameters in the compute precision (entries times g for fixed point)
+template <class R> __device__ __forceinline__ void link_params8(const LinkRaw8<GF_F64> &L, R g, R (&p)[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        p[2 * k] = (R)L.w[k].x * (k < 3 ? g : R(1));
+        p[2 * k + 1] = (R)L.w[k].y * (k < 3 ? g : R(1));
+    }
+}
+template <class R> __device__ __forceinline__ void link_params8(const LinkRaw8<GF_FIX32> &L, R g, R (&p)[8]) {
+    const unsigned ws[8] = {L.w[0].x, L.w[0].y, L.w[0].z, L.w[0].w, L.w[1].x, L.w[1].y, L.w[1].z, L.w[1].w};
+    const R gv = (R)(1.0 / 2147483647.0);
+#pragma unroll
+    for (int k = 0; k < 8; k++) p[k] = (R)(int)ws[k] * (k < 6 ? g : gv);
+}
+
+// U from its eight parameters.  Rows have unit norm: |u00|^2 = 1 - N with
+// N = |u01|^2 + |u02|^2, and the first column: |u20|^2 = N - |u10|^2; the
+// phases e^{i theta} = h^2 with h = (1 + i v)^2 / (1 + v^2).  Row 2 solves
+// the 2x2 system "orthogonal to row 1" and "u20 = conj(u01 u12 - u02 u11)"
+// (determinant N), row 3 the analogous one; in closed form
+//   u11 = -(conj(u00) u01 u10 + conj(u02 u20)) / N
+//   u12 =  (conj(u01 u20) - conj(u00) u02 u10) / N
+//   u21 =  (conj(u02 u10) - conj(u00) u01 u20) / N
+//   u22 = -(conj(u00) u02 u20 + conj(u01 u10)) / N
+// 1/x (x > 0) and sqrt(x) (0 for x <= 0) in FP64 from the hardware estimates
+// refined by two Newton steps each: within a few ulp, far cheaper than the
+// correctly rounded division and root, which the rebuild does not need
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double xp = x > 0.0 ? x : 1.0;
+    double y = __builtin_amdgcn_rsq(xp);
+    const double h = 0.5 * xp;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return x > 0.0 ? xp * y : 0.0;
+}
+
+template <class R> __device__ __forceinline__ Mat<R> su3_from8(const R (&p)[8]) {
+    static_assert(std::is_same<R, double>::value, "eight-parameter links are rebuilt in FP64");
+    auto cmul = [](R ar, R ai, R br, R bi, R &r, R &i) {
+        r = ar * br - ai * bi;
+        i = ar * bi + ai * br;
+    };
+    // e^{i theta} = ((1 + iv)^2 / (1 + v^2))^2
+    auto phase = [](R v, R &er, R &ei) {
+        const R d = rcp_nr(R(1) + v * v);
+        const R hr = (R(1) - v * v) * d, hi = R(2) * v * d;
+        er = hr * hr - hi * hi;
+        ei = R(2) * hr * hi;
+    };
+    const R a2r = p[0], a2i = p[1], a3r = p[2], a3i = p[3], b1r = p[4], b1i = p[5];
+    const R n = a2r * a2r + a2i * a2i + a3r * a3r + a3i * a3i;
+    R ear, eai, ecr, eci;
+    phase(p[6], ear, eai);
+    phase(p[7], ecr, eci);
+    const R ma = sqrt_nr(R(1) - n), mc = sqrt_nr(n - (b1r * b1r + b1i * b1i));
+    const R a1r = ma * ear, a1i = ma * eai, c1r = mc * ecr, c1i = mc * eci;
+    const R in = rcp_nr(n);
+    // conj(a1) a2, conj(a1) a3
+    const R xa2r = a1r * a2r + a1i * a2i, xa2i = a1r * a2i - a1i * a2r;
+    const R xa3r = a1r * a3r + a1i * a3i, xa3i = a1r * a3i - a1i * a3r;
+    R t0r, t0i, t1r, t1i;
+    Mat<R> U;
+    U.re[0] = a1r; U.im[0] = a1i; U.re[1] = a2r; U.im[1] = a2i; U.re[2] = a3r; U.im[2] = a3i;
+    U.re[3] = b1r; U.im[3] = b1i; U.re[6] = c1r; U.im[6] = c1i;
+    cmul(xa2r, xa2i, b1r, b1i, t0r, t0i);          // conj(a1) a2 b1
+    cmul(a3r, a3i, c1r, c1i, t1r, t1i);            // a3 c1
+    U.re[4] = -(t0r + t1r) * in; U.im[4] = -(t0i - t1i) * in;
+    cmul(a2r, a2i, c1r, c1i, t0r, t0i);            // a2 c1
+    cmul(xa3r, xa3i, b1r, b1i, t1r, t1i);          // conj(a1) a3 b1
+    U.re[5] = (t0r - t1r) * in; U.im[5] = (-t0i - t1i) * in;
+    cmul(a3r, a3i, b1r, b1i, t0r, t0i);            // a3 b1
+    cmul(xa2r, xa2i, c1r, c1i, t1r, t1i);          // conj(a1) a2 c1
+    U.re[7] = (t0r - t1r) * in; U.im[7] = (-t0i - t1i) * in;
+    cmul(xa3r, xa3i, c1r, c1i, t0r, t0i);          // conj(a1) a3 c1
+    cmul(a2r, a2i, b1r, b1i, t1r, t1i);            // a2 b1
+    U.re[8] = -(t0r + t1r) * in; U.im[8] = -(t0i - t1i) * in;
+    return U;
+}
+
 template <int SF> struct SpinRaw;
 template <> struct SpinRaw<SF_F64> { f64x2 w[3]; };
 template <> struct SpinRaw<SF_F32> { f32x4 a; f32x2 b; };
@@ -394,6 +502,27 @@ __device__ __forceinline__ Mat<R> hop_link12(const LinkRaw12<GF> &L, R g, R c, R
         f = R(1);
         return link_decode12<R>(L, g, c);
     }
+}
+
+// an eight-parameter long link c * U: M and f (the rebuild needs the true
+// entries, so fixed-point scales are applied to the parameters; c goes into f
+// when the spinor format has a site scale)
+template <int SF, class R, int GF>
+__device__ __forceinline__ Mat<R> hop_link8(const LinkRaw8<GF> &L, R g, R c, R &f) {
+    R prm[8];
+    link_params8<R>(L, g, prm);
+    Mat<R> U = su3_from8<R>(prm);
+    if constexpr (spinor_scaled<SF>()) {
+        f = c;
+    } else {
+        f = R(1);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            U.re[k] *= c;
+            U.im[k] *= c;
+        }
+    }
+    return U;
 }
 
 // ---------------------------------------------------------------------------
@@ -564,8 +693,10 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     const size_t fs = A.field_stride;
     const size_t vh = (size_t)g.vh;
     const int p = A.parity, q = 1 - p;
+    static_assert(LR != 8 || (NR == 1 && GF != GF_SX24), "eight-parameter long links: one right-hand side per lane");
     const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
-    const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
+    const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh
+                                 : LR == 8 ? (size_t)gauge_matrix_bytes8(GF) * vh : sub;
     const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
     // input field of the lane's right-hand side j
     auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
@@ -619,6 +750,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
     const Nbrs n = neighbours(g, s, p);
     LinkRaw<GF> L[NBUF][SB];
     LinkRaw12<GF> L12[NBUF][SB];
+    LinkRaw8<GF> L8[NBUF][SB];
     SpinRaw<SF> P[NBUF][SB][NR];
     // input column of each of the lane's right-hand sides, computed once per
     // site; a column the lane does not compute reads its first live column
@@ -638,10 +770,16 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
             const int ss = hop_spinor_site(n, h);
             const int ls = (h & 1) ? ss : s;
             const int lpar = (h & 1) ? q : p;
-            if (LR == 12 && (h & 2))
+            if constexpr (LR == 8) {
+                if (h & 2)
+                    L8[bf][i] = link_load8<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
+                else
+                    L[bf][i] = link_load<GF>(A.fat + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+            } else if (LR == 12 && (h & 2)) {
                 L12[bf][i] = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
-            else
+            } else {
                 L[bf][i] = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
+            }
 #pragma unroll
             for (int j = 0; j < NR; j++) P[bf][i][j] = spin_load<SF>(colp[j], vh, ss);
         }
@@ -651,9 +789,14 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
         for (int i = 0; i < SB; i++) {
             const int h = h0 + i;
             R f;
-            const Mat<R> U = (LR == 12 && (h & 2))
-                                 ? hop_link12<SF>(L12[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f)
-                                 : hop_link<SF>(L[bf][i], (h & 2) ? gl : gf, f);
+            Mat<R> U;
+            if constexpr (LR == 8)
+                U = (h & 2) ? hop_link8<SF>(L8[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f)
+                            : hop_link<SF>(L[bf][i], gf, f);
+            else
+                U = (LR == 12 && (h & 2))
+                        ? hop_link12<SF>(L12[bf][i], gl, lc * (R)((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f)
+                        : hop_link<SF>(L[bf][i], (h & 2) ? gl : gf, f);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 if (NR > 1 && !((live >> j) & 1u)) continue;
@@ -811,30 +954,55 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     // Tiles of blockDim lanes.  sweep 0: XCD k (blocks b with b % 8 == k) sweeps
     // the contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
     // gridDim/8 blocks taking every (gridDim/8)-th tile.  sweep 1: block b takes
-    // tiles b, b + gridDim, ...  One tile per block when the grid covers the
-    // lattice, a persistent grid-stride sweep otherwise.
+    // tiles b, b + gridDim, ...  sweep 2: XCD k owns the z-slab [Z k/8, Z (k+1)/8)
+    // of every time slice; its tiles run through the slab slice by slice in t
+    // order (a slab slice is zs * Y * X/2 consecutive checkerboard sites, padded
+    // to whole tiles), each of its gridDim/8 blocks taking every (gridDim/8)-th
+    // tile.  One tile per block when the grid covers the lattice, a persistent
+    // grid-stride sweep otherwise.
     const int ntile = (int)(((long long)g.vh * rg + blockDim.x - 1) / blockDim.x);
     int tile0, tend, tstep;
+    int zs0 = 0, slab = 0, tps = 1;
     if (sweep == 0) {
         const int xcd = blockIdx.x & 7;
         tile0 = (int)(((long long)ntile * xcd) >> 3) + (int)(blockIdx.x >> 3);
         tend = (int)(((long long)ntile * (xcd + 1)) >> 3);
         tstep = gridDim.x >> 3;
-    } else {
+    } else if (sweep == 1) {
         tile0 = blockIdx.x;
         tend = ntile;
         tstep = gridDim.x;
+    } else {
+        const int xcd = blockIdx.x & 7;
+        zs0 = (g.Z * xcd) >> 3;
+        slab = (((g.Z * (xcd + 1)) >> 3) - zs0) * g.Y * g.X2;
+        tps = (slab * rg + (int)blockDim.x - 1) / (int)blockDim.x;
+        tile0 = blockIdx.x >> 3;
+        tend = g.T * tps;
+        tstep = gridDim.x >> 3;
     }
     for (int tile = tile0; tile < tend; tile += tstep) {
-    const int tid = tile * blockDim.x + threadIdx.x;
-    const int s = rg == 1 ? tid : fdiv(tid, drg);
-    const int grp = tid - s * rg;
+    int s, grp;
+    bool inside;
+    if (sweep == 2) {
+        const int t = tile / tps;
+        const int off = (tile - t * tps) * (int)blockDim.x + (int)threadIdx.x;
+        const int sl = rg == 1 ? off : fdiv(off, drg);
+        inside = sl < slab;
+        s = (t * g.Z + zs0) * g.Y * g.X2 + sl;
+        grp = off - sl * rg;
+    } else {
+        const int tid = tile * blockDim.x + threadIdx.x;
+        s = rg == 1 ? tid : fdiv(tid, drg);
+        grp = tid - s * rg;
+        inside = s < g.vh;
+    }
     const int r0 = rhs0 + grp * NR;   // == rc
     if constexpr (STAGE == MFMA_STAGE) {
         // every lane takes part in the matrix instructions of its site's block
-        dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, s < g.vh, r0, live, acoef, red);
+        dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, inside, r0, live, acoef, red);
     } else {
-        if (s < g.vh && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
+        if (inside && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
     }
     }
     if (RED) {
@@ -883,6 +1051,7 @@ __global__ void __launch_bounds__(MULTI_BLOCK) k_dslash_multi(MultiArgs M) {
 template <int GF, int SF, class R>
 hipError_t launch_multi(const MultiArgs &m, int long_recon, hipStream_t st) {
     const int nb = m.boff[m.n];
+    if (long_recon != 12 && long_recon != 18) return hipErrorInvalidValue;
     if (long_recon == 12)
         hipLaunchKernelGGL((k_dslash_multi<GF, SF, R, 4, 12>), dim3(nb), dim3(MULTI_BLOCK), 0, st, m);
     else
@@ -893,9 +1062,23 @@ hipError_t launch_multi(const MultiArgs &m, int long_recon, hipStream_t st) {
 template <int GF, int SF, class R, int NR, int STAGE>
 hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid, int sweep, hipStream_t st,
                       int *nblocks) {
-    const int nb = dslash_tile_blocks(a.g.vh, DslashTile{NR, rg, STAGE, block, grid, sweep});
+    const int nb = dslash_tile_blocks(a.g, DslashTile{NR, rg, STAGE, block, grid, sweep});
     if (nblocks) *nblocks = nb;
     const FastDiv drg = make_fastdiv((unsigned)rg);
+    if (a.long_recon == 8) {
+        if constexpr (NR == 1 && std::is_same<R, double>::value && (GF == GF_F64 || GF == GF_FIX32) &&
+                      STAGE != MFMA_STAGE) {
+            if (rg != 1) return hipErrorInvalidValue;
+            if (a.red != RED_NONE)
+                hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 8>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
+            else if (a.guard.stop)
+                hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, true, 8>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
+            else
+                hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, false, false, 8>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.long_recon == 12) {
         if (a.red != RED_NONE)
             hipLaunchKernelGGL((k_dslash<GF, SF, R, NR, STAGE, true, true, 12>), dim3(nb), dim3(block), 0, st, a, rhs0, rg, drg, sweep);
@@ -919,7 +1102,7 @@ hipError_t launch_cfg(const DslashArgs &a, int rhs0, int rg, int block, int grid
 template <int GF, int SF, class R, bool BATCHED>
 hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipStream_t st, int *nblocks) {
     if (t.rg < 1 || t.rg > 16 || (t.rg & (t.rg - 1)) || t.nr * t.rg > 16 || (t.block != 128 && t.block != 256) ||
-        t.grid < 0 || (t.grid & 7) || (t.sweep != 0 && t.sweep != 1))
+        t.grid < 0 || (t.grid & 7) || t.sweep < 0 || t.sweep > 2)
         return hipErrorInvalidValue;
     switch (t.nr * 100 + t.stage) {
     case 99: return launch_cfg<GF, SF, R, 1, -1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);

@@ -44,6 +44,15 @@ bool triplet_ok(const hisq_fmt &f);
 // (FIX32/INT30/FP32 is not: it exists only as a refinement option)
 inline bool has_batched_form(const hisq_fmt &f) { return !(f.spinor == HISQ_SPINOR_INT30 && f.compute == 32); }
 bool aligned16(const void *p);
+// long-link storage a triplet can use: 18 and 12 reals always; the eight
+// parameters only with FP64 arithmetic on F64 or FIX32 links (the rebuild
+// amplifies the rounding of its arithmetic, which FP32 would make visible)
+// and only for launches of one right-hand side per lane
+// (any value but 12 and 8 reads as full storage, as in gauge_args)
+inline bool recon_ok(const hisq_fmt &f, int long_recon, bool batched) {
+    if (long_recon != HISQ_RECON_8) return true;
+    return !batched && f.compute == 64 && (f.gauge == HISQ_GAUGE_F64 || f.gauge == HISQ_GAUGE_FIX32);
+}
 
 // ---------------------------------------------------------------------------
 // Dslash
@@ -68,7 +77,8 @@ struct DslashArgs {
     size_t field_stride;  // batched: bytes between consecutive right-hand-side fields
     int nrhs;             // right-hand sides of the whole application (partials per block)
     size_t pstride;       // partial of right-hand side j, block b at partial[j*pstride + b]
-    int long_recon;       // 18: long links stored in full; 12: two rows, L = lcoef * phase * SU(3)
+    int long_recon;       // 18: long links stored in full; 12: two rows, L = lcoef * phase * SU(3);
+                          // 8: eight parameters of |lcoef| * U (entries times glong are those of U)
     double lcoef;
     const double *acol;   // optional (device): coefficient a of right-hand side j is acol[j]
     const int *cactive;   // optional (device): right-hand side j is skipped (not read, not written) if !cactive[j]
@@ -89,7 +99,10 @@ struct DslashArgs {
 // a multiple of 8, sweeping the tiles), `sweep` the order of the tiles: 0 =
 // XCD k (blocks b with b % 8 == k) takes the k-th eighth of the lattice, 1 =
 // consecutive tiles on consecutive blocks (the eight XCDs advance together,
-// sharing the neighbours they read in the memory-side cache).
+// sharing the neighbours they read in the memory-side cache), 2 = XCD k owns
+// the z-slab [Z k/8, Z (k+1)/8) of every time slice and walks its slabs in t
+// order, each slab slice padded to whole tiles (the t and z neighbours of
+// the sites an XCD works on stay within its own L2).
 struct DslashTile {
     int nr, rg, stage, block, grid, sweep;
 };
@@ -125,14 +138,19 @@ inline double dslash_link_bytes(const hisq_gauge *g) {
 
 // blocks of a Dslash launch over n lanes (multiple of 8 for the XCD order)
 int dslash_blocks(int n, int block);
-// blocks a launch of tile t really uses on vh sites (a persistent grid smaller
-// than the tile count is used as is): the number of per-block partials it writes
-inline int dslash_tile_blocks(int vh, const DslashTile &t) {
-    const int nb = dslash_blocks(vh * t.rg, t.block);
+// tiles of `block` lanes per slab slice of the z-slab order (the largest slab)
+inline int slab_tiles(const Geom &g, int rg, int block) {
+    const int slab = ((g.Z + 7) >> 3) * g.Y * g.X2;
+    return (slab * rg + block - 1) / block;
+}
+// blocks a launch of tile t really uses (a persistent grid smaller than the
+// tile count is used as is): the number of per-block partials it writes
+inline int dslash_tile_blocks(const Geom &g, const DslashTile &t) {
+    const int nb = t.sweep == 2 ? 8 * g.T * slab_tiles(g, t.rg, t.block) : dslash_blocks(g.vh * t.rg, t.block);
     return (t.grid > 0 && t.grid < nb) ? t.grid : nb;
 }
-// largest block count any plan for (vh, nrhs) can use, per right-hand side
-size_t dslash_max_blocks(int vh);
+// largest block count any plan for the lattice can use, per right-hand side
+size_t dslash_max_blocks(const Geom &g);
 // plan (autotuned on first use when a probe is given and the stream is not capturing)
 DslashPlan dslash_plan(const hisq_fmt &f, const Geom &g, int nrhs, const DslashArgs *probe, hipStream_t st);
 // the plan from the shapes already in the table (tuned, fixed or loaded), else
@@ -162,6 +180,10 @@ hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nbloc
 hipError_t launch_long_check(const double *src, const Geom &g, double *partial, int *nblocks, hipStream_t st);
 hipError_t launch_gauge_pack12(char *dst, const double *src, const Geom &g, int gf, double coef, double umax,
                                hipStream_t st);
+// eight parameters of W = L * phase * sign (sign = +-1, the sign of the long-link
+// coefficient); fixed point scaled by lmax (the long field's max |real component|)
+hipError_t launch_gauge_pack8(char *dst, const double *src, const Geom &g, int gf, double sign, double lmax,
+                              hipStream_t st);
 
 // solver control block, shared by the device scalar kernels and the host
 struct SolverCtrl {
@@ -277,6 +299,11 @@ struct BatchedJob {
     size_t ws_bytes;
     hipStream_t st;
     SolverCtrl *h;          // pinned host copy of the control block
+    // optional: called once every launch shape the block can use has been
+    // planned (tuned on first use) and before the first iteration, so that
+    // work the caller starts there on another stream never overlaps a timing
+    void (*after_setup)(void *);
+    void *after_setup_ctx;
     // results
     long iters, rus, dsl, d64;
     double alg;

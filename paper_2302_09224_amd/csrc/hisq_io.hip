@@ -24,7 +24,7 @@ struct FileHeader {
     int32_t fmt;           // spinor or gauge storage format
     int32_t dims[4];       // gauge: lattice extents; spinor: zero
     int64_t nsites;        // spinor: sites; gauge: lattice volume
-    int32_t long_recon;    // gauge: long-link storage (18 or 12); spinor: zero
+    int32_t long_recon;    // gauge: long-link storage (18, 12 or 8); spinor: zero
     int32_t reserved0;
     double fat_max, long_max, long_coeff;   // gauge scales (zero for spinors)
     uint64_t bytes0;       // spinor payload, or the fat-link payload
@@ -103,7 +103,7 @@ hisq_status read_header(FILE *f, FileHeader &h) {
             return set_error(HISQ_EIO, "inconsistent spinor header");
     } else if (h.kind == HISQ_FIELD_GAUGE) {
         if (h.fmt < 0 || h.fmt > HISQ_GAUGE_SX24 || !dims_ok(h.dims) ||
-            (h.long_recon != HISQ_RECON_18 && h.long_recon != HISQ_RECON_12))
+            (h.long_recon != HISQ_RECON_18 && h.long_recon != HISQ_RECON_12 && h.long_recon != HISQ_RECON_8))
             return set_error(HISQ_EIO, "inconsistent gauge header");
         if (h.bytes0 != hisq_gauge_bytes(h.dims, h.fmt) ||
             h.bytes1 != hisq_gauge_long_bytes(h.dims, h.fmt, h.long_recon))
@@ -186,7 +186,7 @@ extern "C" hisq_status hisq_spinor_load(const char *path, void *dst, long nsites
 extern "C" hisq_status hisq_gauge_save(const char *path, const hisq_gauge *g, void *stream) {
     if (!path || !g || !g->fat || !g->lng) return set_error(HISQ_EINVAL, "hisq_gauge_save: null pointer");
     if (!dims_ok(g->dims) || g->fmt < 0 || g->fmt > HISQ_GAUGE_SX24 ||
-        (g->long_recon != HISQ_RECON_18 && g->long_recon != HISQ_RECON_12))
+        (g->long_recon != HISQ_RECON_18 && g->long_recon != HISQ_RECON_12 && g->long_recon != HISQ_RECON_8))
         return set_error(HISQ_EINVAL, "hisq_gauge_save: descriptor not filled by hisq_gauge_pack");
     FileHeader h;
     std::memset(&h, 0, sizeof(h));

@@ -30,6 +30,9 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <functional>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "hisq_internal.h"
@@ -228,6 +231,11 @@ struct DevState {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     SolverCtrl *host_ctrl = nullptr;
+    // the second stream of the multi-shift refinement (shifted systems batched
+    // while the base system is refined on `stream`)
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev2 = nullptr;
+    SolverCtrl *host_ctrl2 = nullptr;
     std::mutex mu;
 };
 
@@ -242,6 +250,9 @@ hisq_status dev_state(DevState **out) {
         HISQ_TRY_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
         HISQ_TRY_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
         HISQ_TRY_HIP(hipHostMalloc((void **)&s.host_ctrl, sizeof(SolverCtrl), hipHostMallocDefault));
+        HISQ_TRY_HIP(hipStreamCreateWithFlags(&s.stream2, hipStreamNonBlocking));
+        HISQ_TRY_HIP(hipEventCreateWithFlags(&s.ev2, hipEventDisableTiming));
+        HISQ_TRY_HIP(hipHostMalloc((void **)&s.host_ctrl2, sizeof(SolverCtrl), hipHostMallocDefault));
     }
     *out = &s;
     return HISQ_OK;
@@ -262,7 +273,7 @@ struct Carver {
 };
 
 size_t partial_doubles(const Geom &g, int nrhs) {
-    const size_t a = dslash_max_blocks(g.vh) * std::max(1, nrhs);
+    const size_t a = dslash_max_blocks(g) * std::max(1, nrhs);
     const size_t b = (size_t)4096 * 4 * std::max(1, nrhs);
     return std::max(a, b);
 }
@@ -353,10 +364,10 @@ struct Run {
         const hisq_fmt f64 = {HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64};
         DslashArgs ps = dargs(gs, B->ts, B->rs, 1);
         plan_s = dslash_plan(fmt, g, 1, &ps, st);
-        nb_s = dslash_tile_blocks(g.vh, plan_s.tile[0]);
+        nb_s = dslash_tile_blocks(g, plan_s.tile[0]);
         DslashArgs p64 = dargs(g64, B->t64, B->x64, 1);
         plan_64 = dslash_plan(f64, g, 1, &p64, st);
-        nb_64 = dslash_tile_blocks(g.vh, plan_64.tile[0]);
+        nb_64 = dslash_tile_blocks(g, plan_64.tile[0]);
         // occupancy queries of the capped-grid kernels, before any capture
         (void)flush_x_grid(vh, fmt.spinor, fmt.compute);
         if (multishift) (void)shift_update_grid(vh, fmt.spinor, fmt.compute);
@@ -597,7 +608,7 @@ hisq_status check_params(const hisq_solver_params *p, hisq_solver_params *out) {
     if (out->grad_buffer < 1 || out->grad_buffer > HISQ_MAX_GRAD_BUFFER)
         return set_error(HISQ_EINVAL, "grad_buffer must be in [1,%d]", HISQ_MAX_GRAD_BUFFER);
     if (out->poll_every <= 0) out->poll_every = d.poll_every;
-    if (out->batch_refine != 0 && out->batch_refine != 1) return set_error(HISQ_EINVAL, "batch_refine must be 0 or 1");
+    if (out->batch_refine < 0 || out->batch_refine > 2) return set_error(HISQ_EINVAL, "batch_refine must be 0, 1 or 2");
     if (out->ru_estimate != 0 && out->ru_estimate != 1) return set_error(HISQ_EINVAL, "ru_estimate must be 0 or 1");
     return HISQ_OK;
 }
@@ -624,12 +635,14 @@ int chunk_of(const hisq_solver_params &p) {
     return ((p.poll_every + nb - 1) / nb) * nb;
 }
 
-hisq_status check_gauge(const hisq_gauge *gg, const int dims[4], int fmt, const char *what) {
+hisq_status check_gauge(const hisq_gauge *gg, const int dims[4], const hisq_fmt &f, const char *what) {
     if (!gg || !gg->fat || !gg->lng) return set_error(HISQ_EINVAL, "%s: null gauge field", what);
     for (int k = 0; k < 4; k++)
         if (gg->dims[k] != dims[k]) return set_error(HISQ_EINVAL, "%s: gauge dims differ from the solve", what);
-    if (gg->fmt != fmt) return set_error(HISQ_EINVAL, "%s: gauge format %d, triplet wants %d", what, gg->fmt, fmt);
+    if (gg->fmt != f.gauge) return set_error(HISQ_EINVAL, "%s: gauge format %d, triplet wants %d", what, gg->fmt, f.gauge);
     if (!aligned16(gg->fat) || !aligned16(gg->lng)) return set_error(HISQ_EALIGN, "%s: gauge not 16-byte aligned", what);
+    if (!recon_ok(f, gg->long_recon, false))
+        return set_error(HISQ_EINVAL, "%s: eight-parameter long links need FP64 arithmetic on F64 or FIX32 links", what);
     return HISQ_OK;
 }
 
@@ -729,8 +742,8 @@ extern "C" hisq_status hisq_cg_solve(double *x, const double *b, const hisq_gaug
     if (!(tol > 0.0)) return set_error(HISQ_EINVAL, "hisq_cg_solve: tol must be > 0");
     const int *dims = g64->dims;
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "hisq_cg_solve: bad lattice dims");
-    HISQ_TRY(check_gauge(g64, dims, HISQ_GAUGE_F64, "g64"));
-    HISQ_TRY(check_gauge(gs, dims, sloppy.gauge, "gs"));
+    HISQ_TRY(check_gauge(g64, dims, hisq_fmt{HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64}, "g64"));
+    HISQ_TRY(check_gauge(gs, dims, sloppy, "gs"));
     hisq_solver_params q;
     HISQ_TRY(check_params(p, &q));
     const Geom g = make_geom(dims);
@@ -807,14 +820,16 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
     if (!triplet_ok(ms_fmt) || !triplet_ok(refine_fmt)) return set_error(HISQ_EINVAL, "unsupported triplet");
     const int *dims = g64->dims;
     if (!dims_ok(dims)) return set_error(HISQ_EINVAL, "bad lattice dims");
-    HISQ_TRY(check_gauge(g64, dims, HISQ_GAUGE_F64, "g64"));
-    HISQ_TRY(check_gauge(g_ms, dims, ms_fmt.gauge, "g_ms"));
-    HISQ_TRY(check_gauge(g_ref, dims, refine_fmt.gauge, "g_ref"));
+    HISQ_TRY(check_gauge(g64, dims, hisq_fmt{HISQ_GAUGE_F64, HISQ_SPINOR_F64, 64}, "g64"));
+    HISQ_TRY(check_gauge(g_ms, dims, ms_fmt, "g_ms"));
+    HISQ_TRY(check_gauge(g_ref, dims, refine_fmt, "g_ref"));
     hisq_solver_params q;
     HISQ_TRY(check_params(p, &q));
     const Geom g = make_geom(dims);
     const int bs = std::max(spinor_site_bytes(ms_fmt.spinor), spinor_site_bytes(refine_fmt.spinor));
-    const MsLayout L = ms_layout(g, nshift, ms_fmt, refine_fmt, q);
+    MsLayout L = ms_layout(g, nshift, ms_fmt, refine_fmt, q);
+    // eight-parameter long links have no batched Dslash: shifts refined one after another
+    L.batch = L.batch && g_ref->long_recon != HISQ_RECON_8;
     if (ws_bytes < L.solver + L.batched)
         return set_error(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.solver + L.batched);
     CgBuffers B;
@@ -894,16 +909,21 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         }
     }
 
-    // ---- refinement (refine_fmt): base first keeping its gradient vector, then each shift ----
-    // (batched: the shifted systems together, every Dslash shared by up to 16 of them)
+    // ---- refinement (refine_fmt): the base keeps its gradient vector, every shift
+    // restarts from its multi-shift solution.  The base first, then the shifts in
+    // ascending order or together as a batch; with batch_refine == 2 the batch
+    // runs on the second stream while a host thread refines the base on the
+    // first (the two are independent once the multi-shift phase is over; every
+    // launch shape either uses is planned before they overlap). ----
     auto t1 = std::chrono::steady_clock::now();
-    for (int i = 0; i < (L.batch ? 1 : nshift) && status == HISQ_OK; i++) {
-        if (i == 1) {
-            HISQ_TRY_HIP(hipStreamSynchronize(s_));
-            t1 = std::chrono::steady_clock::now();
-            st->phase_seconds[1] = std::chrono::duration<double>(t1 - t0).count() - st->phase_seconds[0];
-        }
+    struct Refined {
+        hisq_status status = HISQ_OK;
+        double r0 = 0.0, r1 = 0.0, seconds = 0.0;
+        std::string msg;   // the error message (set in the thread that ran it)
         Run R;
+    };
+    // refinement run of system i on stream sr with host control block hc
+    auto setup_run = [&](Run &R, CgBuffers &Bi, int i, hipStream_t sr) {
         R.g = g;
         R.vh = g.vh;
         R.fmt = refine_fmt;
@@ -915,37 +935,103 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         R.graph = q.use_graph != 0;
         R.multishift = false;
         R.nshift = 1;
-        CgBuffers Bi = B;
+        Bi = B;
         if (i > 0) Bi.x64 = B.xs[i];
         R.B = &Bi;
-        R.st = s_;
+        R.st = sr;
         R.ds = E.ds;
-        double r0 = 0.0;
-        int it0 = 0;
-        if (i == 0 && nshift > 1) {
-            HISQ_TRY_HIP(launch_spinor_convert(B.pconv, refine_fmt.spinor, B.p[base_slot], ms_fmt.spinor, g.vh, s_));
-            status = cg_core(R, q, tol[0], 2, B.pconv, rho_ms, h, &r0);
-        } else {
-            status = cg_core(R, q, tol[i], 1, nullptr, 0.0, h, &r0);
+    };
+    auto refine_one = [&](int i, Refined &out, SolverCtrl *hc) {
+        auto ts = std::chrono::steady_clock::now();
+        CgBuffers Bi;
+        setup_run(out.R, Bi, i, s_);
+        if (i == 0 && nshift > 1)
+            out.status = cg_core(out.R, q, tol[0], 2, B.pconv, rho_ms, hc, &out.r0);
+        else
+            out.status = cg_core(out.R, q, tol[i], 1, nullptr, 0.0, hc, &out.r0);
+        out.r1 = hc->b2 > 0 ? std::sqrt(hc->r2_true / hc->b2) : 0.0;
+        hipError_t e = launch_spinor_unpack(x[i], Bi.x64, g.vh, SF_F64, s_);
+        if (e == hipSuccess) e = hipStreamSynchronize(s_);
+        if (e != hipSuccess && out.status == HISQ_OK)
+            out.status = set_error(HISQ_EHIP, "refinement of system %d: %s", i, hipGetErrorString(e));
+        if (out.status != HISQ_OK) out.msg = hisq_last_error();
+        out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+    };
+    auto account = [&](int i, const Refined &o) {
+        st->shift_resid_ms[i] = o.r0;
+        st->refine_iters[i] = (int)o.R.iters;
+        st->shift_resid[i] = o.r1;
+        st->reliable_updates += (int)o.R.rus;
+        st->dslash_sloppy += (int)o.R.dslash_sloppy;
+        st->dslash_f64 += (int)o.R.dslash_f64;
+        st->alg_bytes += o.R.alg_bytes;
+    };
+    if (nshift > 1 && status == HISQ_OK)
+        HISQ_TRY_HIP(launch_spinor_convert(B.pconv, refine_fmt.spinor, B.p[base_slot], ms_fmt.spinor, g.vh, s_));
+    const bool overlap = L.batch && nshift > 1 && q.batch_refine == 2;
+    if (!overlap) {
+        // the base, then the shifts: one after another, or together as a batch
+        for (int i = 0; i < (L.batch ? 1 : nshift) && status == HISQ_OK; i++) {
+            Refined o;
+            refine_one(i, o, h);
+            status = o.status;
+            account(i, o);
+            if (i == 0) {
+                t1 = std::chrono::steady_clock::now();
+                st->phase_seconds[1] = o.seconds;
+            }
         }
-        (void)it0;
-        st->shift_resid_ms[i] = r0;
-        st->refine_iters[i] = (int)R.iters;
-        st->shift_resid[i] = h->b2 > 0 ? std::sqrt(h->r2_true / h->b2) : 0.0;
-        st->reliable_updates += (int)R.rus;
-        st->dslash_sloppy += (int)R.dslash_sloppy;
-        st->dslash_f64 += (int)R.dslash_f64;
-        st->alg_bytes += R.alg_bytes;
-        HISQ_TRY_HIP(launch_spinor_unpack(x[i], Bi.x64, g.vh, SF_F64, s_));
-    }
-    if (L.batch || nshift == 1) {
-        HISQ_TRY_HIP(hipStreamSynchronize(s_));
-        t1 = std::chrono::steady_clock::now();
-        st->phase_seconds[1] = std::chrono::duration<double>(t1 - t0).count() - st->phase_seconds[0];
-    }
-    if (L.batch && status == HISQ_OK) {
-        // the multi-shift solutions are the initial guesses (clean restarts from them)
+        if (L.batch && status == HISQ_OK) {
+            for (int i = 1; i < nshift; i++) HISQ_TRY_HIP(launch_spinor_unpack(x[i], B.xs[i], g.vh, SF_F64, s_));
+            for (int i0 = 1; i0 < nshift && status == HISQ_OK; i0 += 16) {
+                BatchedJob J;
+                memset(&J, 0, sizeof(J));
+                J.nrhs = std::min(16, nshift - i0);
+                for (int j = 0; j < J.nrhs; j++) {
+                    J.x[j] = x[i0 + j];
+                    J.b[j] = b;
+                    J.c[j] = m2 + shifts[i0 + j];
+                    J.tol[j] = tol[i0 + j];
+                }
+                J.g64 = g64;
+                J.gs = g_ref;
+                J.fmt = refine_fmt;
+                J.q = q;
+                J.ws = (char *)ws + L.solver;
+                J.ws_bytes = L.batched;
+                J.st = s_;
+                J.h = h;
+                status = batched_run(J);
+                for (int j = 0; j < J.nrhs; j++) {
+                    st->shift_resid_ms[i0 + j] = J.resid0_j[j];
+                    st->refine_iters[i0 + j] = J.iters_j[j];
+                    st->shift_resid[i0 + j] = J.resid_j[j];
+                }
+                st->reliable_updates += (int)J.rus;
+                st->dslash_sloppy += (int)J.dsl;
+                st->dslash_f64 += (int)J.d64;
+                st->alg_bytes += J.alg;
+            }
+        }
+    } else if (status == HISQ_OK) {
+        // the multi-shift solutions are the shifted systems' initial guesses
         for (int i = 1; i < nshift; i++) HISQ_TRY_HIP(launch_spinor_unpack(x[i], B.xs[i], g.vh, SF_F64, s_));
+        // the base run's launch shapes, planned before anything overlaps
+        {
+            Run Rp;
+            CgBuffers Bp;
+            setup_run(Rp, Bp, 0, s_);
+            Rp.setup_plans();
+        }
+        HISQ_TRY_HIP(hipEventRecord(E.ds->ev2, s_));
+        hipStream_t s2 = E.ds->stream2;
+        HISQ_TRY_HIP(hipStreamWaitEvent(s2, E.ds->ev2, 0));
+        Refined base;
+        std::thread worker;
+        struct Start {
+            std::thread *w;
+            std::function<void()> fn;
+        } start{&worker, [&] { refine_one(0, base, h); }};
         for (int i0 = 1; i0 < nshift && status == HISQ_OK; i0 += 16) {
             BatchedJob J;
             memset(&J, 0, sizeof(J));
@@ -962,8 +1048,20 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
             J.q = q;
             J.ws = (char *)ws + L.solver;
             J.ws_bytes = L.batched;
-            J.st = s_;
-            J.h = h;
+            J.st = s2;
+            J.h = E.ds->host_ctrl2;
+            if (!worker.joinable()) {
+                // the base starts once the block's launch shapes are planned
+                J.after_setup = [](void *c) {
+                    Start *sp = static_cast<Start *>(c);
+                    try {
+                        *sp->w = std::thread(sp->fn);
+                    } catch (...) {
+                        // no thread: the base is refined after the batch
+                    }
+                };
+                J.after_setup_ctx = &start;
+            }
             status = batched_run(J);
             for (int j = 0; j < J.nrhs; j++) {
                 st->shift_resid_ms[i0 + j] = J.resid0_j[j];
@@ -975,6 +1073,15 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
             st->dslash_f64 += (int)J.d64;
             st->alg_bytes += J.alg;
         }
+        if (worker.joinable()) {
+            worker.join();
+        } else {
+            refine_one(0, base, h);   // the batched block stopped before it started the base
+        }
+        account(0, base);
+        st->phase_seconds[1] = base.seconds;
+        if (status == HISQ_OK && base.status != HISQ_OK)
+            status = set_error(base.status, "base refinement: %s", base.msg.c_str());
     }
     hisq_status s2 = E.end();
     if (status == HISQ_OK) status = s2;

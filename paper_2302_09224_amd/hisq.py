@@ -49,7 +49,7 @@ class hisq_gauge(ctypes.Structure):
                 ("long_recon", ctypes.c_int), ("long_coeff", ctypes.c_double)]
 
 
-RECON_18, RECON_12 = 18, 12
+RECON_18, RECON_12, RECON_8 = 18, 12, 8
 FIELD_SPINOR, FIELD_GAUGE = 1, 2
 
 

@@ -106,3 +106,21 @@ def format_bounds():
         name, d, n = [part.split() for part in line.split("|")]
         out[name[0]] = (float(d[1]), float(n[1]))
     return out
+
+
+def long8_records(packed, dims, gfmt):
+    """packed eight-parameter long field -> canonical-order [4, V, 8]: float64
+    parameters (F64) or the stored int32 (FIX32), as oracle.long_recon8_encode"""
+    V = oracle.volume(dims)
+    vh = V // 2
+    b = np.ascontiguousarray(packed)
+    mb = {0: 64, 3: 32}[gfmt]
+    dt = {0: np.float64, 3: np.int32}[gfmt]
+    out = np.zeros((4, V, 8), dtype=dt)
+    for mu in range(4):
+        for p in range(2):
+            sub = b[(2 * mu + p) * mb * vh:(2 * mu + p + 1) * mb * vh].view(dt)
+            per = 16 // np.dtype(dt).itemsize                  # parameters per 16-byte plane entry
+            r = sub.reshape(8 // per, vh, per).transpose(1, 0, 2).reshape(vh, 8)
+            out[mu, oracle.parity_sites(dims, p)] = r
+    return out

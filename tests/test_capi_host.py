@@ -83,7 +83,9 @@ def test_sizes(hisq):
     a = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
     p.batch_refine = 0
     assert a == hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
-    p.batch_refine = 2
+    p.batch_refine = 2                                           # the batch overlapping the base: same room
+    assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == wb
+    p.batch_refine = 3
     assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == 0
     p.batch_refine = 1
     p.ru_estimate = 2
@@ -138,9 +140,11 @@ def test_tune_set_validation(hisq):
     hisq.hisq_tune_set("int24", dims, 4, 4, 1, 1, 256, 0)
     hisq.hisq_tune_set("int30", dims, 1, 1, 1, -2, 256, 0)
     hisq.hisq_tune_set("int20", dims, 16, 4, 4, 5, 256, 0)      # matrix-core path, four lanes per site
+    hisq.hisq_tune_set("int30", dims, 1, 1, 1, -2, 256, 0, long_recon=8)   # eight-parameter long links
     rep = hisq.hisq_tune_report()
     assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
     assert "recon 12 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage 2 block 128 grid 0 sweep 0" in rep
+    assert "triplet 341 recon 8 lattice 8x8x8x16 rhs-block 1: nr 1 rg 1 stage -2 block 256 grid 0 sweep 0" in rep
     bad = [("half", dims, 3, 1, 3, 1, 256, 0),          # block of 3 right-hand sides
            ("half", dims, 4, 2, 1, 1, 256, 0),          # nr*rg != block
            ("half", dims, 1, 1, 1, 3, 256, 0),          # stage
@@ -153,8 +157,10 @@ def test_tune_set_validation(hisq):
            ("half", dims, 1, 1, 1, 1, 256, 12),         # grid not a multiple of 8
            ("int30_fp32", dims, 2, 1, 2, 1, 256, 0),    # no batched form
            ("half", (8, 8, 8, 7), 1, 1, 1, 1, 256, 0),  # odd extent
-           ("half", dims, 1, 1, 1, 1, 256, 0, 2),       # sweep order
-           ("half", dims, 1, 1, 1, 1, 256, 0, 0, 9)]    # long-link storage
+           ("half", dims, 1, 1, 1, 1, 256, 0, 3),       # sweep order
+           ("half", dims, 1, 1, 1, 1, 256, 0, 0, 9),    # long-link storage
+           ("half", dims, 1, 1, 1, 1, 256, 0, 0, 8),    # eight parameters: FP64 triplets only
+           ("double", dims, 2, 1, 2, 1, 256, 0, 0, 8)]  # eight parameters: one right-hand side
     for args in bad:
         with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
             hisq.hisq_tune_set(*args)

@@ -281,10 +281,12 @@ def test_batched_padding_columns_untouched(name, shape):
 
 # every lane layout the autotuner may choose for a block of 16 right-hand
 # sides: (nr, rg, stage) with stage 5 the matrix-core path (FP32 compute
-# only), and (grid, sweep) for tile-per-block and persistent grids
+# only), and (grid, sweep) for tile-per-block and persistent grids in the
+# three tile orders
 SHAPES_16 = [((1, 16, 1), (0, 1)), ((1, 16, 2), (0, 1)), ((2, 8, 1), (0, 1)), ((4, 4, 1), (0, 1)),
              ((4, 4, 1), (2048, 0)), ((8, 2, 1), (0, 1)), ((16, 1, 1), (0, 1)), ((16, 1, 1), (2048, 0)),
-             ((4, 4, 5), (0, 1)), ((4, 4, 5), (2048, 0))]
+             ((4, 4, 5), (0, 1)), ((4, 4, 5), (2048, 0)), ((1, 16, 1), (0, 2)), ((4, 4, 1), (0, 2)),
+             ((16, 1, 1), (2048, 2)), ((4, 4, 5), (0, 2))]
 
 
 @pytest.mark.parametrize("recon", [18, 12])

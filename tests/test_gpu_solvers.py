@@ -115,10 +115,12 @@ def test_cg_maxiter_reports_noconv():
 @pytest.mark.parametrize("ms,ref,batch", [("single", "half", 1), ("int30", "int20", 1), ("double", "double", 1),
                                           ("single", "single", 1), ("int30", "int20", 0), ("single", "half", 0),
                                           ("int30", "int30_fp32", 1), ("int30", "int24", 1),
-                                          ("sx24_int30", "int20", 1)])
+                                          ("sx24_int30", "int20", 1), ("int30", "int20", 2), ("single", "half", 2),
+                                          ("int30", "int30_fp32", 2)])
 def test_multishift(ms, ref, batch):
-    """batch: refine the shifted systems together (1) or one after another (0);
-    int30_fp32 has no batched form, so it refines one after another either way"""
+    """batch: refine the shifted systems together (1), together while the
+    base is refined concurrently (2), or one after another (0); int30_fp32 has
+    no batched form, so it refines one after another either way"""
     hisq = need_gpu()
     dims, mass = (8, 8, 8, 8), 0.05
     shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
@@ -156,21 +158,23 @@ def test_multishift_per_shift_tolerances():
 
 def test_multishift_many_shifts_two_blocks():
     """18 shifts: the batched refinement runs the 17 shifted systems as a block
-    of 16 and a block of 1; per-shift targets differ inside a block"""
+    of 16 and a block of 1; per-shift targets differ inside a block; with the
+    base refined concurrently (batch_refine 2) as well"""
     hisq = need_gpu()
     dims, mass = (6, 8, 10, 12), 0.05
     shifts = [10.0 ** (-4 + 5 * i / 17) for i in range(18)]
     tol = [1e-9 if i % 3 == 1 else 1e-10 for i in range(18)]
     fat, lng, ev, b = setup(dims, "near_unit")
     pg = packed(hisq, fat, lng, dims, ["double", "single", "half"])
-    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[1], pg[2], mass,
-                                      ms_fmt="single", ref_fmt="half")
-    assert st["status"] == "HISQ_OK", st
-    for i, s in enumerate(shifts):
-        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[i].cpu().numpy()), full(dims, ev, b),
-                                   dims, mass, s)
-        assert res <= tol[i] * (1 + 1e-6), (i, res)
-        assert abs(res - st["shift_resid"][i]) <= 1e-3 * res + 1e-15
+    for batch in (1, 2):
+        xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[1], pg[2], mass,
+                                          ms_fmt="single", ref_fmt="half", batch_refine=batch)
+        assert st["status"] == "HISQ_OK", st
+        for i, s in enumerate(shifts):
+            res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, xs[i].cpu().numpy()),
+                                       full(dims, ev, b), dims, mass, s)
+            assert res <= tol[i] * (1 + 1e-6), (batch, i, res)
+            assert abs(res - st["shift_resid"][i]) <= 1e-3 * res + 1e-15
 
 
 def test_multishift_single_shift():

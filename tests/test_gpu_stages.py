@@ -16,20 +16,21 @@ pytestmark = pytest.mark.gpu
 DIMS = (6, 8, 10, 12)       # Vh = 2880: a ragged last tile
 
 
-@pytest.mark.parametrize("recon", [18, 12])
+@pytest.mark.parametrize("recon", [18, 12, 8])
 def test_stage_schedules_bit_identical(recon):
     hisq = need_gpu()
     fat, lng = inputs.make_links(DIMS, "near_unit", seed=inputs.GAUGE_SEED + 80, device="cuda")
     vh = oracle.volume(DIMS) // 2
     psi = inputs.gaussian_spinor(vh, 81, device="cuda")
+    names = ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30")
     try:
-        for name in ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30"):
+        for name in (("double", "int30") if recon == 8 else names):
             f = hisq.fmt(name)
             pg = hisq.pack_gauge(fat, lng, DIMS, f.gauge, long_recon=recon)
             pin = hisq.pack_spinor(psi, f.spinor)
             ref = None
             for stage in (1, 2, 4, 8, -1, -2):
-                for block, grid, sweep in ((256, 0, 1), (128, 16, 0)):
+                for block, grid, sweep in ((256, 0, 1), (128, 16, 0), (256, 0, 2), (128, 16, 2)):
                     hisq.hisq_tune_set(name, DIMS, 1, 1, 1, stage, block, grid, sweep=sweep, long_recon=recon)
                     y = hisq.dslash(pin, pg, 0, f)
                     if ref is None:

@@ -134,18 +134,31 @@ def test_eight_params_degenerate_column():
     assert err < 4 * np.sqrt(np.finfo(float).eps), err
 
 
+def test_phase_param_is_tan_quarter_angle():
+    """the fixed operation sequence computes tan(arg(z)/4): closed forms and
+    random arguments (including both signs of zero and the negative axis)"""
+    z = np.array([1, 1j, -1, -1j, 1 + 1j, -1 + 0j, complex(-1, -0.0), 0, 3 - 4j], dtype=np.complex128)
+    want = np.array([0, np.tan(np.pi / 8), 1, -np.tan(np.pi / 8), np.tan(np.pi / 16), 1, -1, 0,
+                     np.tan(np.arctan2(-4, 3) / 4)])
+    assert np.abs(oracle.phase_param(z) - want).max() < 2e-16
+    rng = np.random.default_rng(3)
+    zr = (rng.standard_normal(20000) + 1j * rng.standard_normal(20000)) * 10.0 ** rng.uniform(-3, 3, 20000)
+    assert np.abs(oracle.phase_param(zr) - np.tan(np.angle(zr) / 4)).max() < 4e-16
+
+
 def test_eight_param_long_links_round_trip():
-    """FP64 storage of the eight parameters gives the long links back; fixed
-    point stays within the stored quantum amplified by 1/N (measured)"""
+    """FP64 storage of the eight parameters gives the long links back (to the
+    rebuild's conditioning); FIX32 within the stored quantum amplified by it"""
     dims = (4, 4, 4, 6)
     _, lng = inputs.make_links(dims, "near_unit", seed=23)
     lng = lng.numpy()
-    back = oracle.long_recon8_roundtrip(lng, dims, "f64", 64)
-    _, u = oracle.long_link_split(lng, dims)
-    n = np.minimum(np.abs(u[..., 0, 1]) ** 2 + np.abs(u[..., 0, 2]) ** 2, np.abs(u[..., 2, 0]) ** 2)[..., None, None]
-    assert (np.abs(back - lng) <= 1e-13 / n).all()
-    for fmt, q in (("fix32", 2.0 ** -31), ("fix16", 2.0 ** -15)):
-        back = oracle.long_recon8_roundtrip(lng, dims, fmt, 64)
-        rel = np.abs(back - lng) / (np.abs(lng).max())
-        assert (rel <= 64 * q / n).all(), fmt
-        assert np.median(rel) <= 4 * q, fmt
+    c, u = oracle.long_link_split(lng, dims)
+    kappa = 1.0 / np.minimum(np.abs(u[..., 0, 1]) ** 2 + np.abs(u[..., 0, 2]) ** 2, np.abs(u[..., 2, 0]) ** 2)
+    back = oracle.long_recon8_roundtrip(lng, dims, "f64")
+    assert (np.abs(back - lng).max(axis=(-1, -2)) <= 1e-13 * abs(c) * kappa).all()
+    back = oracle.long_recon8_roundtrip(lng, dims, "fix32")
+    rel = np.abs(back - lng).max(axis=(-1, -2)) / abs(c)
+    assert (rel <= 64 * 2.0 ** -31 * kappa).all()
+    assert np.median(rel) <= 8 * 2.0 ** -31
+    with pytest.raises(ValueError):
+        oracle.long_recon8_encode(lng, dims, "fix16")

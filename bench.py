@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 FLOP_PER_SITE = 1146
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "dslash_int30_r12_48x48x48x96_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_int30_r8_48x48x48x96_counters.txt")
 COUNTER_SOURCES = ["hisq_dslash_kernels.h", "hisq_device.h", "hisq_dslash_t_int30.hip"]
 
 
@@ -441,9 +441,10 @@ def main():
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--batched", action="store_true",
                     help="also time the 16-right-hand-side Dslash on 32^3x64 against 16 single applications")
-    ap.add_argument("--batched-only", action="store_true",
+    ap.add_argument("--batched-only", nargs="?", const="both", default=None, choices=("both", "32x64", "48x96"),
                     help="only the batched FIX16/INT20 Dslash with two-row long links: 16 right-hand sides on "
-                         "32^3x64 and 11 (a block of 16) on 48^3x96, as the refinement runs it (for counters)")
+                         "32^3x64 and 11 (a block of 16) on 48^3x96, as the refinement runs it (for counters); "
+                         "32x64 or 48x96 selects one of the two")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -473,10 +474,9 @@ def main():
         del src, dst
 
     if args.batched_only:
-        res = [bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, names=("int20",),
-                             recon=12),
-               bench_batched(args, hisq, inputs, torch, dev, dims=(48, 48, 48, 96), nrhs=11, names=("int20",),
-                             recon=12)]
+        cases = {"32x64": ((32, 32, 32, 64), 16), "48x96": ((48, 48, 48, 96), 11)}
+        res = [bench_batched(args, hisq, inputs, torch, dev, dims=d, nrhs=n, names=("int20",), recon=12)
+               for k, (d, n) in cases.items() if args.batched_only in ("both", k)]
         print(json.dumps(dict(batched=res, tuning=hisq.hisq_tune_report().strip().splitlines())))
         return
 

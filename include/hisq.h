@@ -453,9 +453,11 @@ hisq_status hisq_gauge_load(const char *path, hisq_gauge *g, void *fat_dst, size
  * rhs_block right-hand sides (1, 2, 4, 8 or 16), replacing what the
  * autotuner chose or would choose: nr right-hand sides per lane and rg lanes
  * per site (nr * rg == rhs_block, both powers of two), stage hops per load
- * stage (1, 2, 4 or 8 when nr == 1; 1 otherwise; -1 or -2: one or two hops
- * per stage, double-buffered, the next stage's loads issued before the
- * current stage's arithmetic; nr == 1 only), block threads (128 or 256),
+ * stage (1, 2, 4, 8, -1 or -2 when nr == 1; 1 or -1 when 1 < nr <= 8; 1 when
+ * nr == 16; -1 and -2: one or two hops per stage, double-buffered, the next
+ * stage's loads issued before the current stage's arithmetic; 5: the
+ * matrix-core path, rg == 4 and nr <= 4, FP32-arithmetic triplets only),
+ * block threads (128 or 256),
  * grid blocks (0: one tile of lanes per block; otherwise a multiple of 8,
  * a persistent grid when smaller than the tile count) and sweep, the order in
  * which the blocks take the tiles of lanes (0: the blocks of XCD k, b % 8 ==

@@ -70,7 +70,7 @@ bool shape_ok(const hisq_fmt &f, int c, const DslashTile &t) {
     const bool mfma = t.stage == 5 && t.rg == 4 && t.nr <= 4 && f.compute == 32;   // the matrix-core path
     return ok && (mfma || (t.nr == 1 ? (t.stage == 1 || t.stage == 2 || t.stage == 4 || t.stage == 8 ||
                                         t.stage == -1 || t.stage == -2)
-                                     : t.stage == 1));
+                                     : (t.stage == 1 || (t.stage == -1 && t.nr <= 8))));
 }
 
 // ---------------------------------------------------------------------------
@@ -202,12 +202,14 @@ std::vector<DslashTile> candidates(int c, bool batched_ok, bool fp32, bool slab_
             for (int sw = 0; sw < nsweep; sw++) {
                 v.push_back(DslashTile{nr, rg, 1, 256, grid, sw});
                 if (nr == 1) v.push_back(DslashTile{nr, rg, 2, 256, grid, sw});
+                // double-buffered: the next hop's words in flight during this hop's arithmetic
+                if (nr > 1 && nr <= 8) v.push_back(DslashTile{nr, rg, -1, 256, grid, sw});
             }
     }
     // the matrix-core path: four lanes per site, FP32 compute only
     if (fp32 && c >= 4)
         for (int grid : {0, 2048})
-            for (int sw : {0, 1}) v.push_back(DslashTile{c / 4, 4, 5, 256, grid, sw});
+            for (int sw = 0; sw < nsweep; sw++) v.push_back(DslashTile{c / 4, 4, 5, 256, grid, sw});
     return v;
 }
 
@@ -302,6 +304,19 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
         if (ms > 0.f && (tbest < 0.f || ms < tbest)) {
             tbest = ms;
             best = timed[k].second;
+        }
+    }
+    // The z-slab order keeps each XCD's neighbour planes in its own L2: about
+    // 9 % fewer bytes fetched into L2 for the same time (the other orders'
+    // extra fetches hit the memory-side cache).  Within 1 % of the fastest,
+    // the same shape in that order is kept.
+    if (tbest > 0.f && best.sweep != 2 && g.Z >= 8) {
+        DslashTile twin = best;
+        twin.sweep = 2;
+        const float ms = time_tile(p, f, twin, st, 10);
+        if (ms > 0.f && ms <= 1.01f * tbest) {
+            tbest = ms;
+            best = twin;
         }
     }
     (void)hipStreamSynchronize(st);

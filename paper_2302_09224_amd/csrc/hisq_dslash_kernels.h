@@ -633,17 +633,18 @@ __device__ __forceinline__ bool colvalid(const DslashArgs &A, int k, int ncol) {
 }
 
 // The epilogue of one output site: out = b*D(in) + a*x + c*y for each live
-// right-hand side of the lane, packed and stored, and the optional reduction.
-template <int SF, class R, int NR, bool RED>
-__device__ __forceinline__ void site_epilogue(const DslashArgs &A, int s, int r0, unsigned live, const R (&acoef)[NR],
-                                              CVec<R> (&acc)[NR], double (&red)[NR]) {
+// right-hand side j of the lane (field column col(j)), packed and stored, and
+// the optional reduction.
+template <int SF, class R, int NR, bool RED, class ColF>
+__device__ __forceinline__ void site_epilogue(const DslashArgs &A, int s, ColF col, unsigned live,
+                                              const R (&acoef)[NR], CVec<R> (&acc)[NR], double (&red)[NR]) {
     const size_t fs = A.field_stride;
     const size_t vh = (size_t)A.g.vh;
     const R b = (R)A.b, cc = (R)A.c;
 #pragma unroll
     for (int j = 0; j < NR; j++) {
         if (!((live >> j) & 1u)) continue;
-        const size_t off = (size_t)colmap(A, r0 + j) * fs;
+        const size_t off = (size_t)col(j) * fs;
         const R a = acoef[j];
         CVec<R> xv;
         cvec_zero(xv);
@@ -819,25 +820,99 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
         apply_stage(k * SB, k % NBUF);
         if (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
-    site_epilogue<SF, R, NR, RED>(A, s, r0, live, acoef, acc, red);
+    site_epilogue<SF, R, NR, RED>(A, s, [&](int j) { return colmap(A, r0 + j); }, live, acoef, acc, red);
 }
 
-// Batched sites on the matrix cores (STAGE == MFMA_STAGE, FP32 compute, rg = 4
+// Batched sites on the matrix cores (STAGE == MFMA_STAGE, FP32 compute, four
 // lanes per site).  The four lanes of a site form one block of the 16-block
-// 4x4x1 FP32 MFMA: lane i supplies row i of the operand A (a column of the
-// link's 6x6 real form), lane j supplies column j of B (a component of its own
-// right-hand side's neighbour spinor), and lane j receives column j of the
-// 4x4 product in its four accumulator registers.  Output rows 0-2 are the real
-// parts of colours 0-2 (rows 4-6 the imaginary parts, in the second tile);
-// rows 3 and 7 are padding, lane 3 supplies zeros for them.  The 16 hops
-// accumulate in place, so after the last hop each lane holds the six output
-// reals of each of its NR right-hand sides, as the FMA path would.
+// 4x4x1 FP32 MFMA.  Lane i supplies row i of the operand A, row i of the
+// hop's link in real form (the real parts of the output in one tile, the
+// imaginary parts in another); lane j supplies column j of B, one component
+// of its own right-hand side's neighbour spinor per K step, and receives
+// column j of the product in four accumulator registers.  Output rows 0-2
+// are colours 0-2; the fourth lane's row is padding whose output is never
+// read.  Each lane therefore needs only its own row (forward hops) or column
+// (backward hops) of the link: fat and 18-real links select the stored words
+// of those three entries and decode only them; two-row long links are
+// completed in full (row 3 needs both stored rows) before the selection.
+// The lane's right-hand sides are the columns 4 m + lane (m < NR).
 constexpr int MFMA_STAGE = 5;
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
+// lane of the site's block: li == 0 (and the padding lane 3), li == 1, else li == 2
+struct QuadSel {
+    bool c0, c1;
+};
+template <class T> __device__ __forceinline__ T qsel(const QuadSel &q, T a, T b, T c) {
+    return q.c0 ? a : (q.c1 ? b : c);
+}
+
+// stored words of complex entry k (row-major) of a fat or 18-real link
+__device__ __forceinline__ unsigned entry_word(const LinkRaw<GF_FIX16> &L, int k) {
+    return k < 4 ? L.w[0][k] : k < 8 ? L.w[1][k - 4] : L.t;
+}
+__device__ __forceinline__ u32x2 entry_word(const LinkRaw<GF_FIX32> &L, int k) {
+    return k < 8 ? u32x2{L.w[k >> 1][2 * (k & 1)], L.w[k >> 1][2 * (k & 1) + 1]} : L.t;
+}
+__device__ __forceinline__ f32x2 entry_word(const LinkRaw<GF_F32> &L, int k) {
+    return k < 8 ? f32x2{L.w[k >> 1][2 * (k & 1)], L.w[k >> 1][2 * (k & 1) + 1]} : L.t;
+}
+template <int GF> constexpr bool entry_select() { return GF == GF_FIX16 || GF == GF_FIX32 || GF == GF_F32; }
+
+// row li (BACK false) or column li (BACK true) of a fat or 18-real link with
+// scale g, as M and f with the convention of hop_link
+template <int SF, int GF, bool BACK>
+__device__ __forceinline__ void lane_link(const LinkRaw<GF> &L, float g, const QuadSel &q, float (&ur)[3],
+                                          float (&ui)[3], float &f) {
+    constexpr bool fold = spinor_scaled<SF>() && gauge_fixed<GF>();
+    if constexpr (entry_select<GF>()) {
+        f = fold ? g : 1.0f;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int k0 = BACK ? 3 * c : c, k1 = BACK ? 3 * c + 1 : 3 + c, k2 = BACK ? 3 * c + 2 : 6 + c;
+            const auto w = qsel(q, entry_word(L, k0), entry_word(L, k1), entry_word(L, k2));
+            if constexpr (GF == GF_FIX16) {
+                ur[c] = (float)sext16(w);
+                ui[c] = (float)sext16(w >> 16);
+            } else if constexpr (GF == GF_FIX32) {
+                ur[c] = (float)(int)w.x;
+                ui[c] = (float)(int)w.y;
+            } else {
+                ur[c] = w.x;
+                ui[c] = w.y;
+            }
+            if constexpr (gauge_fixed<GF>() && !fold) {
+                ur[c] *= g;
+                ui[c] *= g;
+            }
+        }
+    } else {
+        const Mat<float> U = hop_link<SF>(L, g, f);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int k0 = BACK ? 3 * c : c, k1 = BACK ? 3 * c + 1 : 3 + c, k2 = BACK ? 3 * c + 2 : 6 + c;
+            ur[c] = qsel(q, U.re[k0], U.re[k1], U.re[k2]);
+            ui[c] = qsel(q, U.im[k0], U.im[k1], U.im[k2]);
+        }
+    }
+}
+
+// the same for a two-row long link c * U
+template <int SF, int GF, bool BACK>
+__device__ __forceinline__ void lane_link12(const LinkRaw12<GF> &L, float g, float c, const QuadSel &q,
+                                            float (&ur)[3], float (&ui)[3], float &f) {
+    const Mat<float> U = hop_link12<SF>(L, g, c, f);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int k0 = BACK ? 3 * k : k, k1 = BACK ? 3 * k + 1 : 3 + k, k2 = BACK ? 3 * k + 2 : 6 + k;
+        ur[k] = qsel(q, U.re[k0], U.re[k1], U.re[k2]);
+        ui[k] = qsel(q, U.im[k0], U.im[k1], U.im[k2]);
+    }
+}
+
 template <int GF, int SF, int NR, bool RED, int LR>
-__device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, bool valid, int r0, unsigned live,
-                                                 const float (&acoef)[NR], double (&red)[NR]) {
+__device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, bool valid, int rhs0, int li,
+                                                 unsigned live, const float (&acoef)[NR], double (&red)[NR]) {
     const Geom &g = A.g;
     const size_t fs = A.field_stride;
     const size_t vh = (size_t)g.vh;
@@ -845,20 +920,21 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
     const size_t sub = (size_t)gauge_matrix_bytes(GF) * vh;
     const size_t lsub = LR == 12 ? (size_t)gauge_matrix_bytes12(GF) * vh : sub;
     const float gf = (float)A.gfat, gl = (float)A.glong, lc = (float)A.lcoef;
-    const int li = (int)(threadIdx.x & 3u);          // row of the site's block this lane supplies
+    const QuadSel qs{li == 0 || li == 3, li == 1};
     const int se = valid ? s : 0;                     // invalid lanes read site 0, results discarded
     const unsigned lv = valid ? live : 0u;
-    // input column of each right-hand side; columns the lane does not compute
-    // (and every column of an invalid lane) read valid memory whose products
-    // only reach this lane's own, unstored, outputs
+    // input column of each of the lane's right-hand sides; a column the lane
+    // does not compute (every column of an invalid lane) reads valid memory
+    // whose products reach only this lane's own, unstored, outputs
     const char *colp[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) colp[j] = ((lv >> j) & 1u) ? A.in + (size_t)colmap(A, r0 + j) * fs : A.in;
+    for (int m = 0; m < NR; m++)
+        colp[m] = ((lv >> m) & 1u) ? A.in + (size_t)colmap(A, rhs0 + 4 * m + li) * fs : A.in;
     f32x4v acc_re[NR], acc_im[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) {
-        acc_re[j] = f32x4v{0.f, 0.f, 0.f, 0.f};
-        acc_im[j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < NR; m++) {
+        acc_re[m] = f32x4v{0.f, 0.f, 0.f, 0.f};
+        acc_im[m] = f32x4v{0.f, 0.f, 0.f, 0.f};
     }
     const Nbrs n = neighbours(g, se, p);
 #pragma unroll
@@ -866,65 +942,73 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
         const int ss = hop_spinor_site(n, h);
         const int ls = (h & 1) ? ss : se;
         const int lpar = (h & 1) ? q : p;
-        Mat<float> U;
-        float f;
+        const bool back = (h & 1) != 0;
+        float ur[3], ui[3], f;
         if (LR == 12 && (h & 2)) {
             const LinkRaw12<GF> L = link_load12<GF>(A.lng + (size_t)(2 * (h >> 2) + lpar) * lsub, vh, ls);
-            U = hop_link12<SF>(L, gl, lc * ((h & 1) ? n.lsb[h >> 2] : n.lsf[h >> 2]), f);
+            const float c = lc * (back ? n.lsb[h >> 2] : n.lsf[h >> 2]);
+            if (back)
+                lane_link12<SF, GF, true>(L, gl, c, qs, ur, ui, f);
+            else
+                lane_link12<SF, GF, false>(L, gl, c, qs, ur, ui, f);
         } else {
             const LinkRaw<GF> L = link_load<GF>(((h & 2) ? A.lng : A.fat) + (size_t)(2 * (h >> 2) + lpar) * sub, vh, ls);
-            U = hop_link<SF>(L, (h & 2) ? gl : gf, f);
+            if (back)
+                lane_link<SF, GF, true>(L, (h & 2) ? gl : gf, qs, ur, ui, f);
+            else
+                lane_link<SF, GF, false>(L, (h & 2) ? gl : gf, qs, ur, ui, f);
         }
+        // backward hops add -U^dag y: with a site scale the sign goes into it
+        // (U^dag applied to -y), otherwise into the link row
+        constexpr bool ssign = spinor_scaled<SF>();
+        const float fy = (back && ssign) ? -f : f;
         CVec<float> v[NR];
 #pragma unroll
-        for (int j = 0; j < NR; j++) v[j] = spin_decode<float>(spin_load<SF>(colp[j], vh, ss), f);
-        // this lane's entries of the real form: forward hops U (row li), backward
-        // hops -U^dagger (column li of U); lane 3 pads with zeros
-        float ur[3], ui[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            // entry (li, c) of U (forward) or (c, li) (backward) for li = 0, 1, 2
-            const int e0 = (h & 1) ? 3 * c : c, e1 = (h & 1) ? 3 * c + 1 : 3 + c, e2 = (h & 1) ? 3 * c + 2 : 6 + c;
-            ur[c] = li == 0 ? U.re[e0] : li == 1 ? U.re[e1] : li == 2 ? U.re[e2] : 0.f;
-            ui[c] = li == 0 ? U.im[e0] : li == 1 ? U.im[e1] : li == 2 ? U.im[e2] : 0.f;
+        for (int m = 0; m < NR; m++) {
+            if constexpr (SF == SF_INT20)
+                v[m] = SpinorIO<SF_INT20, float>::template decode<true>(spin_load<SF>(colp[m], vh, ss).w, fy);
+            else
+                v[m] = spin_decode<float>(spin_load<SF>(colp[m], vh, ss), fy);
         }
-        // operand A for K index k (k < 3: Re of input colour k, k >= 3: Im of colour k-3)
+        if (back && !ssign) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                ur[c] = -ur[c];
+                ui[c] = -ui[c];
+            }
+        }
+        // A for K index k (k < 3: Re of input colour k, k >= 3: Im of colour k - 3).
+        // forward  U y:     Re row: ur yr - ui yi, Im row: ui yr + ur yi
+        // backward U^dag y: Re row: ur yr + ui yi, Im row: ur yi - ui yr
         float a_re[6], a_im[6];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            if (h & 1) {   // -conj(U[c][li]) x: Re row: -ur xr - ui xi, Im row: ui xr - ur xi
-                a_re[c] = -ur[c];
-                a_re[3 + c] = -ui[c];
-                a_im[c] = ui[c];
-                a_im[3 + c] = -ur[c];
-            } else {       // U[li][c] x: Re row: ur xr - ui xi, Im row: ui xr + ur xi
-                a_re[c] = ur[c];
-                a_re[3 + c] = -ui[c];
-                a_im[c] = ui[c];
-                a_im[3 + c] = ur[c];
-            }
+            a_re[c] = ur[c];
+            a_re[3 + c] = back ? ui[c] : -ui[c];
+            a_im[c] = back ? -ui[c] : ui[c];
+            a_im[3 + c] = ur[c];
         }
 #pragma unroll
         for (int k = 0; k < 6; k++) {
 #pragma unroll
-            for (int j = 0; j < NR; j++) {
-                const float bk = k < 3 ? v[j].re[k] : v[j].im[k - 3];
-                acc_re[j] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_re[k], bk, acc_re[j], 0, 0, 0);
-                acc_im[j] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_im[k], bk, acc_im[j], 0, 0, 0);
+            for (int m = 0; m < NR; m++) {
+                const float bk = k < 3 ? v[m].re[k] : v[m].im[k - 3];
+                acc_re[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_re[k], bk, acc_re[m], 0, 0, 0);
+                acc_im[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(a_im[k], bk, acc_im[m], 0, 0, 0);
             }
         }
     }
     if (!lv) return;
     CVec<float> acc[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) {
+    for (int m = 0; m < NR; m++) {
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            acc[j].re[c] = acc_re[j][c];
-            acc[j].im[c] = acc_im[j][c];
+            acc[m].re[c] = acc_re[m][c];
+            acc[m].im[c] = acc_im[m][c];
         }
     }
-    site_epilogue<SF, float, NR, RED>(A, s, r0, lv, acoef, acc, red);
+    site_epilogue<SF, float, NR, RED>(A, s, [&](int m) { return colmap(A, rhs0 + 4 * m + li); }, lv, acoef, acc, red);
 }
 
 // GUARD: launched inside a solver's block of iterations (may return at once);
@@ -938,19 +1022,25 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
     double red[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) red[j] = 0.0;
-    // The lane's right-hand sides rc..rc+NR-1 (rg divides blockDim, so a lane
-    // keeps its group in every tile).  Those at or beyond ncol (a block padded
-    // to a power of two) and those marked inactive are neither read nor written.
+    // The lane's right-hand sides (rg divides blockDim, so a lane keeps its
+    // group in every tile): rhs0 + grp*NR + j, or rhs0 + j*rg + grp on the
+    // matrix cores (one column of each group of rg per lane).  Those at or beyond ncol (a block padded to a power of two) and
+    // those marked inactive are neither read nor written.
+    constexpr bool IL = STAGE == MFMA_STAGE;
     const int ncol = A.nrhs > 1 ? A.nrhs : 1;
-    const int rc = rhs0 + (int)(threadIdx.x & (unsigned)(rg - 1)) * NR;
+    const int grp0 = (int)(threadIdx.x & (unsigned)(rg - 1));
+    auto cofs = [&](int lg, int j) { return IL ? j * rg + lg : lg * NR + j; };
     unsigned live = 0;
 #pragma unroll
-    for (int j = 0; j < NR; j++)
-        if (colvalid(A, rc + j, ncol) && (!A.cactive || A.cactive[colmap(A, rc + j)])) live |= 1u << j;
+    for (int j = 0; j < NR; j++) {
+        const int c = rhs0 + cofs(grp0, j);
+        if (colvalid(A, c, ncol) && (!A.cactive || A.cactive[colmap(A, c)])) live |= 1u << j;
+    }
     // xpay coefficient of each of the lane's right-hand sides, read once
     R acoef[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) acoef[j] = (A.acol && ((live >> j) & 1u)) ? (R)A.acol[colmap(A, rc + j)] : (R)A.a;
+    for (int j = 0; j < NR; j++)
+        acoef[j] = (A.acol && ((live >> j) & 1u)) ? (R)A.acol[colmap(A, rhs0 + cofs(grp0, j))] : (R)A.a;
     // Tiles of blockDim lanes.  sweep 0: XCD k (blocks b with b % 8 == k) sweeps
     // the contiguous tile range [k*ntile/8, (k+1)*ntile/8) in order, each of its
     // gridDim/8 blocks taking every (gridDim/8)-th tile.  sweep 1: block b takes
@@ -997,12 +1087,11 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         grp = tid - s * rg;
         inside = s < g.vh;
     }
-    const int r0 = rhs0 + grp * NR;   // == rc
     if constexpr (STAGE == MFMA_STAGE) {
         // every lane takes part in the matrix instructions of its site's block
-        dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, inside, r0, live, acoef, red);
+        dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, inside, rhs0, grp, live, acoef, red);
     } else {
-        if (inside && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, r0, live, acoef, red);
+        if (inside && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, rhs0 + grp * NR, live, acoef, red);
     }
     }
     if (RED) {
@@ -1017,7 +1106,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         }
         if (lane < rg) {
 #pragma unroll
-            for (int j = 0; j < NR; j++) lds[w * rg * NR + lane * NR + j] = red[j];
+            for (int j = 0; j < NR; j++) lds[w * rg * NR + cofs(lane, j)] = red[j];
         }
         __syncthreads();
         const int k = threadIdx.x;
@@ -1129,6 +1218,9 @@ hipError_t launch_tile(const DslashArgs &a, int rhs0, const DslashTile &t, hipSt
         case 201: return launch_cfg<GF, SF, R, 2, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
         case 401: return launch_cfg<GF, SF, R, 4, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
         case 801: return launch_cfg<GF, SF, R, 8, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 199: return launch_cfg<GF, SF, R, 2, -1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 399: return launch_cfg<GF, SF, R, 4, -1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
+        case 799: return launch_cfg<GF, SF, R, 8, -1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
         case 1601: return launch_cfg<GF, SF, R, 16, 1>(a, rhs0, t.rg, t.block, t.grid, t.sweep, st, nblocks);
         default: break;
         }

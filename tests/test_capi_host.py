@@ -140,6 +140,7 @@ def test_tune_set_validation(hisq):
     hisq.hisq_tune_set("int24", dims, 4, 4, 1, 1, 256, 0)
     hisq.hisq_tune_set("int30", dims, 1, 1, 1, -2, 256, 0)
     hisq.hisq_tune_set("int20", dims, 16, 4, 4, 5, 256, 0)      # matrix-core path, four lanes per site
+    hisq.hisq_tune_set("int20", dims, 8, 4, 2, -1, 256, 0)      # double-buffered hops, 4 right-hand sides per lane
     hisq.hisq_tune_set("int30", dims, 1, 1, 1, -2, 256, 0, long_recon=8)   # eight-parameter long links
     rep = hisq.hisq_tune_report()
     assert "recon 18 lattice 8x8x8x16 rhs-block 4: nr 2 rg 2 stage 1 block 256 grid 2048 sweep 1" in rep
@@ -149,7 +150,8 @@ def test_tune_set_validation(hisq):
            ("half", dims, 4, 2, 1, 1, 256, 0),          # nr*rg != block
            ("half", dims, 1, 1, 1, 3, 256, 0),          # stage
            ("half", dims, 2, 2, 1, 2, 256, 0),          # stages only with one right-hand side per lane
-           ("half", dims, 2, 2, 1, -1, 256, 0),         # double-buffered stages: one right-hand side only
+           ("half", dims, 16, 16, 1, -1, 256, 0),       # double-buffered stages: at most 8 right-hand sides per lane
+           ("half", dims, 2, 2, 1, -2, 256, 0),         # two-hop double-buffered stages: one right-hand side only
            ("half", dims, 1, 1, 1, -4, 256, 0),         # double-buffered stages of 1 or 2 hops
            ("half", dims, 16, 8, 2, 5, 256, 0),         # matrix-core path needs four lanes per site
            ("double", dims, 16, 4, 4, 5, 256, 0),       # matrix-core path is FP32 only

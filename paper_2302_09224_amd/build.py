@@ -28,6 +28,10 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-ffp-contract=fast",
+    # full unrolling of the stencil's hop loops also when they hold inline
+    # asm (whose cost estimate would otherwise stop the unroll and leave
+    # per-hop arrays indexed at run time, in scratch memory)
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -118,12 +118,10 @@ __device__ __forceinline__ int sext30(unsigned u) { return (int)((u & 0x3fffffff
 // 2^(e-127) for an 8-bit biased exponent e in [1,254]
 __device__ __forceinline__ float pow2_f32(unsigned e) { return __uint_as_float(e << 23); }
 // (a & m) | (b & ~m) in one instruction (the compiler splits the pattern
-// into an AND and an AND-OR once it knows the zero bits of b; in the fully
-// unrolled many-column stencils the asm statement costs more in register
-// allocation than it saves, so only the matrix-core path uses it)
+// into an AND and an AND-OR once it knows the zero bits of b)
 __device__ __forceinline__ unsigned bfi32(unsigned m, unsigned a, unsigned b) {
     unsigned r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(a), "v"(b));
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
     return r;
 }
 __device__ __forceinline__ double pow2_f64(unsigned e) {
@@ -240,7 +238,7 @@ template <class R> struct SpinorIO<SF_HALF16, R> {
 // 20-bit shared exponent (Appendix A): E = biased exponent of fl(M/(2^19-1)) + 1,
 // q = rint(v * 2^(127-E)), v = q * 2^(E-127).
 template <class R> struct SpinorIO<SF_INT20, R> {
-    template <bool BFI = false> static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f = 1.0f) {
+    static __device__ __forceinline__ CVec<R> decode(u32x4 w, float f = 1.0f) {
         // A field inside one word is a signed bit-field extract.  A field split
         // over two words has its high bits at the top of the earlier word, so
         // inserting the next word's low bits just below them gives the field
@@ -251,17 +249,11 @@ template <class R> struct SpinorIO<SF_INT20, R> {
         const float sl = sc * 0x1p-12f;
         CVec<R> v;
         v.re[0] = (float)((int)(w.x << 12) >> 12) * sc;
+        v.im[0] = (float)(int)bfi32(0xfff00000u, w.x, w.y << 12) * sl;
         v.re[1] = (float)((int)(w.y << 4) >> 12) * sc;
+        v.im[1] = (float)(int)bfi32(0xf0000000u, w.y, w.z << 12) * sl;
+        v.re[2] = (float)(int)bfi32(0xffff0000u, w.z, w.w << 12) * sl;
         v.im[2] = (float)((int)(w.w << 8) >> 12) * sc;
-        if constexpr (BFI) {
-            v.im[0] = (float)(int)bfi32(0xfff00000u, w.x, w.y << 12) * sl;
-            v.im[1] = (float)(int)bfi32(0xf0000000u, w.y, w.z << 12) * sl;
-            v.re[2] = (float)(int)bfi32(0xffff0000u, w.z, w.w << 12) * sl;
-        } else {
-            v.im[0] = (float)(int)((w.x & 0xfff00000u) | ((w.y & 0xffu) << 12)) * sl;
-            v.im[1] = (float)(int)((w.y & 0xf0000000u) | ((w.z & 0xffffu) << 12)) * sl;
-            v.re[2] = (float)(int)((w.z & 0xffff0000u) | ((w.w & 0xfu) << 12)) * sl;
-        }
         return v;
     }
     static __device__ __forceinline__ u32x4 encode(const CVec<R> &vin) {

@@ -964,12 +964,7 @@ __device__ __forceinline__ void dslash_site_mfma(const DslashArgs &A, int s, boo
         const float fy = (back && ssign) ? -f : f;
         CVec<float> v[NR];
 #pragma unroll
-        for (int m = 0; m < NR; m++) {
-            if constexpr (SF == SF_INT20)
-                v[m] = SpinorIO<SF_INT20, float>::template decode<true>(spin_load<SF>(colp[m], vh, ss).w, fy);
-            else
-                v[m] = spin_decode<float>(spin_load<SF>(colp[m], vh, ss), fy);
-        }
+        for (int m = 0; m < NR; m++) v[m] = spin_decode<float>(spin_load<SF>(colp[m], vh, ss), fy);
         if (back && !ssign) {
 #pragma unroll
             for (int c = 0; c < 3; c++) {

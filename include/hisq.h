@@ -21,14 +21,13 @@
  *    synchronised) and waits for each timing before the real launch is
  *    enqueued.  HISQ_TUNE=0, hisq_tune_set and hisq_tune_load avoid it.
  *    Gauge packing synchronises `stream` (the scales are returned on the host).
- *    The CG solvers (hisq_cg_solve, hisq_multishift_cg_solve,
- *    hisq_cg_solve_batched) run on a library-owned non-blocking stream of the
- *    current device (default priority), ordered after the work enqueued on
- *    `stream` before the call by an event (graphs cannot be captured on the
- *    null stream), and return after that stream has drained: the results are
- *    complete on return.  Solver calls on one device are serialised by a
- *    lock.  hisq_bicgstab_solve enqueues on `stream` and synchronises it for
- *    every scalar.
+ *    The solvers (hisq_cg_solve, hisq_multishift_cg_solve,
+ *    hisq_cg_solve_batched, hisq_bicgstab_solve) run on a library-owned
+ *    non-blocking stream of the current device (default priority), ordered
+ *    after the work enqueued on `stream` before the call by an event (graphs
+ *    cannot be captured on the null stream), and return after that stream has
+ *    drained: the results are complete on return.  Calls of one solver on one
+ *    device are serialised by a lock.
  *  - Errors are returned as hisq_status; no C++ exception crosses the ABI.
  *    hisq_last_error() gives a message for the calling thread's last error.
  *  - Lattice: dims = {X, Y, Z, T}, each even and >= 4; site index
@@ -367,8 +366,12 @@ size_t hisq_bicgstab_workspace_bytes(const int dims[4], int l, hisq_fmt sloppy);
  * stats: iters = operator applications (2 per BiCG step), reliable_updates,
  * true_resid, seconds.  p->maxiter bounds the operator applications
  * (HISQ_ENOCONV beyond, x is the last iterate); HISQ_EBREAKDOWN when a BiCG
- * or minimal-residual denominator vanishes.  Runs on `stream`, which it
- * synchronises for every scalar. */
+ * or minimal-residual denominator vanishes.  Runs on a library-owned stream
+ * ordered after `stream` and returns when x is written: every scalar of the
+ * method is formed on the device, each cycle (l BiCG steps and the
+ * minimal-residual step) is enqueued as a whole (replayed as a captured
+ * hipGraph when p->use_graph) and followed by one synchronisation, where the
+ * reliable-update decision is taken. */
 hisq_status hisq_bicgstab_solve(double *x, const double *b, const hisq_gauge *g64, const hisq_gauge *gs,
                                 double mass, double tol, int l, hisq_fmt sloppy,
                                 const hisq_solver_params *p, void *ws, size_t ws_bytes,

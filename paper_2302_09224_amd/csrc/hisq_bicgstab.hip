@@ -6,8 +6,12 @@
 // every update (Sec. 3.1 item 1).  Reliable updates (Sec. 3, delta): when the
 // iterated |r_0| drops by delta below its maximum since the last update (or
 // meets the target), r = b - M x is computed with the FP64 operator and
-// replaces r_0.  Scalars are formed on the host from device reductions (fixed
-// reduction order, reproducible); every vector operation is a HIP kernel.
+// replaces r_0.  Every scalar (rho, alpha, beta, tau, sigma, gamma, omega) is
+// formed on the device by one-thread kernels from fixed-order reductions, and
+// every vector kernel reads its coefficients from device memory, so a whole
+// cycle (l BiCG steps and the minimal-residual step) is enqueued without the
+// host, replayed as a captured hipGraph, and followed by one synchronisation,
+// where the host reads |r_0|^2 and decides on a reliable update.
 //
 // A whole-lattice field is two single-parity fields back to back: the even
 // sites, then the odd sites, each in the usual packed layout of Vh sites.
@@ -16,8 +20,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <complex>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hisq_internal.h"
@@ -26,26 +30,46 @@ namespace hisq {
 
 namespace {
 
-typedef std::complex<double> cplx;
 constexpr int BL_MAXK = 8;    // vectors combined or dotted in one pass
 constexpr int BL_BLOCK = 256;
+
+constexpr int BL_MAXL = HISQ_MAX_BICGSTAB_L;
 
 struct VecList {
     const char *p[BL_MAXK];
 };
-struct CoefList {
-    double re[BL_MAXK], im[BL_MAXK];
+
+// device scalars of one solve (complex values as re, im)
+struct BlCtl {
+    int stop;     // guard of every kernel of a cycle: 0 while running, -1 after a breakdown
+    int broke;    // 1: a BiCG or minimal-residual denominator vanished, 2: non-finite residual
+    double one[2];
+    double rho0[2], alpha[2], omega[2];
+    double beta_neg[2], alpha_neg[2], tau_neg[2];
+    double tau[BL_MAXL + 1][BL_MAXL + 1][2];
+    double sigma[BL_MAXL + 1];
+    double gp[BL_MAXL + 1][2], gm[BL_MAXL + 1][2];
+    double cx[BL_MAXK][2], cu[BL_MAXK][2], cr[BL_MAXK][2];   // coefficients of the closing updates
+    double rs2;
+};
+// what the host reads after a cycle
+struct BlSummary {
+    int stop, broke;
+    double rs2;
 };
 
 __device__ __forceinline__ size_t bl_tid() { return (size_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ size_t bl_stride() { return (size_t)gridDim.x * blockDim.x; }
 
 // y = a*y + sum_k c_k x_k on the 2*vh sites of whole-lattice fields (half h at
-// byte offset h*fb); partial[block] = |y_new|^2 (stored values) if partial
+// byte offset h*fb); a and c (K complex values) in device memory;
+// partial[block] = |y_new|^2 (stored values) if partial
 template <int SF, class R>
-__global__ void k_bl_combine(char *y, double are, double aim, int read_y, VecList xs, CoefList c, int K, size_t vh,
-                             size_t fb, double *partial) {
+__global__ void k_bl_combine(char *y, const double *a, int read_y, VecList xs, const double *c, int K, size_t vh,
+                             size_t fb, double *partial, const int *stop) {
     __shared__ double lds[8];
+    if (*stop < 0) return;
+    const double are = a[0], aim = a[1];
     double acc[1] = {0.0};
     for (size_t i = bl_tid(); i < 2 * vh; i += bl_stride()) {
         const size_t h = i >= vh ? 1 : 0, s = i - h * vh;
@@ -62,7 +86,7 @@ __global__ void k_bl_combine(char *y, double are, double aim, int read_y, VecLis
         }
         for (int k = 0; k < K; k++) {
             const CVec<R> v = SpinorIO<SF, R>::load(xs.p[k] + h * fb, vh, s);
-            const R cr = (R)c.re[k], ci = (R)c.im[k];
+            const R cr = (R)c[2 * k], ci = (R)c[2 * k + 1];
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 o.re[q] = fma(cr, v.re[q], fma(-ci, v.im[q], o.re[q]));
@@ -83,8 +107,9 @@ __global__ void k_bl_combine(char *y, double are, double aim, int read_y, VecLis
 
 // <x_k, y> for k < K (re, im) and |y|^2: partial[(block)*(2K+1) + v]
 template <int SF, class R>
-__global__ void k_bl_dots(VecList xs, int K, const char *y, size_t vh, size_t fb, double *partial) {
+__global__ void k_bl_dots(VecList xs, int K, const char *y, size_t vh, size_t fb, double *partial, const int *stop) {
     __shared__ double lds[4 * (2 * BL_MAXK + 1)];
+    if (*stop < 0) return;
     double acc[2 * BL_MAXK + 1];
 #pragma unroll
     for (int v = 0; v < 2 * BL_MAXK + 1; v++) acc[v] = 0.0;
@@ -126,9 +151,11 @@ __global__ void k_bl_fin(const double *partial, int nb, int nv, double *out) {
     }
 }
 
-// x64 += sum_k c_k v_k (FP64 solution, sloppy vectors)
+// x64 += sum_k c_k v_k (FP64 solution, sloppy vectors; c in device memory)
 template <int SF, class R>
-__global__ void k_bl_xupdate(char *x64, VecList vs, CoefList c, int K, size_t vh, size_t fb, size_t fb64) {
+__global__ void k_bl_xupdate(char *x64, VecList vs, const double *c, int K, size_t vh, size_t fb, size_t fb64,
+                             const int *stop) {
+    if (*stop < 0) return;
     for (size_t i = bl_tid(); i < 2 * vh; i += bl_stride()) {
         const size_t h = i >= vh ? 1 : 0, s = i - h * vh;
         CVec<double> x = SpinorIO<SF_F64, double>::load(x64 + h * fb64, vh, s);
@@ -136,12 +163,155 @@ __global__ void k_bl_xupdate(char *x64, VecList vs, CoefList c, int K, size_t vh
             const CVec<R> v = SpinorIO<SF, R>::load(vs.p[k] + h * fb, vh, s);
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                x.re[q] += c.re[k] * (double)v.re[q] - c.im[k] * (double)v.im[q];
-                x.im[q] += c.re[k] * (double)v.im[q] + c.im[k] * (double)v.re[q];
+                x.re[q] += c[2 * k] * (double)v.re[q] - c[2 * k + 1] * (double)v.im[q];
+                x.im[q] += c[2 * k] * (double)v.im[q] + c[2 * k + 1] * (double)v.re[q];
             }
         }
         SpinorIO<SF_F64, double>::store(x64 + h * fb64, vh, s, x);
     }
+}
+
+// ---- the scalars of the method, one thread ----
+enum BlOp { BL_START, BL_RHO, BL_GAM, BL_TAU, BL_SIGMA, BL_MR, BL_RS2 };
+
+__device__ __forceinline__ void bl_mul(const double *a, const double *b, double *o) {
+    const double re = a[0] * b[0] - a[1] * b[1], im = a[0] * b[1] + a[1] * b[0];
+    o[0] = re;
+    o[1] = im;
+}
+// a / b with Smith's scaling (no overflow of |b|^2)
+__device__ __forceinline__ void bl_div(const double *a, const double *b, double *o) {
+    double re, im;
+    if (fabs(b[0]) >= fabs(b[1])) {
+        const double r = b[1] / b[0], d = b[0] + b[1] * r;
+        re = (a[0] + a[1] * r) / d;
+        im = (a[1] - a[0] * r) / d;
+    } else {
+        const double r = b[0] / b[1], d = b[0] * r + b[1];
+        re = (a[0] * r + a[1]) / d;
+        im = (a[1] * r - a[0]) / d;
+    }
+    o[0] = re;
+    o[1] = im;
+}
+__device__ __forceinline__ bool bl_zero(const double *a) { return a[0] == 0.0 && a[1] == 0.0; }
+__device__ __forceinline__ bool bl_finite(const double *a) { return __builtin_isfinite(a[0]) && __builtin_isfinite(a[1]); }
+
+// res: the finished reduction of the step's dot products (<x, y> as re, im, then |y|^2)
+__global__ void k_bl_step(BlCtl *c, const double *res, int op, int i, int j, int l) {
+    if (threadIdx.x || c->stop < 0) return;
+    auto fail = [&](int code) {
+        c->broke = code;
+        c->stop = -1;
+    };
+    switch (op) {
+    case BL_START: {   // rho0 = -omega rho0
+        double t[2];
+        bl_mul(c->omega, c->rho0, t);
+        c->rho0[0] = -t[0];
+        c->rho0[1] = -t[1];
+        break;
+    }
+    case BL_RHO: {     // rho1 = <r~, r_j>; beta = alpha rho1 / rho0; rho0 = rho1
+        const double rho1[2] = {res[0], res[1]};
+        if (bl_zero(c->rho0) || !bl_finite(rho1)) {
+            fail(1);
+            break;
+        }
+        double t[2], beta[2];
+        bl_mul(c->alpha, rho1, t);
+        bl_div(t, c->rho0, beta);
+        c->rho0[0] = rho1[0];
+        c->rho0[1] = rho1[1];
+        c->beta_neg[0] = -beta[0];
+        c->beta_neg[1] = -beta[1];
+        break;
+    }
+    case BL_GAM: {     // gamma = <r~, u_{j+1}>; alpha = rho0 / gamma
+        const double gam[2] = {res[0], res[1]};
+        if (bl_zero(gam) || !bl_finite(gam)) {
+            fail(1);
+            break;
+        }
+        bl_div(c->rho0, gam, c->alpha);
+        c->alpha_neg[0] = -c->alpha[0];
+        c->alpha_neg[1] = -c->alpha[1];
+        break;
+    }
+    case BL_TAU: {     // tau_ij = <r_i, r_j> / sigma_i
+        c->tau[i][j][0] = res[0] / c->sigma[i];
+        c->tau[i][j][1] = res[1] / c->sigma[i];
+        c->tau_neg[0] = -c->tau[i][j][0];
+        c->tau_neg[1] = -c->tau[i][j][1];
+        break;
+    }
+    case BL_SIGMA: {   // sigma_j = |r_j|^2; gamma'_j = <r_j, r_0> / sigma_j
+        const double s2 = res[2];
+        c->sigma[j] = s2;
+        if (!(s2 > 0.0) || !__builtin_isfinite(s2)) {
+            fail(1);
+            break;
+        }
+        c->gp[j][0] = res[0] / s2;
+        c->gp[j][1] = -res[1] / s2;
+        break;
+    }
+    case BL_MR: {      // gamma_l, gamma_j (back substitution), gamma''_j; the closing coefficients
+        double gpp[BL_MAXL + 1][2];
+        c->gm[l][0] = c->gp[l][0];
+        c->gm[l][1] = c->gp[l][1];
+        c->omega[0] = c->gm[l][0];
+        c->omega[1] = c->gm[l][1];
+        for (int jj = l - 1; jj >= 1; jj--) {
+            double sr = c->gp[jj][0], si = c->gp[jj][1];
+            for (int ii = jj + 1; ii <= l; ii++) {
+                double t[2];
+                bl_mul(c->tau[jj][ii], c->gm[ii], t);
+                sr -= t[0];
+                si -= t[1];
+            }
+            c->gm[jj][0] = sr;
+            c->gm[jj][1] = si;
+        }
+        for (int jj = 1; jj < l; jj++) {
+            double sr = c->gm[jj + 1][0], si = c->gm[jj + 1][1];
+            for (int ii = jj + 1; ii < l; ii++) {
+                double t[2];
+                bl_mul(c->tau[jj][ii], c->gm[ii + 1], t);
+                sr += t[0];
+                si += t[1];
+            }
+            gpp[jj][0] = sr;
+            gpp[jj][1] = si;
+        }
+        // x += gamma_1 r_0 + sum_{j<l} gamma''_j r_j; u_0 -= sum gamma_j u_j; r_0 -= sum gamma'_j r_j
+        c->cx[0][0] = c->gm[1][0];
+        c->cx[0][1] = c->gm[1][1];
+        for (int jj = 1; jj < l; jj++) {
+            c->cx[jj][0] = gpp[jj][0];
+            c->cx[jj][1] = gpp[jj][1];
+        }
+        for (int jj = 1; jj <= l; jj++) {
+            c->cu[jj - 1][0] = -c->gm[jj][0];
+            c->cu[jj - 1][1] = -c->gm[jj][1];
+            c->cr[jj - 1][0] = -c->gp[jj][0];
+            c->cr[jj - 1][1] = -c->gp[jj][1];
+        }
+        break;
+    }
+    case BL_RS2:       // |r_0|^2 after the cycle
+        c->rs2 = res[0];
+        if (!__builtin_isfinite(res[0])) fail(2);
+        break;
+    default: break;
+    }
+}
+
+__global__ void k_bl_summary(const BlCtl *c, BlSummary *o) {
+    if (threadIdx.x) return;
+    o->stop = c->stop;
+    o->broke = c->broke;
+    o->rs2 = c->rs2;
 }
 
 // canonical lexicographic [V][3] <-> (even field, odd field) in F64 layout
@@ -212,74 +382,60 @@ struct Bl {
     long matvecs = 0, f64apps = 0;
     double alg = 0.0;
 
-    hisq_status fetch(int nv) {
-        hipLaunchKernelGGL(k_bl_fin, dim3(1), dim3(BL_BLOCK), 0, st, partial, nbl, nv, dres);
-        HISQ_TRY_HIP(hipGetLastError());
-        HISQ_TRY_HIP(hipMemcpyAsync(hres, dres, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-        HISQ_TRY_HIP(hipStreamSynchronize(st));
-        return HISQ_OK;
-    }
+    BlCtl *ctl = nullptr;         // device scalars
+    const int *stopp = nullptr;   // &ctl->stop
 
-    // y = a*y + sum c_k x_k; *norm2 = |y|^2 if norm2
-    hisq_status combine(char *y, cplx a, bool read_y, const std::vector<const char *> &x, const std::vector<cplx> &c,
-                        double *norm2) {
+    // y = a*y + sum c_k x_k (a, c: device addresses of complex values); with
+    // norm, |y|^2 is reduced into dres[0]
+    hisq_status combine(char *y, const double *a, bool read_y, const std::vector<const char *> &x, const double *c,
+                        bool norm) {
         VecList xl;
-        CoefList cl;
         memset(&xl, 0, sizeof(xl));
-        memset(&cl, 0, sizeof(cl));
         const int K = (int)x.size();
         if (K > BL_MAXK) return set_error(HISQ_EINVAL, "bicgstab: too many vectors in one update");
-        for (int k = 0; k < K; k++) {
-            xl.p[k] = x[k];
-            cl.re[k] = c[k].real();
-            cl.im[k] = c[k].imag();
-        }
-        double *pp = norm2 ? partial : nullptr;
+        for (int k = 0; k < K; k++) xl.p[k] = x[k];
+        double *pp = norm ? partial : nullptr;
         HISQ_BL_DISPATCH(f.spinor, f.compute,
-                         hipLaunchKernelGGL((k_bl_combine<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, y, a.real(),
-                                            a.imag(), read_y ? 1 : 0, xl, cl, K, vh, fb, pp));
+                         hipLaunchKernelGGL((k_bl_combine<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, y, a,
+                                            read_y ? 1 : 0, xl, c, K, vh, fb, pp, stopp));
         HISQ_TRY_HIP(hipGetLastError());
         alg += 2.0 * vh * spinor_site_bytes(f.spinor) * (K + (read_y ? 2 : 1));
-        if (norm2) {
-            HISQ_TRY(fetch(1));
-            *norm2 = hres[0];
+        if (norm) {
+            hipLaunchKernelGGL(k_bl_fin, dim3(1), dim3(BL_BLOCK), 0, st, partial, nbl, 1, dres);
+            HISQ_TRY_HIP(hipGetLastError());
         }
         return HISQ_OK;
     }
 
-    // d[k] = <x_k, y>, *ynorm2 = |y|^2
-    hisq_status dots(const std::vector<const char *> &x, const char *y, std::vector<cplx> &d, double *ynorm2) {
+    // dres = (<x, y> re, im, |y|^2)
+    hisq_status dot(const char *x, const char *y) {
         VecList xl;
         memset(&xl, 0, sizeof(xl));
-        const int K = (int)x.size();
-        if (K > BL_MAXK) return set_error(HISQ_EINVAL, "bicgstab: too many dot products in one pass");
-        for (int k = 0; k < K; k++) xl.p[k] = x[k];
+        xl.p[0] = x;
         HISQ_BL_DISPATCH(f.spinor, f.compute,
-                         hipLaunchKernelGGL((k_bl_dots<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, xl, K, y, vh, fb,
-                                            partial));
+                         hipLaunchKernelGGL((k_bl_dots<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, xl, 1, y, vh, fb,
+                                            partial, stopp));
         HISQ_TRY_HIP(hipGetLastError());
-        alg += 2.0 * vh * spinor_site_bytes(f.spinor) * (K + 1);
-        HISQ_TRY(fetch(2 * K + 1));
-        d.resize(K);
-        for (int k = 0; k < K; k++) d[k] = cplx(hres[2 * k], hres[2 * k + 1]);
-        if (ynorm2) *ynorm2 = hres[2 * K];
+        hipLaunchKernelGGL(k_bl_fin, dim3(1), dim3(BL_BLOCK), 0, st, partial, nbl, 3, dres);
+        HISQ_TRY_HIP(hipGetLastError());
+        alg += 2.0 * vh * spinor_site_bytes(f.spinor) * 2;
         return HISQ_OK;
     }
 
-    hisq_status xupdate(char *x64, const std::vector<const char *> &v, const std::vector<cplx> &c) {
+    hisq_status step(int op, int i = 0, int j = 0, int l = 0) {
+        hipLaunchKernelGGL(k_bl_step, dim3(1), dim3(64), 0, st, ctl, dres, op, i, j, l);
+        HISQ_TRY_HIP(hipGetLastError());
+        return HISQ_OK;
+    }
+
+    hisq_status xupdate(char *x64, const std::vector<const char *> &v, const double *c) {
         VecList vl;
-        CoefList cl;
         memset(&vl, 0, sizeof(vl));
-        memset(&cl, 0, sizeof(cl));
         const int K = (int)v.size();
-        for (int k = 0; k < K; k++) {
-            vl.p[k] = v[k];
-            cl.re[k] = c[k].real();
-            cl.im[k] = c[k].imag();
-        }
+        for (int k = 0; k < K; k++) vl.p[k] = v[k];
         HISQ_BL_DISPATCH(f.spinor, f.compute,
-                         hipLaunchKernelGGL((k_bl_xupdate<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, x64, vl, cl, K,
-                                            vh, fb, fb64));
+                         hipLaunchKernelGGL((k_bl_xupdate<SFc, Rc>), dim3(nbl), dim3(BL_BLOCK), 0, st, x64, vl, c, K,
+                                            vh, fb, fb64, stopp));
         HISQ_TRY_HIP(hipGetLastError());
         alg += 2.0 * vh * (96.0 + K * spinor_site_bytes(f.spinor));
         return HISQ_OK;
@@ -298,6 +454,7 @@ struct Bl {
     }
 
     // out = M in = 2m in + D in (sloppy): per output parity p, out_p = D in_q + 2m in_p
+    // (skipped after a breakdown in the cycle)
     hisq_status matvec(char *out, const char *in) {
         for (int p = 0; p < 2; p++) {
             DslashArgs a = dargs(gs, f.spinor);
@@ -306,6 +463,7 @@ struct Bl {
             a.x = in + p * fb;
             a.a = 2.0 * mass;
             a.parity = p;
+            a.guard = Guard{stopp, 0, 0};
             HISQ_TRY_HIP(launch_dslash(a, f, plan_s, st, nullptr));
         }
         matvecs++;
@@ -351,9 +509,19 @@ struct Bl {
 
 inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// library-owned stream per device (default priority), ordered after the caller's
+// stream with an event; a cycle is captured from it (the caller's stream may be
+// the null stream, which cannot be captured)
+struct BlDev {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    std::mutex mu;
+};
+BlDev g_bldev[64];
+
 struct BlLayout {
     size_t fb, fb64, part_doubles, total;
-    size_t off_part, off_dres, off_x64, off_b64, off_r64, off_vec;
+    size_t off_part, off_dres, off_ctl, off_x64, off_b64, off_r64, off_vec;
     int nvec;
 };
 
@@ -369,6 +537,8 @@ BlLayout bl_layout(const Geom &g, int l, const hisq_fmt &f) {
     off += al256(L.part_doubles * sizeof(double));
     L.off_dres = off;
     off += al256(64 * sizeof(double));
+    L.off_ctl = off;
+    off += al256(sizeof(BlCtl));
     L.off_x64 = off;
     off += 2 * L.fb64;
     L.off_b64 = off;
@@ -433,10 +603,23 @@ extern "C" hisq_status hisq_bicgstab_solve(double *x, const double *b, const his
     B.g64 = g64;
     B.gs = gs;
     B.mass = mass;
-    B.st = (hipStream_t)stream;
+    int dev = 0;
+    HISQ_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(HISQ_EINVAL, "device index %d out of range", dev);
+    BlDev &dv = g_bldev[dev];
+    std::unique_lock<std::mutex> lk(dv.mu);
+    if (!dv.stream) {
+        HISQ_TRY_HIP(hipStreamCreateWithFlags(&dv.stream, hipStreamNonBlocking));
+        HISQ_TRY_HIP(hipEventCreateWithFlags(&dv.ev, hipEventDisableTiming));
+    }
+    HISQ_TRY_HIP(hipEventRecord(dv.ev, (hipStream_t)stream));
+    HISQ_TRY_HIP(hipStreamWaitEvent(dv.stream, dv.ev, 0));
+    B.st = dv.stream;
     B.nbl = blas_blocks(2 * (size_t)g.vh);
     B.partial = (double *)(w + L.off_part);
     B.dres = (double *)(w + L.off_dres);
+    B.ctl = (BlCtl *)(w + L.off_ctl);
+    B.stopp = &B.ctl->stop;
     HISQ_TRY_HIP(hipHostMalloc((void **)&B.hres, 64 * sizeof(double), hipHostMallocDefault));
     struct Free {
         double *p;
@@ -495,98 +678,104 @@ extern "C" hisq_status hisq_bicgstab_solve(double *x, const double *b, const his
         HISQ_TRY(B.to_sloppy(r[0], r64));
         HISQ_TRY(B.to_sloppy(rt, r64));
         HISQ_TRY_HIP(hipMemsetAsync(u[0], 0, 2 * L.fb, B.st));
-        cplx rho0(1.0, 0.0), alpha(0.0, 0.0), omega(1.0, 0.0);
-        double rmax2 = r2, rs2 = r2;
-        std::vector<cplx> d;
+        {   // rho0 = 1, alpha = 0, omega = 1
+            BlCtl c0;
+            memset(&c0, 0, sizeof(c0));
+            c0.one[0] = c0.rho0[0] = c0.omega[0] = 1.0;
+            HISQ_TRY_HIP(hipMemcpyAsync(B.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, B.st));
+            HISQ_TRY_HIP(hipStreamSynchronize(B.st));
+        }
+        BlCtl *c = B.ctl;
+        // one cycle: l BiCG steps, then the minimal-residual step by modified Gram-Schmidt
+        auto enq_cycle = [&]() -> hisq_status {
+            HISQ_TRY(B.step(BL_START));
+            for (int j = 0; j < l; j++) {
+                HISQ_TRY(B.dot(rt, r[j]));
+                HISQ_TRY(B.step(BL_RHO));
+                for (int i = 0; i <= j; i++) HISQ_TRY(B.combine(u[i], c->beta_neg, true, {r[i]}, c->one, false));
+                HISQ_TRY(B.matvec(u[j + 1], u[j]));
+                HISQ_TRY(B.dot(rt, u[j + 1]));
+                HISQ_TRY(B.step(BL_GAM));
+                for (int i = 0; i <= j; i++) HISQ_TRY(B.combine(r[i], c->one, true, {u[i + 1]}, c->alpha_neg, false));
+                HISQ_TRY(B.matvec(r[j + 1], r[j]));
+                HISQ_TRY(B.xupdate(x64, {u[0]}, c->alpha));
+            }
+            for (int j = 1; j <= l; j++) {
+                for (int i = 1; i < j; i++) {
+                    HISQ_TRY(B.dot(r[i], r[j]));
+                    HISQ_TRY(B.step(BL_TAU, i, j));
+                    HISQ_TRY(B.combine(r[j], c->one, true, {r[i]}, c->tau_neg, false));
+                }
+                HISQ_TRY(B.dot(r[0], r[j]));                  // <r_0, r_j> and |r_j|^2
+                HISQ_TRY(B.step(BL_SIGMA, 0, j));
+            }
+            HISQ_TRY(B.step(BL_MR, 0, 0, l));
+            std::vector<const char *> vx{r[0]}, vr, vu;
+            for (int j = 1; j < l; j++) vx.push_back(r[j]);
+            for (int j = 1; j <= l; j++) {
+                vr.push_back(r[j]);
+                vu.push_back(u[j]);
+            }
+            HISQ_TRY(B.xupdate(x64, vx, &c->cx[0][0]));
+            HISQ_TRY(B.combine(u[0], c->one, true, vu, &c->cu[0][0], false));
+            HISQ_TRY(B.combine(r[0], c->one, true, vr, &c->cr[0][0], true));
+            HISQ_TRY(B.step(BL_RS2));
+            hipLaunchKernelGGL(k_bl_summary, dim3(1), dim3(64), 0, B.st, c, (BlSummary *)B.dres);
+            HISQ_TRY_HIP(hipGetLastError());
+            return HISQ_OK;
+        };
+        hipGraphExec_t exec = nullptr;
+        struct ExecFree {
+            hipGraphExec_t *e;
+            ~ExecFree() {
+                if (*e) (void)hipGraphExecDestroy(*e);
+            }
+        } exec_free{&exec};
+        double cyc_alg = 0.0;
+        double rmax2 = r2;
         while (status == HISQ_OK) {
             if (B.matvecs >= q.maxiter) {
                 status = set_error(HISQ_ENOCONV, "bicgstab: no convergence in %ld operator applications", B.matvecs);
                 break;
             }
-            rho0 = -omega * rho0;
-            // ---- BiCG part ----
-            bool broke = false;
-            for (int j = 0; j < l && !broke; j++) {
-                HISQ_TRY(B.dots({rt}, r[j], d, nullptr));
-                const cplx rho1 = d[0];
-                if (std::abs(rho0) == 0.0 || !std::isfinite(std::abs(rho1))) {
-                    broke = true;
-                    break;
+            if (q.use_graph) {
+                if (!exec) {
+                    const double a0 = B.alg;
+                    hipGraph_t gr = nullptr;
+                    HISQ_TRY_HIP(hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
+                    hisq_status cs = enq_cycle();
+                    hipError_t e = hipStreamEndCapture(B.st, &gr);
+                    if (cs != HISQ_OK) {
+                        if (gr) (void)hipGraphDestroy(gr);
+                        return cs;
+                    }
+                    HISQ_TRY_HIP(e);
+                    e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    HISQ_TRY_HIP(e);
+                    cyc_alg = B.alg - a0;
+                    B.alg = a0;
+                    B.matvecs -= 2 * l;
                 }
-                const cplx beta = alpha * rho1 / rho0;
-                rho0 = rho1;
-                for (int i = 0; i <= j; i++) HISQ_TRY(B.combine(u[i], -beta, true, {r[i]}, {cplx(1.0, 0.0)}, nullptr));
-                HISQ_TRY(B.matvec(u[j + 1], u[j]));
-                HISQ_TRY(B.dots({rt}, u[j + 1], d, nullptr));
-                const cplx gam = d[0];
-                if (std::abs(gam) == 0.0 || !std::isfinite(std::abs(gam))) {
-                    broke = true;
-                    break;
-                }
-                alpha = rho0 / gam;
-                for (int i = 0; i <= j; i++)
-                    HISQ_TRY(B.combine(r[i], cplx(1.0, 0.0), true, {u[i + 1]}, {-alpha}, nullptr));
-                HISQ_TRY(B.matvec(r[j + 1], r[j]));
-                HISQ_TRY(B.xupdate(x64, {u[0]}, {alpha}));
+                HISQ_TRY_HIP(hipGraphLaunch(exec, B.st));
+                B.alg += cyc_alg;
+                B.matvecs += 2 * l;
+            } else {
+                HISQ_TRY(enq_cycle());
             }
-            // ---- minimal-residual part (modified Gram-Schmidt) ----
-            std::vector<std::vector<cplx>> tau(l + 1, std::vector<cplx>(l + 1));
-            std::vector<double> sigma(l + 1, 0.0);
-            std::vector<cplx> gp(l + 1), gm(l + 1), gpp(l + 1);
-            for (int j = 1; j <= l && !broke; j++) {
-                for (int i = 1; i < j; i++) {
-                    HISQ_TRY(B.dots({r[i]}, r[j], d, nullptr));
-                    tau[i][j] = d[0] / sigma[i];
-                    HISQ_TRY(B.combine(r[j], cplx(1.0, 0.0), true, {r[i]}, {-tau[i][j]}, nullptr));
-                }
-                double s2 = 0.0;
-                HISQ_TRY(B.dots({r[0]}, r[j], d, &s2));    // <r_0, r_j> and |r_j|^2
-                sigma[j] = s2;
-                if (!(s2 > 0.0) || !std::isfinite(s2)) {
-                    broke = true;
-                    break;
-                }
-                gp[j] = std::conj(d[0]) / s2;               // <r_j, r_0> / sigma_j
-            }
-            if (broke) {
-                status = set_error(HISQ_EBREAKDOWN, "bicgstab: breakdown after %ld operator applications", B.matvecs);
-                break;
-            }
-            gm[l] = gp[l];
-            omega = gm[l];
-            for (int j = l - 1; j >= 1; j--) {
-                cplx s = gp[j];
-                for (int i = j + 1; i <= l; i++) s -= tau[j][i] * gm[i];
-                gm[j] = s;
-            }
-            for (int j = 1; j < l; j++) {
-                cplx s = gm[j + 1];
-                for (int i = j + 1; i < l; i++) s += tau[j][i] * gm[i + 1];
-                gpp[j] = s;
-            }
-            {
-                std::vector<const char *> vx{r[0]};
-                std::vector<cplx> cx{gm[1]};
-                for (int j = 1; j < l; j++) {
-                    vx.push_back(r[j]);
-                    cx.push_back(gpp[j]);
-                }
-                HISQ_TRY(B.xupdate(x64, vx, cx));
-                std::vector<const char *> vr, vu;
-                std::vector<cplx> cr, cu;
-                for (int j = 1; j <= l; j++) {
-                    vr.push_back(r[j]);
-                    cr.push_back(-gp[j]);
-                    vu.push_back(u[j]);
-                    cu.push_back(-gm[j]);
-                }
-                HISQ_TRY(B.combine(u[0], cplx(1.0, 0.0), true, vu, cu, nullptr));
-                HISQ_TRY(B.combine(r[0], cplx(1.0, 0.0), true, vr, cr, &rs2));
-            }
-            if (!std::isfinite(rs2)) {
+            HISQ_TRY_HIP(hipMemcpyAsync(B.hres, B.dres, sizeof(BlSummary), hipMemcpyDeviceToHost, B.st));
+            HISQ_TRY_HIP(hipStreamSynchronize(B.st));
+            BlSummary sum;
+            memcpy(&sum, B.hres, sizeof(sum));
+            if (sum.broke == 2) {
                 status = set_error(HISQ_EBREAKDOWN, "bicgstab: non-finite residual");
                 break;
             }
+            if (sum.broke) {
+                status = set_error(HISQ_EBREAKDOWN, "bicgstab: breakdown after %ld operator applications", B.matvecs);
+                break;
+            }
+            const double rs2 = sum.rs2;
             rmax2 = std::max(rmax2, rs2);
             // ---- reliable update ----
             if (rs2 < delta2 * rmax2 || rs2 <= tol2) {

@@ -417,9 +417,9 @@ def main():
                     help="long-link storage of the solver's operators (12: two rows)")
     ap.add_argument("--ms-recon", type=int, default=8, choices=(8, 12, 18),
                     help="long-link storage of the multi-shift operator (8: eight parameters)")
-    ap.add_argument("--batch-refine", type=int, default=1, choices=(0, 1, 2),
+    ap.add_argument("--batch-refine", type=int, default=3, choices=(0, 1, 2, 3),
                     help="refine the shifted systems together (1), together while the base is refined "
-                         "concurrently (2), or one after another (0)")
+                         "concurrently (2), together with the base in the same block (3), or one after another (0)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the 16^4 CG-stability table (not part of the timed step)")

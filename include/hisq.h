@@ -266,10 +266,11 @@ typedef struct {
                             max(tol_i, shift_floor) (Sec. 3.2: "reach the limit of the sloppy precision");
                             <= 0 selects the sloppy format's epsilon */
     int batch_refine;    /* multi-shift: refine the shifted systems together, one Dslash per iteration shared
-                            by up to 16 of them (1), or one after another (0); the base is refined first.
+                            by up to 16 of them (1), or one after another (0), the base refined first.
                             2: as 1, but the batch runs on a second library stream while a host thread refines
                             the base concurrently on the first (every launch shape planned beforehand);
-                            phase_seconds[1] and [2] then overlap */
+                            phase_seconds[1] and [2] then overlap; 3: the base joins the first block as its
+                            system 0, still continuing its gradient vector (phase_seconds[1] is then 0) */
     int ru_estimate;     /* CG and the multi-shift base: 0 = reliable update when |r| drops below delta times its
                             maximum since the last one; 1 = when an estimate of |r_true - r_iterated| (each
                             iteration's sloppy roundoff, accumulated in quadrature: residual replacement in the
@@ -296,7 +297,7 @@ typedef struct {
 } hisq_solver_stats;
 
 /* Default parameters: delta 0.1, maxiter 100000, grad_buffer 8, PR beta,
- * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 1, ru_estimate 0. */
+ * re-projection on, poll_every 32, graphs on, shift_floor 0 (auto), batch_refine 3, ru_estimate 0. */
 void hisq_solver_params_default(hisq_solver_params *p);
 
 /* Workspace bytes for hisq_cg_solve on `dims` with sloppy format `sloppy`. */
@@ -331,12 +332,14 @@ size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift, hisq_fmt m
  * (FP64) and gradient vectors are updated in one fused launch per iteration;
  * shift i stops updating when its iterated residual reaches
  * max(tol_i, shift_floor); the phase ends when every shift i >= 1 has
- * stopped.  Then CG refinement in the refine_fmt triplet: the base first,
- * keeping its gradient vector, then every shift from a clean restart, each to
- * its own tol_i (true residual): in ascending order, or (p->batch_refine,
- * the default, for refine triplets other than FIX32/INT30/FP32) in blocks of
- * up to 16 independent CGs sharing every Dslash (each the iteration of a
- * lone solve, with its own reliable updates).
+ * stopped.  Then CG refinement in the refine_fmt triplet: the base keeping
+ * its gradient vector, every shift from a clean restart, each to its own
+ * tol_i (true residual).  By default (p->batch_refine 3, refine triplets other
+ * than FIX32/INT30/FP32) all of them as blocks of up to 16 independent CGs
+ * sharing every Dslash (each the iteration of a lone solve, with its own
+ * reliable updates), the base in the first block; otherwise the base first,
+ * then the shifts in ascending order (batch_refine 0) or as such blocks
+ * (1, or 2 concurrently with the base).
  * x: (host) array of nshift (device) canonical complex128 [Vh][3] outputs.
  * shifts, tol: (host) arrays of nshift doubles, shifts strictly ascending,
  * shifts[0] >= 0 and 1 <= nshift <= HISQ_MAX_SHIFTS.

@@ -168,7 +168,10 @@ __global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, i
         if (threadIdx.x || !c->bactive[j] || !c->bru[j]) continue;   // the others keep their CG step
         const double rho = v[0];
         double beta = 0.0, cr = 0.0, ci = 0.0;
-        if (mode != 1) {
+        // the first reliable update restarts every system, except one that
+        // continues a given gradient vector (re-projected, Fletcher-Reeves beta:
+        // there is no previous iterated residual to form Polak-Ribiere's)
+        if (mode != 1 || c->bwarm[j]) {
             if (c->reproject && rho > 0.0) {
                 cr = v[1] / rho;
                 ci = v[2] / rho;
@@ -181,6 +184,7 @@ __global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, i
         c->bbeta[j] = beta;
         c->brho[j] = rho;
         c->brmax2[j] = rho;
+        c->bwarm[j] = 0;
     }
     if (threadIdx.x) return;
     for (int j = 0; j < nrhs; j++) c->bru[j] = 0;
@@ -410,12 +414,12 @@ struct BRun {
         d64 += 2;
         alg += 2.0 * vh * (dslash_link_bytes(g64) + nru * 2.0 * 48) + 2.0 * vh * nru * 48;
         const Guard g0{&c->stop, 0, 0};
-        HISQ_TRY_HIP(launch_bru_convert(B->rs, B->r64, fs64, mode == 1 ? nullptr : p_src, mode == 0 ? B->aps : nullptr,
+        HISQ_TRY_HIP(launch_bru_convert(B->rs, B->r64, fs64, p_src, mode == 0 ? B->aps : nullptr,
                                         c, vh, fs, nrhs, fmt.spinor, fmt.compute, B->partial, g0, st));
         hipLaunchKernelGGL(k_bfin_ru_finish, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), nrhs,
                            mode, g0);
         HISQ_TRY_HIP(hipGetLastError());
-        HISQ_TRY_HIP(launch_bcg_pupdate(B->p[0], B->rs, mode == 1 ? B->rs : p_src, c, vh, fs, nrhs, fmt.spinor,
+        HISQ_TRY_HIP(launch_bcg_pupdate(B->p[0], B->rs, p_src ? p_src : B->rs, c, vh, fs, nrhs, fmt.spinor,
                                         fmt.compute, g0, st));
         return HISQ_OK;
     }
@@ -513,6 +517,15 @@ hisq_status batched_run(BatchedJob &J) {
         h->bnc[j] = -J.c[j];
         h->btol2[j] = J.tol[j] * J.tol[j];
     }
+    if (J.p_warm) {
+        // system 0 continues the given gradient vector: it goes to column 0 of
+        // the first ring slot (the other columns are zero, so the fused update
+        // p = r + 0 p of the restarting systems stays finite)
+        h->bwarm[0] = 1;
+        h->brho_prev[0] = J.rho_warm;
+        HISQ_TRY_HIP(hipMemsetAsync(B.p[0], 0, (size_t)nrhs * R.fs, s_));
+        HISQ_TRY_HIP(hipMemcpyAsync(B.p[0], J.p_warm, R.fs, hipMemcpyDeviceToDevice, s_));
+    }
     HISQ_TRY_HIP(hipMemcpyAsync(B.ctrl, h, sizeof(SolverCtrl), hipMemcpyHostToDevice, s_));
     // |b_j|^2: the F64 norm kernel per right-hand side, each into its own partial column
     for (int j = 0; j < nrhs; j++) {
@@ -547,7 +560,7 @@ hisq_status batched_run(BatchedJob &J) {
         if (h->bactive[j]) m0 |= 1u << j;
     hisq_status status = HISQ_OK;
     if (m0) {
-        status = R.enq_reliable(1, 0, nullptr, m0);
+        status = R.enq_reliable(1, 0, J.p_warm ? B.p[0] : nullptr, m0);
         if (status == HISQ_OK) status = R.read_ctrl(h);
     } else {
         h->done = 1;

@@ -233,6 +233,7 @@ struct SolverCtrl {
     int bru[16];       // 1: right-hand side j takes part in the pending reliable update
     int bdone[16];
     int bk[16];
+    int bwarm[16];     // 1: system j continues a given gradient vector at its first reliable update
 };
 
 enum { STOP_NONE = 0, STOP_RU = 1, STOP_CONV = 2, STOP_BREAKDOWN = 3, STOP_MAXITER = 4, STOP_MSDONE = 5 };
@@ -304,6 +305,11 @@ struct BatchedJob {
     // work the caller starts there on another stream never overlaps a timing
     void (*after_setup)(void *);
     void *after_setup_ctx;
+    // optional: system 0 continues the gradient vector p_warm (the job's
+    // storage format) instead of restarting, with beta = |r|^2 / rho_warm at the
+    // first reliable update (the multi-shift base system of Sec. 3.2)
+    const char *p_warm;
+    double rho_warm;
     // results
     long iters, rus, dsl, d64;
     double alg;

@@ -608,13 +608,15 @@ hisq_status check_params(const hisq_solver_params *p, hisq_solver_params *out) {
     if (out->grad_buffer < 1 || out->grad_buffer > HISQ_MAX_GRAD_BUFFER)
         return set_error(HISQ_EINVAL, "grad_buffer must be in [1,%d]", HISQ_MAX_GRAD_BUFFER);
     if (out->poll_every <= 0) out->poll_every = d.poll_every;
-    if (out->batch_refine < 0 || out->batch_refine > 2) return set_error(HISQ_EINVAL, "batch_refine must be 0, 1 or 2");
+    if (out->batch_refine < 0 || out->batch_refine > 3)
+        return set_error(HISQ_EINVAL, "batch_refine must be 0, 1, 2 or 3");
     if (out->ru_estimate != 0 && out->ru_estimate != 1) return set_error(HISQ_EINVAL, "ru_estimate must be 0 or 1");
     return HISQ_OK;
 }
 
 // multi-shift workspace: the solver buffers, then (batched refinement) the
-// buffers of a block of min(16, nshift-1) shifted systems
+// buffers of a block of min(16, nshift-1) shifted systems (min(16, nshift)
+// when the base system joins the block)
 struct MsLayout {
     size_t solver, batched;
     bool batch;
@@ -626,7 +628,8 @@ MsLayout ms_layout(const Geom &g, int nshift, const hisq_fmt &ms_fmt, const hisq
     L.solver = (carve_cg(nullptr, nullptr, g, bs, q.grad_buffer, nshift, spinor_site_bytes(ms_fmt.spinor),
                          spinor_site_bytes(refine_fmt.spinor)) + 255) & ~(size_t)255;
     L.batch = q.batch_refine && nshift > 1 && batched_fmt_ok(refine_fmt);
-    L.batched = L.batch ? batched_ws_bytes(g, std::min(16, nshift - 1), refine_fmt.spinor, q.grad_buffer) : 0;
+    const int nblock = std::min(16, q.batch_refine == 3 ? nshift : nshift - 1);
+    L.batched = L.batch ? batched_ws_bytes(g, nblock, refine_fmt.spinor, q.grad_buffer) : 0;
     return L;
 }
 
@@ -715,7 +718,7 @@ extern "C" void hisq_solver_params_default(hisq_solver_params *p) {
     p->poll_every = 32;
     p->use_graph = 1;
     p->shift_floor = 0.0;
-    p->batch_refine = 1;
+    p->batch_refine = 3;
     p->ru_estimate = 0;
 }
 
@@ -969,7 +972,55 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
     if (nshift > 1 && status == HISQ_OK)
         HISQ_TRY_HIP(launch_spinor_convert(B.pconv, refine_fmt.spinor, B.p[base_slot], ms_fmt.spinor, g.vh, s_));
     const bool overlap = L.batch && nshift > 1 && q.batch_refine == 2;
-    if (!overlap) {
+    const bool joint = L.batch && nshift > 1 && q.batch_refine == 3;
+    // one batched block of the systems [i0, i0 + n): the base (i0 == 0) continues its gradient vector
+    auto run_block = [&](int i0, int n, hipStream_t sr, SolverCtrl *hc, BatchedJob &J) {
+        memset(&J, 0, sizeof(J));
+        J.nrhs = n;
+        for (int j = 0; j < n; j++) {
+            J.x[j] = x[i0 + j];
+            J.b[j] = b;
+            J.c[j] = m2 + shifts[i0 + j];
+            J.tol[j] = tol[i0 + j];
+        }
+        J.g64 = g64;
+        J.gs = g_ref;
+        J.fmt = refine_fmt;
+        J.q = q;
+        J.ws = (char *)ws + L.solver;
+        J.ws_bytes = L.batched;
+        J.st = sr;
+        J.h = hc;
+        if (i0 == 0) {
+            J.p_warm = B.pconv;
+            J.rho_warm = rho_ms;
+        }
+    };
+    auto account_block = [&](int i0, const BatchedJob &J) {
+        for (int j = 0; j < J.nrhs; j++) {
+            st->shift_resid_ms[i0 + j] = J.resid0_j[j];
+            st->refine_iters[i0 + j] = J.iters_j[j];
+            st->shift_resid[i0 + j] = J.resid_j[j];
+        }
+        st->reliable_updates += (int)J.rus;
+        st->dslash_sloppy += (int)J.dsl;
+        st->dslash_f64 += (int)J.d64;
+        st->alg_bytes += J.alg;
+    };
+    if (joint) {
+        // the base joins the shifts' batch as system 0 of the first block,
+        // continuing its gradient vector; every system converges on its own
+        if (status == HISQ_OK) HISQ_TRY_HIP(launch_spinor_unpack(x[0], B.x64, g.vh, SF_F64, s_));
+        for (int i = 1; i < nshift && status == HISQ_OK; i++)
+            HISQ_TRY_HIP(launch_spinor_unpack(x[i], B.xs[i], g.vh, SF_F64, s_));
+        for (int i0 = 0; i0 < nshift && status == HISQ_OK; i0 += 16) {
+            BatchedJob J;
+            run_block(i0, std::min(16, nshift - i0), s_, h, J);
+            status = batched_run(J);
+            account_block(i0, J);
+        }
+        st->phase_seconds[1] = 0.0;
+    } else if (!overlap) {
         // the base, then the shifts: one after another, or together as a batch
         for (int i = 0; i < (L.batch ? 1 : nshift) && status == HISQ_OK; i++) {
             Refined o;
@@ -985,32 +1036,9 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
             for (int i = 1; i < nshift; i++) HISQ_TRY_HIP(launch_spinor_unpack(x[i], B.xs[i], g.vh, SF_F64, s_));
             for (int i0 = 1; i0 < nshift && status == HISQ_OK; i0 += 16) {
                 BatchedJob J;
-                memset(&J, 0, sizeof(J));
-                J.nrhs = std::min(16, nshift - i0);
-                for (int j = 0; j < J.nrhs; j++) {
-                    J.x[j] = x[i0 + j];
-                    J.b[j] = b;
-                    J.c[j] = m2 + shifts[i0 + j];
-                    J.tol[j] = tol[i0 + j];
-                }
-                J.g64 = g64;
-                J.gs = g_ref;
-                J.fmt = refine_fmt;
-                J.q = q;
-                J.ws = (char *)ws + L.solver;
-                J.ws_bytes = L.batched;
-                J.st = s_;
-                J.h = h;
+                run_block(i0, std::min(16, nshift - i0), s_, h, J);
                 status = batched_run(J);
-                for (int j = 0; j < J.nrhs; j++) {
-                    st->shift_resid_ms[i0 + j] = J.resid0_j[j];
-                    st->refine_iters[i0 + j] = J.iters_j[j];
-                    st->shift_resid[i0 + j] = J.resid_j[j];
-                }
-                st->reliable_updates += (int)J.rus;
-                st->dslash_sloppy += (int)J.dsl;
-                st->dslash_f64 += (int)J.d64;
-                st->alg_bytes += J.alg;
+                account_block(i0, J);
             }
         }
     } else if (status == HISQ_OK) {
@@ -1034,22 +1062,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         } start{&worker, [&] { refine_one(0, base, h); }};
         for (int i0 = 1; i0 < nshift && status == HISQ_OK; i0 += 16) {
             BatchedJob J;
-            memset(&J, 0, sizeof(J));
-            J.nrhs = std::min(16, nshift - i0);
-            for (int j = 0; j < J.nrhs; j++) {
-                J.x[j] = x[i0 + j];
-                J.b[j] = b;
-                J.c[j] = m2 + shifts[i0 + j];
-                J.tol[j] = tol[i0 + j];
-            }
-            J.g64 = g64;
-            J.gs = g_ref;
-            J.fmt = refine_fmt;
-            J.q = q;
-            J.ws = (char *)ws + L.solver;
-            J.ws_bytes = L.batched;
-            J.st = s2;
-            J.h = E.ds->host_ctrl2;
+            run_block(i0, std::min(16, nshift - i0), s2, E.ds->host_ctrl2, J);
             if (!worker.joinable()) {
                 // the base starts once the block's launch shapes are planned
                 J.after_setup = [](void *c) {
@@ -1063,15 +1076,7 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
                 J.after_setup_ctx = &start;
             }
             status = batched_run(J);
-            for (int j = 0; j < J.nrhs; j++) {
-                st->shift_resid_ms[i0 + j] = J.resid0_j[j];
-                st->refine_iters[i0 + j] = J.iters_j[j];
-                st->shift_resid[i0 + j] = J.resid_j[j];
-            }
-            st->reliable_updates += (int)J.rus;
-            st->dslash_sloppy += (int)J.dsl;
-            st->dslash_f64 += (int)J.d64;
-            st->alg_bytes += J.alg;
+            account_block(i0, J);
         }
         if (worker.joinable()) {
             worker.join();

@@ -70,7 +70,8 @@ def test_sizes(hisq):
     assert hisq.hisq_bicgstab_workspace_bytes(dims, 4, hisq.fmt("int20")) > 0
     assert hisq.hisq_bicgstab_workspace_bytes(dims, 0, hisq.fmt("int20")) == 0
     assert hisq.hisq_bicgstab_workspace_bytes(dims, 9, hisq.fmt("int20")) == 0
-    assert p.batch_refine == 1
+    assert p.batch_refine == 3
+    p.batch_refine = 1
     wb = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
     p.batch_refine = 0
     ws = hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p)
@@ -85,7 +86,9 @@ def test_sizes(hisq):
     assert a == hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int30_fp32"), p)
     p.batch_refine = 2                                           # the batch overlapping the base: same room
     assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == wb
-    p.batch_refine = 3
+    p.batch_refine = 3                                           # the base joins the block: room for 12
+    assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) > wb
+    p.batch_refine = 4
     assert hisq.hisq_multishift_workspace_bytes(dims, 12, hisq.fmt("int30"), hisq.fmt("int20"), p) == 0
     p.batch_refine = 1
     p.ru_estimate = 2

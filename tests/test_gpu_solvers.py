@@ -116,11 +116,13 @@ def test_cg_maxiter_reports_noconv():
                                           ("single", "single", 1), ("int30", "int20", 0), ("single", "half", 0),
                                           ("int30", "int30_fp32", 1), ("int30", "int24", 1),
                                           ("sx24_int30", "int20", 1), ("int30", "int20", 2), ("single", "half", 2),
-                                          ("int30", "int30_fp32", 2)])
+                                          ("int30", "int30_fp32", 2), ("int30", "int20", 3), ("single", "half", 3),
+                                          ("int30", "int30_fp32", 3)])
 def test_multishift(ms, ref, batch):
     """batch: refine the shifted systems together (1), together while the
-    base is refined concurrently (2), or one after another (0); int30_fp32 has
-    no batched form, so it refines one after another either way"""
+    base is refined concurrently (2), together with the base continuing its
+    gradient vector in the same block (3), or one after another (0);
+    int30_fp32 has no batched form, so it refines one after another either way"""
     hisq = need_gpu()
     dims, mass = (8, 8, 8, 8), 0.05
     shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
@@ -159,14 +161,15 @@ def test_multishift_per_shift_tolerances():
 def test_multishift_many_shifts_two_blocks():
     """18 shifts: the batched refinement runs the 17 shifted systems as a block
     of 16 and a block of 1; per-shift targets differ inside a block; with the
-    base refined concurrently (batch_refine 2) as well"""
+    base refined concurrently (batch_refine 2) as well, and with the base in
+    the first block (batch_refine 3: blocks of 16 and 2)"""
     hisq = need_gpu()
     dims, mass = (6, 8, 10, 12), 0.05
     shifts = [10.0 ** (-4 + 5 * i / 17) for i in range(18)]
     tol = [1e-9 if i % 3 == 1 else 1e-10 for i in range(18)]
     fat, lng, ev, b = setup(dims, "near_unit")
     pg = packed(hisq, fat, lng, dims, ["double", "single", "half"])
-    for batch in (1, 2):
+    for batch in (1, 2, 3):
         xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[1], pg[2], mass,
                                           ms_fmt="single", ref_fmt="half", batch_refine=batch)
         assert st["status"] == "HISQ_OK", st

@@ -684,12 +684,12 @@ __device__ __forceinline__ void site_epilogue(const DslashArgs &A, int s, ColF c
     }
 }
 
-// One output site s for the lane's right-hand sides r0..r0+NR-1 (those in
-// `live`): the 16 hops, the epilogue out = b*D(in) + a*x + c*y, the packed
+// One output site s for the lane's right-hand sides c0 + j*cs, j < NR (those
+// in `live`): the 16 hops, the epilogue out = b*D(in) + a*x + c*y, the packed
 // store, and the optional reduction into red[].
 template <int GF, int SF, class R, int NR, int STAGE, bool RED, int LR>
-__device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, unsigned live, const R (&acoef)[NR],
-                                            double (&red)[NR]) {
+__device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int c0, int cs, unsigned live,
+                                            const R (&acoef)[NR], double (&red)[NR]) {
     const Geom &g = A.g;
     const size_t fs = A.field_stride;
     const size_t vh = (size_t)g.vh;
@@ -700,7 +700,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
                                  : LR == 8 ? (size_t)gauge_matrix_bytes8(GF) * vh : sub;
     const R gf = (R)A.gfat, gl = (R)A.glong, lc = (R)A.lcoef;
     // input field of the lane's right-hand side j
-    auto in_col = [&](int j) { return A.in + (size_t)colmap(A, r0 + j) * fs; };
+    auto in_col = [&](int j) { return A.in + (size_t)colmap(A, c0 + j * cs) * fs; };
     CVec<R> acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; j++) cvec_zero(acc[j]);
@@ -820,7 +820,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs &A, int s, int r0, 
         apply_stage(k * SB, k % NBUF);
         if (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
-    site_epilogue<SF, R, NR, RED>(A, s, [&](int j) { return colmap(A, r0 + j); }, live, acoef, acc, red);
+    site_epilogue<SF, R, NR, RED>(A, s, [&](int j) { return colmap(A, c0 + j * cs); }, live, acoef, acc, red);
 }
 
 // Batched sites on the matrix cores (STAGE == MFMA_STAGE, FP32 compute, four
@@ -1018,13 +1018,14 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
 #pragma unroll
     for (int j = 0; j < NR; j++) red[j] = 0.0;
     // The lane's right-hand sides (rg divides blockDim, so a lane keeps its
-    // group in every tile): rhs0 + grp*NR + j, or rhs0 + j*rg + grp on the
-    // matrix cores (one column of each group of rg per lane).  Those at or beyond ncol (a block padded to a power of two) and
-    // those marked inactive are neither read nor written.
-    constexpr bool IL = STAGE == MFMA_STAGE;
+    // group in every tile): rhs0 + j*rg + grp, one column of each group of rg
+    // per lane, so that the live columns of a block (a prefix: the solvers
+    // compact them) leave whole groups dead in every lane, whose arithmetic
+    // the wave then skips.  Those at or beyond ncol (a block padded to a power
+    // of two) and those marked inactive are neither read nor written.
     const int ncol = A.nrhs > 1 ? A.nrhs : 1;
     const int grp0 = (int)(threadIdx.x & (unsigned)(rg - 1));
-    auto cofs = [&](int lg, int j) { return IL ? j * rg + lg : lg * NR + j; };
+    auto cofs = [&](int lg, int j) { return j * rg + lg; };
     unsigned live = 0;
 #pragma unroll
     for (int j = 0; j < NR; j++) {
@@ -1086,7 +1087,7 @@ __global__ void __launch_bounds__(256) k_dslash(DslashArgs A, int rhs0, int rg, 
         // every lane takes part in the matrix instructions of its site's block
         dslash_site_mfma<GF, SF, NR, RED, LR>(A, s, inside, rhs0, grp, live, acoef, red);
     } else {
-        if (inside && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, rhs0 + grp * NR, live, acoef, red);
+        if (inside && live) dslash_site<GF, SF, R, NR, STAGE, RED, LR>(A, s, rhs0 + grp, rg, live, acoef, red);
     }
     }
     if (RED) {
@@ -1125,7 +1126,7 @@ __global__ void __launch_bounds__(MULTI_BLOCK) k_dslash_multi(MultiArgs M) {
     if (s >= A.g.vh) return;
     const R acoef[1] = {(R)A.a};
     double red[1] = {0.0};
-    dslash_site<GF, SF, R, 1, STAGE, false, LR>(A, s, 0, 1u, acoef, red);
+    dslash_site<GF, SF, R, 1, STAGE, false, LR>(A, s, 0, 1, 1u, acoef, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -307,14 +307,14 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
         }
     }
     // The z-slab order keeps each XCD's neighbour planes in its own L2: about
-    // 9 % fewer bytes fetched into L2 for the same time (the other orders'
-    // extra fetches hit the memory-side cache).  Within 2 % of the fastest
-    // (about the spread of these timings) the same shape in that order is kept.
+    // 9 % fewer bytes fetched into L2 at nearly the same time (the other
+    // orders' extra fetches hit the memory-side cache).  Within 1 % of the
+    // fastest (the spread of these timings) the same shape in that order is kept.
     if (tbest > 0.f && best.sweep != 2 && g.Z >= 8) {
         DslashTile twin = best;
         twin.sweep = 2;
         const float ms = time_tile(p, f, twin, st, 10);
-        if (ms > 0.f && ms <= 1.02f * tbest) {
+        if (ms > 0.f && ms <= 1.01f * tbest) {
             tbest = ms;
             best = twin;
         }

@@ -47,16 +47,22 @@ def test_bicgstab4(sloppy, dims, kind, mass):
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
 
 
-@pytest.mark.parametrize("l", [1, 2, 8])
-def test_bicgstab_l(l):
+@pytest.mark.parametrize("l,graph", [(1, 1), (2, 1), (8, 1), (4, 0), (1, 0)])
+def test_bicgstab_l(l, graph):
+    """every l; graph 0 enqueues each cycle's kernels directly instead of
+    replaying the captured cycle (the same kernels, the same device scalars)"""
     hisq = need_gpu()
     dims, mass = (8, 8, 8, 8), 0.05
     fat, lng, b, xo = system(dims, "near_unit", mass)
     g64 = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_F64)
     gs = hisq.pack_gauge(fat.cuda(), lng.cuda(), dims, hisq.GAUGE_FIX16, long_recon=12)
-    x, st = hisq.bicgstab_solve(torch.from_numpy(b).cuda(), g64, gs, mass, tol=1e-10, l=l, sloppy="int20")
+    x, st = hisq.bicgstab_solve(torch.from_numpy(b).cuda(), g64, gs, mass, tol=1e-10, l=l, sloppy="int20",
+                                use_graph=graph)
     assert st["status"] == "HISQ_OK", st
     assert residual(fat, lng, x.cpu().numpy(), b, dims, mass) <= 1e-10 * (1 + 1e-6)
+    if l == 4:   # the captured and the direct cycle compute the same iterates
+        xg, sg = hisq.bicgstab_solve(torch.from_numpy(b).cuda(), g64, gs, mass, tol=1e-10, l=l, sloppy="int20")
+        assert sg["iters"] == st["iters"] and torch.equal(xg, x), (sg, st)
 
 
 def test_bicgstab_guess_zero_rhs_and_cap():

@@ -532,13 +532,18 @@ template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], dou
 // Solver iteration guard: a kernel that belongs to iteration j of a block of
 // iterations runs iff j < *stop (strict) or j <= *stop; the solver's scalar
 // kernels lower *stop to end a block early (reliable update, convergence).
+// *stop is written only by earlier kernels of the stream, never during a
+// guarded dispatch, and is read first thing: a plain load the compiler turns
+// into one scalar load per wave (the packet processor invalidates the scalar
+// cache between dispatches), so the wave's vector loads do not queue behind a
+// coherent vector load of the flag.
 struct Guard {
     const int *stop;
     int j;
     int strict;
     __device__ __forceinline__ bool pass() const {
         if (!stop) return true;
-        int s = *(volatile const int *)stop;
+        const int s = *stop;
         return strict ? (j < s) : (j <= s);
     }
 };

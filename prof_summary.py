@@ -1,14 +1,16 @@
 """Condense rocprofv3 CSV output into a short text summary.
 
-    python3 prof_summary.py DIR [--match SUBSTR] [--block B --grid G] [--top N] [--delete]
+    python3 prof_summary.py DIR [--match SUBSTR] [--block B --grid G] [--split-us T] [--top N] [--delete]
 
 DIR is a rocprofv3 ``-d`` output directory written with ``--output-format csv``.
 Prints the per-kernel statistics (``*kernel_stats.csv``: calls, total, average),
 and, for the dispatches of the kernels whose name contains SUBSTR (optionally
 only those launched with workgroup size B and B*G lanes), the dispatch count
 and the average duration (``*kernel_trace.csv``) or the average value of each
-hardware counter (``*counter_collection.csv``).  --delete removes the bulky
-per-dispatch CSV files afterwards.
+hardware counter (``*counter_collection.csv``).  --split-us T also reports the
+dispatches shorter and not shorter than T microseconds apart (a solver's
+guarded launches that return at once against those that run).  --delete
+removes the bulky per-dispatch CSV files afterwards.
 """
 from __future__ import annotations
 
@@ -42,7 +44,12 @@ def _shape_ok(row, block, grid):
     return grid is None or gs == block * grid
 
 
-def summarize(d, match=None, block=None, grid=None, top=25, out=sys.stdout):
+def _line(label, ts):
+    return (f"{label}: {len(ts)}; average {sum(ts) / len(ts) / 1e3:.2f} us; "
+            f"min {min(ts) / 1e3:.2f} us; max {max(ts) / 1e3:.2f} us\n")
+
+
+def summarize(d, match=None, block=None, grid=None, top=25, split_us=None, out=sys.stdout):
     for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
         rows = _rows(f)
         rows.sort(key=lambda r: -float(_get(r, "TotalDurationNs", default="0")))
@@ -63,8 +70,12 @@ def summarize(d, match=None, block=None, grid=None, top=25, out=sys.stdout):
             for name, ts in per.items():
                 out.write(f"# dispatches of {name[:150]}\n")
                 shape = f" with workgroup {block}" + (f" and {grid} blocks" if grid is not None else "") if block else ""
-                out.write(f"dispatches{shape}: {len(ts)}; average {sum(ts) / len(ts) / 1e3:.2f} us; "
-                          f"min {min(ts) / 1e3:.2f} us; max {max(ts) / 1e3:.2f} us\n")
+                out.write(_line(f"dispatches{shape}", ts))
+                if split_us is not None:
+                    for label, part in ((f"shorter than {split_us:g} us", [t for t in ts if t < split_us * 1e3]),
+                                        (f"{split_us:g} us or longer", [t for t in ts if t >= split_us * 1e3])):
+                        if part:
+                            out.write(_line(f"  {label}", part))
     for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         acc = defaultdict(lambda: defaultdict(float))
         for r in _rows(f):
@@ -92,10 +103,11 @@ def main(argv=None):
     ap.add_argument("--match", default=None)
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--grid", type=int, default=None)
+    ap.add_argument("--split-us", type=float, default=None)
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--delete", action="store_true")
     a = ap.parse_args(argv)
-    summarize(a.dir, a.match, a.block, a.grid, a.top)
+    summarize(a.dir, a.match, a.block, a.grid, a.top, a.split_us)
     if a.delete:
         for pat in ("*kernel_trace.csv", "*counter_collection.csv"):
             for f in glob.glob(os.path.join(a.dir, "**", pat), recursive=True):

@@ -397,6 +397,97 @@ def cpu_baseline(np, dims, fat, lng, b, shifts, tols, mass, kernels, fp64_iters,
                 vs_gpu_mixed_solve=round(extrap / gpu_seconds, 1) if extrap else None)
 
 
+def cg_time_to_solution(np, hisq, inputs, torch, dev, batched_cg, tol=1e-10):
+    """The FP64 oracle's CG time to solution on the host beside the GPU's, on the
+    smaller workloads: 4^4 (Haar links, m = 0.1) and 16^4 (near-unit, m = 0.05)
+    to completion; 32^4 (near-unit, m = 0.01) and the 32^3x64 block of 16
+    systems (m = 0.01) as the oracle's time per iteration (the difference of two
+    short runs, setup and final residual cancelling) times the GPU FP64 CG's
+    iteration count (extrapolated; the same algorithm).  GPU: plain FP64 CG
+    and the mixed CG (double-single on the first two, double-int20 with two-row
+    long links on 32^4), each timed after a warm-up solve, excluding the pack."""
+    import oracle
+    olib = oracle.load()
+    rows = []
+
+    def gpu_solve(b, g64, gs, mass, sloppy, **kw):
+        hisq.cg_solve(b, g64, gs, mass, tol=tol, sloppy=sloppy, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = hisq.cg_solve(b, g64, gs, mass, tol=tol, sloppy=sloppy, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st
+
+    def oracle_per_iter(fat_h, lng_h, bfull, dims, mass, k0, k1):
+        ts = []
+        for k in (k0, k1):
+            t = time.perf_counter()
+            oracle.cg(fat_h, lng_h, bfull, dims, mass, tol=tol, maxiter=k, lib=olib)
+            ts.append(time.perf_counter() - t)
+        return (ts[1] - ts[0]) / (k1 - k0)
+
+    cases = [((4, 4, 4, 4), "haar", 0.1, 0, "single", True),
+             ((16, 16, 16, 16), "near_unit", 0.05, 1, "single", True),
+             ((32, 32, 32, 32), "near_unit", 0.01, 2, "int20", False)]
+    for dims, kind, mass, k, sloppy, complete in cases:
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + k, device=dev)
+        ev = np.nonzero(((np.arange(V) % dims[0]) + (np.arange(V) // dims[0]) % dims[1]
+                         + (np.arange(V) // (dims[0] * dims[1])) % dims[2]
+                         + np.arange(V) // (dims[0] * dims[1] * dims[2])) % 2 == 0)[0]
+        bh = inputs.gaussian_spinor(ev.size, inputs.SOURCE_SEED + k).numpy()
+        b = torch.from_numpy(bh).to(dev)
+        fs = hisq.fmt(sloppy)
+        recon = 12 if sloppy == "int20" else 18
+        g64 = hisq.pack_gauge(fat, lng, dims, hisq.GAUGE_F64)
+        gs = hisq.pack_gauge(fat, lng, dims, fs.gauge, long_recon=recon)
+        t64, s64 = gpu_solve(b, g64, g64, mass, "double", delta=0.0)
+        tmx, smx = gpu_solve(b, g64, gs, mass, sloppy)
+        fat_h, lng_h = fat.cpu().numpy(), lng.cpu().numpy()
+        bfull = np.zeros((V, 3), dtype=np.complex128)
+        bfull[ev] = bh
+        row = dict(lattice=list(dims), links=kind, mass=mass, tol=tol,
+                   gpu_fp64_seconds=round(t64, 4), gpu_fp64_iters=s64["iters"],
+                   gpu_mixed=f"double-{sloppy}", gpu_mixed_seconds=round(tmx, 4), gpu_mixed_iters=smx["iters"],
+                   gpu_mixed_resid=float(f"{smx['true_resid']:.3g}"))
+        if complete:
+            t = time.perf_counter()
+            _, it, res, _ = oracle.cg(fat_h, lng_h, bfull, dims, mass, tol=tol, lib=olib)
+            row.update(oracle_seconds=round(time.perf_counter() - t, 3), oracle_iters=it,
+                       oracle_resid=float(f"{res:.3g}"), extrapolated=False)
+        else:
+            per = oracle_per_iter(fat_h, lng_h, bfull, dims, mass, 2, 6)
+            row.update(oracle_seconds=round(per * s64["iters"], 1), oracle_seconds_per_iter=round(per, 4),
+                       oracle_iters=s64["iters"], extrapolated=True)
+        row["oracle_over_gpu_mixed"] = round(row["oracle_seconds"] / tmx, 1)
+        rows.append(row)
+        log(f"[bench]   CG {dims} m={mass}: oracle {row['oracle_seconds']} s"
+            f"{' (extrapolated)' if not complete else ''}, GPU FP64 {t64:.3f} s, GPU double-{sloppy} {tmx:.3f} s")
+        del fat, lng, g64, gs, fat_h, lng_h, bfull, b
+        torch.cuda.empty_cache()
+    if batched_cg:
+        dims, mass, nrhs = tuple(batched_cg["lattice"]), batched_cg["mass"], batched_cg["nrhs"]
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 4, device=dev)
+        fat_h, lng_h = fat.cpu().numpy(), lng.cpu().numpy()
+        del fat, lng
+        ev = np.nonzero(((np.arange(V) % dims[0]) + (np.arange(V) // dims[0]) % dims[1]
+                         + (np.arange(V) // (dims[0] * dims[1])) % dims[2]
+                         + np.arange(V) // (dims[0] * dims[1] * dims[2])) % 2 == 0)[0]
+        bfull = np.zeros((V, 3), dtype=np.complex128)
+        bfull[ev] = inputs.gaussian_spinor(ev.size, inputs.RHS_SEED).numpy()
+        per = oracle_per_iter(fat_h, lng_h, bfull, dims, mass, 1, 3)
+        tot = per * batched_cg["fp64_iters_mean"] * nrhs
+        rows.append(dict(lattice=list(dims), links="near_unit", mass=mass, tol=tol, nrhs=nrhs,
+                         gpu_fp64_seconds=batched_cg["fp64_seconds"], gpu_mixed="batched double-int20",
+                         gpu_mixed_seconds=batched_cg["batched_seconds"], oracle_seconds=round(tot, 1),
+                         oracle_seconds_per_iter=round(per, 4), oracle_iters=batched_cg["fp64_iters_mean"],
+                         extrapolated=True, oracle_over_gpu_mixed=round(tot / batched_cg["batched_seconds"], 1)))
+        log(f"[bench]   CG {dims} x{nrhs}: oracle {tot:.0f} s (extrapolated), GPU batched {batched_cg['batched_seconds']} s")
+        del fat_h, lng_h, bfull
+    return rows
+
+
 def _pack_like(hisq, inputs, dims, gf, dev, kind):
     fat, lng = inputs.make_links(dims, kind, inputs.GAUGE_SEED + 90, device=dev)
     return hisq.pack_gauge(fat, lng, dims, gf, long_recon=12)
@@ -673,6 +764,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(np, dims, fat, lng, b, shifts, tols, args.mass, kernels,
                            fp64["iters"] if fp64 else None, ms_per_step / 1e3)
+        cpu["cg_time_to_solution"] = cg_time_to_solution(np, hisq, inputs, torch, dev, batched_cg)
 
     line = {
         "metric": "HISQ Dslash GB/s (% HBM peak); multi-shift CG s to 1e-10 vs FP64 CG",

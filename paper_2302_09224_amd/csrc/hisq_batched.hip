@@ -27,14 +27,30 @@ namespace hisq {
 
 namespace {
 
-constexpr int FIN_THREADS = 256;
+// finalize kernels: 16 waves per block; each thread loads its strided share
+// of the block partials four entries at a time (all four in flight) and adds
+// them in index order
+constexpr int FIN_THREADS = 1024;
 
 // sum over blocks b of partial[(b*nrhs + j)*NV + k], k < NV; valid in thread 0
 template <int NV>
 __device__ __forceinline__ void bsum(const double *partial, int nb, int nrhs, int j, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; k++) v[k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int step = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 3 * step < nb; b += 4 * step) {
+        double q[4][NV];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int k = 0; k < NV; k++) q[u][k] = partial[((size_t)(b + u * step) * nrhs + j) * NV + k];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int k = 0; k < NV; k++) v[k] += q[u][k];
+    }
+    for (; b < nb; b += step) {
 #pragma unroll
         for (int k = 0; k < NV; k++) v[k] += partial[((size_t)b * nrhs + j) * NV + k];
     }
@@ -50,7 +66,16 @@ struct NbList {
 
 __device__ __forceinline__ void csum(const double *col, int nb, double (&v)[1], double *lds) {
     v[0] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += col[b];
+    const int step = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 3 * step < nb; b += 4 * step) {
+        const double q0 = col[b], q1 = col[b + step], q2 = col[b + 2 * step], q3 = col[b + 3 * step];
+        v[0] += q0;
+        v[0] += q1;
+        v[0] += q2;
+        v[0] += q3;
+    }
+    for (; b < nb; b += step) v[0] += col[b];
     block_sum<1>(v, lds);
     __syncthreads();
 }
@@ -59,7 +84,7 @@ __device__ __forceinline__ void csum(const double *col, int nb, double (&v)[1], 
 // independent, and a Dslash over rg lanes per site leaves rg times more partials
 // per column than sites per block; each column is summed in a fixed order
 __global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, NbList nl, int nrhs, int jb, Guard gd) {
-    __shared__ double lds[16];
+    __shared__ double lds[FIN_THREADS / 64];
     const int j = blockIdx.x;
     if (j >= nrhs || !gd.pass()) return;
     double v[1];
@@ -87,7 +112,7 @@ __global__ void k_bfin_alpha(SolverCtrl *c, const double *partial, NbList nl, in
 }
 
 __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nrhs, Guard gd) {
-    __shared__ double lds[32];
+    __shared__ double lds[2 * (FIN_THREADS / 64)];
     if (!gd.pass()) return;
     int reason = STOP_NONE;
     for (int j = 0; j < nrhs; j++) {
@@ -137,7 +162,7 @@ __global__ void k_bfin_beta(SolverCtrl *c, const double *partial, int nb, int nr
 }
 
 __global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, NbList nl, int nrhs) {
-    __shared__ double lds[16];
+    __shared__ double lds[FIN_THREADS / 64];
     int all = 1;
     for (int j = 0; j < nrhs; j++) {
         double v[1];
@@ -160,7 +185,7 @@ __global__ void k_bfin_ru_check(SolverCtrl *c, const double *partial, NbList nl,
 }
 
 __global__ void k_bfin_ru_finish(SolverCtrl *c, const double *partial, int nb, int nrhs, int mode, Guard gd) {
-    __shared__ double lds[64];
+    __shared__ double lds[4 * (FIN_THREADS / 64)];
     if (!gd.pass()) return;
     for (int j = 0; j < nrhs; j++) {
         double v[4];

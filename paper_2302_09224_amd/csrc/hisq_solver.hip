@@ -41,13 +41,29 @@ namespace hisq {
 
 namespace {
 
-constexpr int FIN_THREADS = 256;
+// one block of 16 waves sums the block partials of a whole-lattice launch
+// (tens of thousands at 48^3x96); each thread loads its strided share four
+// entries at a time (all four in flight) and adds them in index order
+constexpr int FIN_THREADS = 1024;
 
 template <int NV>
 __device__ __forceinline__ void fin_sums(const double *partial, int n, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; k++) v[k] = 0.0;
-    for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    const int step = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 3 * step < n; b += 4 * step) {
+        double q[4][NV];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int k = 0; k < NV; k++) q[u][k] = partial[(size_t)(b + u * step) * NV + k];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int k = 0; k < NV; k++) v[k] += q[u][k];
+    }
+    for (; b < n; b += step) {
 #pragma unroll
         for (int k = 0; k < NV; k++) v[k] += partial[(size_t)b * NV + k];
     }
@@ -55,7 +71,7 @@ __device__ __forceinline__ void fin_sums(const double *partial, int n, double (&
 }
 
 __global__ void k_fin_b2(SolverCtrl *c, const double *partial, int n) {
-    __shared__ double lds[16];
+    __shared__ double lds[FIN_THREADS / 64];
     double v[1];
     fin_sums<1>(partial, n, v, lds);
     if (threadIdx.x == 0) c->b2 = v[0];
@@ -63,7 +79,7 @@ __global__ void k_fin_b2(SolverCtrl *c, const double *partial, int n) {
 
 // alpha = rho / <p, A p>
 __global__ void k_fin_alpha(SolverCtrl *c, const double *partial, int n, int jb, Guard gd) {
-    __shared__ double lds[16];
+    __shared__ double lds[FIN_THREADS / 64];
     if (!gd.pass()) return;
     double v[1];
     fin_sums<1>(partial, n, v, lds);
@@ -84,7 +100,7 @@ __global__ void k_fin_alpha(SolverCtrl *c, const double *partial, int n, int jb,
 // beta and the decisions of one iteration; multi-shift: zeta recurrences
 __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd, int multishift, int jb,
                            const double *ppart, int npp) {
-    __shared__ double lds[32], lds2[16];
+    __shared__ double lds[2 * (FIN_THREADS / 64)], lds2[FIN_THREADS / 64];
     if (!gd.pass()) return;
     double v[2];
     fin_sums<2>(partial, n, v, lds);
@@ -173,7 +189,7 @@ __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd
 
 // |b - A x|^2 from the FP64 operator; done when below tol^2 |b|^2
 __global__ void k_fin_ru_check(SolverCtrl *c, const double *partial, int n) {
-    __shared__ double lds[16];
+    __shared__ double lds[FIN_THREADS / 64];
     double v[1];
     fin_sums<1>(partial, n, v, lds);
     if (threadIdx.x) return;
@@ -195,7 +211,7 @@ __global__ void k_fin_ru_check(SolverCtrl *c, const double *partial, int n) {
 // mode 1: fresh start (p = r)
 // mode 2: continuation of a gradient vector from another solve (Fletcher-Reeves against rho_prev)
 __global__ void k_fin_ru_finish(SolverCtrl *c, const double *partial, int n, int mode, Guard gd) {
-    __shared__ double lds[64];
+    __shared__ double lds[4 * (FIN_THREADS / 64)];
     if (!gd.pass()) return;
     double v[4];
     fin_sums<4>(partial, n, v, lds);

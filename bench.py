@@ -526,6 +526,8 @@ def main():
                     help="per-triplet Dslash GB/s and mixed CG iterations/time on 32^4, m = 0.01")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the warm-up and timed steps of the multi-shift solve (for kernel traces)")
     ap.add_argument("--kernel", type=str, default=None,
                     help="only these rows of the Dslash table (comma-separated keys, e.g. int30_r8)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -596,6 +598,8 @@ def main():
     stream = torch.cuda.current_stream()
     names = ("double", "single", "half", "int20", "int30", "int30_fp32", "int24", "sx24", "sx24_int30")
     table = [(n, 18) for n in names] + [(n, 12) for n in names] + [("double", 8), ("int30", 8)]
+    if args.solve_only:
+        table = []
     if args.kernel:
         want = set(args.kernel.split(","))
         table = [(n, r) for n, r in table if (n if r == 18 else f"{n}_r{r}") in want]
@@ -624,9 +628,10 @@ def main():
     batched = None
     if args.batched:
         batched = bench_batched(args, hisq, inputs, torch, dev)
-    multi = bench_multi(hisq, inputs, torch, dev)
-    batched_cg = None if args.kernels_only else bench_batched_cg(hisq, inputs, torch, dev)
-    stability = None if (args.kernels_only or args.no_stability) else bench_cg_stability(hisq, inputs, torch, dev)
+    multi = None if args.solve_only else bench_multi(hisq, inputs, torch, dev)
+    batched_cg = None if (args.kernels_only or args.solve_only) else bench_batched_cg(hisq, inputs, torch, dev)
+    stability = None if (args.kernels_only or args.no_stability or args.solve_only) else bench_cg_stability(
+        hisq, inputs, torch, dev)
     bicg = None
     if args.bicgstab:
         bicg = bench_bicgstab(hisq, inputs, torch, dev, tuple(int(v) for v in args.bicgstab.split(",")),
@@ -692,6 +697,15 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
+    if args.solve_only:
+        print(json.dumps(dict(ms_per_step=round(ms_per_step, 2), steps=[
+            dict(seconds=round(st_["seconds"], 4), phase_seconds=[round(v, 4) for v in st_["phase_seconds"]],
+                 ms_iters=st_["iters"], refine_iters=st_["refine_iters"], reliable_updates=st_["reliable_updates"],
+                 dslash_sloppy=st_["dslash_sloppy"], dslash_f64=st_["dslash_f64"]) for st_ in stats],
+            config={"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "ms_triplet": repr(fms),
+                    "refine_triplet": repr(fref), "ms_long_recon": ms_recon, "long_recon": args.recon,
+                    "batch_refine": args.batch_refine})))
+        return
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
         return 4 * V * (2 * 144 + hisq.GAUGE_BYTES[gf] + long_link_bytes(hisq, gf, recon))

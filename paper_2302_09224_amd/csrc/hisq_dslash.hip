@@ -288,6 +288,11 @@ DslashTile tile_for(const hisq_fmt &f, const Geom &g, int c, const DslashArgs *p
         }
         p.red = RED_NORM;
         p.partial = scratch;
+        // the fused launches are the second Dslash of a normal operator or a
+        // residual, with an xpay term: time them reading one more field per
+        // column (the probe's input again, read-only, the same layout)
+        p.x = probe->in;
+        p.a = 1.0;
     }
     // every candidate three times, then the three fastest ten times each (a
     // single noisy sample does not decide between shapes a few per cent apart)

@@ -49,7 +49,8 @@ def _line(label, ts):
             f"min {min(ts) / 1e3:.2f} us; max {max(ts) / 1e3:.2f} us\n")
 
 
-def summarize(d, match=None, block=None, grid=None, top=25, split_us=None, out=sys.stdout):
+def summarize(d, match=None, block=None, grid=None, top=25, split_us=None, out=None):
+    out = out or sys.stdout
     for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
         rows = _rows(f)
         rows.sort(key=lambda r: -float(_get(r, "TotalDurationNs", default="0")))

@@ -528,6 +528,8 @@ def main():
     ap.add_argument("--kernels-only", action="store_true", help="only the per-triplet Dslash table")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the warm-up and timed steps of the multi-shift solve (for kernel traces)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="enqueue the solver's iterations directly instead of replaying them as hipGraphs")
     ap.add_argument("--kernel", type=str, default=None,
                     help="only these rows of the Dslash table (comma-separated keys, e.g. int30_r8)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -659,6 +661,8 @@ def main():
         gms = hisq.pack_gauge(fat, lng, dims, f_ms.gauge, long_recon=rms)
         gref = gms if (f_ref.gauge == f_ms.gauge and rms == args.recon) else hisq.pack_gauge(
             fat, lng, dims, f_ref.gauge, long_recon=args.recon)
+        if args.no_graph:
+            kw["use_graph"] = 0
         return hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=ms, ref_fmt=ref, **kw)
 
     def step():
@@ -704,7 +708,7 @@ def main():
                  dslash_sloppy=st_["dslash_sloppy"], dslash_f64=st_["dslash_f64"]) for st_ in stats],
             config={"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "ms_triplet": repr(fms),
                     "refine_triplet": repr(fref), "ms_long_recon": ms_recon, "long_recon": args.recon,
-                    "batch_refine": args.batch_refine})))
+                    "batch_refine": args.batch_refine, "graphs": not args.no_graph})))
         return
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
@@ -797,7 +801,7 @@ def main():
                    "mass": args.mass, "shifts": [float(f"{s:.4g}") for s in shifts], "tol": args.tol,
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
                    "ms_long_recon": rms,
-                   "batch_refine": args.batch_refine,
+                   "batch_refine": args.batch_refine, "graphs": not args.no_graph,
                    "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "phase_seconds": [round(v, 3) for v in last["phase_seconds"]],

@@ -67,9 +67,12 @@ def log(*a):
 
 
 def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16, reps=10,
-                  names=("half", "int20", "single"), recon=18):
+                  names=("half", "int20", "single"), recon=18, shapes=None):
     """Block of nrhs right-hand sides (one link load per site for the block)
-    against nrhs single-right-hand-side applications (default 16 on 32^3x64)."""
+    against nrhs single-right-hand-side applications (default 16 on 32^3x64).
+    shapes: launch shapes (nr, rg, stage, sweep) to pin one after another with
+    hisq_tune_set and time (2 warm-up and `reps` timed launches each), in place
+    of the autotuned one."""
     V = dims[0] * dims[1] * dims[2] * dims[3]
     vh = V // 2
     fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED + 4, device=dev)
@@ -82,9 +85,30 @@ def bench_batched(args, hisq, inputs, torch, dev, dims=(32, 32, 32, 64), nrhs=16
         nb = hisq.hisq_spinor_bytes(vh, f.spinor)
         pin = torch.cat([hisq.pack_spinor(srcs[j], f.spinor)[:nb] for j in range(nrhs)]).contiguous()
         pout = torch.empty_like(pin)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if shapes:
+            block = 1
+            while block < nrhs:
+                block <<= 1
+            pinned = {}
+            for nr, rg, stage, sweep in shapes:
+                hisq.hisq_tune_set(name, dims, block, nr, rg, stage, 256, 0, sweep=sweep, long_recon=recon)
+                for _ in range(2):
+                    hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
+                e0.record(stream)
+                for _ in range(reps):
+                    hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                pinned[f"{nr},{rg},{stage},{sweep}"] = round(e0.elapsed_time(e1) / reps * 1e3, 1)
+                log(f"[bench] batched {name} {dims} x{nrhs} shape nr {nr} rg {rg} stage {stage} order {sweep}: "
+                    f"{pinned[f'{nr},{rg},{stage},{sweep}']} us")
+            hisq.hisq_tune_clear()
+            out[name] = dict(dims=list(dims), nrhs=nrhs, long_recon=recon, us_per_shape=pinned)
+            del pg, pin, pout
+            continue
         for _ in range(2):
             hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
             hisq.hisq_dslash_batched(pout, pin, pg.desc, 1, f, nrhs)
@@ -536,6 +560,8 @@ def main():
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--batched", action="store_true",
                     help="also time the 16-right-hand-side Dslash on 32^3x64 against 16 single applications")
+    ap.add_argument("--batched-shapes", type=str, default=None, metavar="NR,RG,STAGE,ORDER[;...]",
+                    help="with --batched-only: pin and time these launch shapes instead of the autotuned one")
     ap.add_argument("--batched-only", nargs="?", const="both", default=None, choices=("both", "32x64", "48x96"),
                     help="only the batched FIX16/INT20 Dslash with two-row long links: 16 right-hand sides on "
                          "32^3x64 and 11 (a block of 16) on 48^3x96, as the refinement runs it (for counters); "
@@ -570,7 +596,10 @@ def main():
 
     if args.batched_only:
         cases = {"32x64": ((32, 32, 32, 64), 16), "48x96": ((48, 48, 48, 96), 11)}
-        res = [bench_batched(args, hisq, inputs, torch, dev, dims=d, nrhs=n, names=("int20",), recon=12)
+        shapes = ([tuple(int(v) for v in sh.split(",")) for sh in args.batched_shapes.split(";") if sh.strip()]
+                  if args.batched_shapes else None)
+        res = [bench_batched(args, hisq, inputs, torch, dev, dims=d, nrhs=n, names=("int20",), recon=12,
+                             shapes=shapes)
                for k, (d, n) in cases.items() if args.batched_only in ("both", k)]
         print(json.dumps(dict(batched=res, tuning=hisq.hisq_tune_report().strip().splitlines())))
         return

@@ -722,6 +722,39 @@ def phase_param(z, lib=None):
 LONG8_FORMATS = ("f64", "fix32")
 
 
+def _long8_records(lng, ph, c, m, fmt, lib=None):
+    """the eight-parameter records of long links lng [..., 3, 3] with phases ph
+    [...], the global real c of L = c * phase * U and the long field's max
+    |real component| m (the fixed-point scale of the entries)"""
+    lng = np.asarray(lng, dtype=np.complex128)
+    w = lng * (ph * np.sign(c))[..., None, None]
+    z = np.stack([w[..., 0, 1], w[..., 0, 2], w[..., 1, 0],
+                  phase_param(w[..., 0, 0], lib) + 1j * phase_param(w[..., 2, 0], lib)], axis=-1)
+    if fmt == "f64":
+        return np.ascontiguousarray(z).view(np.float64)
+    q, _ = fix_encode(z[..., :3], 32, absmax=m, lib=lib)
+    qv, _ = fix_encode(z[..., 3], 32, absmax=1.0, lib=lib)
+    out = np.empty(z.shape[:-1] + (8,), dtype=np.int32)
+    out[..., :6] = q.reshape(z.shape[:-1] + (6,))
+    out[..., 6:] = qv.reshape(z.shape[:-1] + (2,))
+    return out
+
+
+def _long8_rebuild(rec, ph, c, m, fmt, lib=None):
+    """links from their eight-parameter records (the inverse storage step of
+    _long8_records, then su3_from_eight in FP64)"""
+    if fmt == "f64":
+        p = rec.astype(np.float64).copy()
+    else:
+        p = np.empty(rec.shape, dtype=np.float64)
+        p[..., :6] = fix_decode(np.ascontiguousarray(rec[..., :6]), m, 64, lib=lib).view(np.float64).reshape(
+            rec.shape[:-1] + (6,))
+        p[..., 6:] = fix_decode(np.ascontiguousarray(rec[..., 6:]), 1.0, 64, lib=lib).view(np.float64).reshape(
+            rec.shape[:-1] + (2,))
+    p[..., :6] /= abs(c)
+    return c * ph[..., None, None] * su3_from_eight(p)
+
+
 def long_recon8_encode(lng, dims, fmt, lib=None):
     """long links L = c * phase * U (U special unitary) stored as eight
     parameters per link, [4, V, 8]: Re/Im of the entries (0,1), (0,2) and
@@ -733,18 +766,7 @@ def long_recon8_encode(lng, dims, fmt, lib=None):
     if fmt not in LONG8_FORMATS:
         raise ValueError(f"eight-parameter long links in {fmt}")
     c, _ = long_link_split(lng, dims)
-    lng = np.asarray(lng, dtype=np.complex128)
-    w = lng * (long_phases(dims) * np.sign(c))[..., None, None]
-    z = np.stack([w[..., 0, 1], w[..., 0, 2], w[..., 1, 0],
-                  phase_param(w[..., 0, 0], lib) + 1j * phase_param(w[..., 2, 0], lib)], axis=-1)
-    if fmt == "f64":
-        return np.ascontiguousarray(z).view(np.float64)
-    q, _ = fix_encode(z[..., :3], 32, absmax=field_absmax(lng), lib=lib)
-    qv, _ = fix_encode(z[..., 3], 32, absmax=1.0, lib=lib)
-    out = np.empty(z.shape[:-1] + (8,), dtype=np.int32)
-    out[..., :6] = q.reshape(z.shape[:-1] + (6,))
-    out[..., 6:] = qv.reshape(z.shape[:-1] + (2,))
-    return out
+    return _long8_records(lng, long_phases(dims), c, field_absmax(lng), fmt, lib)
 
 
 def long_recon8_roundtrip(lng, dims, fmt, compute_bits=64, lib=None):
@@ -753,18 +775,18 @@ def long_recon8_roundtrip(lng, dims, fmt, compute_bits=64, lib=None):
     rebuild is covered by the tests' compute-precision allowance, amplified
     by the rebuild's conditioning)"""
     c, _ = long_link_split(lng, dims)
-    rec = long_recon8_encode(lng, dims, fmt, lib)
-    if fmt == "f64":
-        p = rec.astype(np.float64).copy()
-    else:
-        m = field_absmax(lng)
-        p = np.empty(rec.shape, dtype=np.float64)
-        p[..., :6] = fix_decode(np.ascontiguousarray(rec[..., :6]), m, 64, lib=lib).view(np.float64).reshape(
-            rec.shape[:-1] + (6,))
-        p[..., 6:] = fix_decode(np.ascontiguousarray(rec[..., 6:]), 1.0, 64, lib=lib).view(np.float64).reshape(
-            rec.shape[:-1] + (2,))
-    p[..., :6] /= abs(c)
-    return c * long_phases(dims)[..., None, None] * su3_from_eight(p)
+    m = field_absmax(lng)
+    ph = long_phases(dims)
+    return _long8_rebuild(_long8_records(lng, ph, c, m, fmt, lib), ph, c, m, fmt, lib)
+
+
+def long8_links_roundtrip(lng, ph, c, m, fmt, lib=None):
+    """long_recon8_roundtrip for a subset of the links of a field: lng
+    [..., 3, 3], their phases ph [...] (from long_phases), the field's c and
+    max |real component| m given"""
+    if fmt not in LONG8_FORMATS:
+        raise ValueError(f"eight-parameter long links in {fmt}")
+    return _long8_rebuild(_long8_records(lng, ph, c, m, fmt, lib), ph, c, m, fmt, lib)
 
 
 def emulated_dslash(fat, lng, psi, dims, parity, gauge_fmt, spinor_fmt, compute_bits, lib=None, long_recon=18):

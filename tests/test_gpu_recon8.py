@@ -142,3 +142,75 @@ def test_recon8_rejections():
         hisq.hisq_dslash_multi([torch.empty_like(pin[:nb])], [pin[:nb]], [g8.desc], 0, f)
     with pytest.raises(hisq.HisqError, match="HISQ_EINVAL"):
         hisq.hisq_tune_set("int30", dims, 4, 4, 1, 1, 256, 0, long_recon=8)
+
+
+@pytest.mark.parametrize("name", TRIPLETS8)
+def test_full_size_sampled_recon8(name):
+    """48^3x96 (the benchmark lattice) with the multi-shift operator's long-link
+    storage, eight parameters, in the autotuned launch shape the benchmark
+    times: sampled output sites against the oracle's emulation of the same
+    storage, evaluated site by site, within the bound of test_dslash_recon8"""
+    hisq = need_gpu()
+    dims = (48, 48, 48, 96)
+    V = oracle.volume(dims)
+    X, Y, Z, T = dims
+    fat, lng = inputs.make_links(dims, "near_unit", seed=inputs.GAUGE_SEED + 3, device="cuda")
+    psi = inputs.gaussian_spinor(V // 2, inputs.SOURCE_SEED + 3, device="cuda")
+    f = hisq.fmt(name)
+    gname, sname = GF_NAME[f.gauge], SF_NAME[f.spinor]
+    parity = 0
+    out_sites, in_sites = oracle.parity_sites(dims, parity), oracle.parity_sites(dims, 1 - parity)
+    rng = np.random.default_rng(2)
+    samp_cb = np.unique(np.concatenate([rng.integers(0, V // 2, 3000), [0, V // 2 - 1]]))
+    samp = out_sites[samp_cb]
+    co = [samp % X, (samp // X) % Y, (samp // (X * Y)) % Z, samp // (X * Y * Z)]
+    need_links, need_sp, long_hops = set(), set(), []
+    for mu in range(4):
+        for h in (1, -1, 3, -3):
+            cc = [v.copy() for v in co]
+            cc[mu] = (cc[mu] + h) % dims[mu]
+            nb = ((cc[3] * Z + cc[2]) * Y + cc[1]) * X + cc[0]
+            li = mu * V + (samp if h > 0 else nb)
+            need_sp.update(nb.tolist())
+            need_links.update(li.tolist())
+            if abs(h) == 3:
+                long_hops.append((li, nb))
+    lidx, sidx = np.array(sorted(need_links)), np.array(sorted(need_sp))
+    fat_h = fat.reshape(4 * V, 3, 3)[torch.from_numpy(lidx).cuda()].cpu().numpy()
+    lng_h = lng.reshape(4 * V, 3, 3)[torch.from_numpy(lidx).cuda()].cpu().numpy()
+    psi_h = psi[torch.from_numpy(np.searchsorted(in_sites, sidx)).cuda()].cpu().numpy()
+    fmax = float(torch.view_as_real(fat).abs().amax())
+    lmax = float(torch.view_as_real(lng).abs().amax())
+    c = -1.0 / 24.0                                           # the generator's long-link constant
+    pg = hisq.pack_gauge(fat, lng, dims, f.gauge, long_recon=hisq.RECON_8)
+    assert abs(pg.desc.long_coeff - c) < 1e-14 and pg.desc.long_max == lmax
+    pin = hisq.pack_spinor(psi, f.spinor)
+    y = hisq.unpack_spinor(hisq.dslash(pin, pg, parity, f), V // 2, f.spinor)
+    y = y[torch.from_numpy(samp_cb).cuda()].cpu().numpy()
+    del pg, pin, fat, lng, psi
+    torch.cuda.empty_cache()
+    full_fat = np.zeros((4 * V, 3, 3), dtype=np.complex128)   # lazily allocated; only touched entries used
+    full_lng = np.zeros((4 * V, 3, 3), dtype=np.complex128)
+    full_psi = np.zeros((V, 3), dtype=np.complex128)
+    if gname == "fix32":
+        qf, _ = oracle.fix_encode(fat_h, 32, absmax=fmax)
+        full_fat[lidx] = oracle.fix_decode(qf, fmax, 64, shape=fat_h.shape)
+    else:
+        full_fat[lidx] = oracle.gauge_roundtrip(fat_h, gname, 64)
+    ph = oracle.long_phases(dims).reshape(4 * V)[lidx]
+    full_lng[lidx] = oracle.long8_links_roundtrip(lng_h, ph, c, lmax, gname)
+    full_psi[sidx] = oracle.spinor_roundtrip(psi_h, sname)
+    ref = oracle.dslash_sites(full_fat.reshape(4, V, 3, 3), full_lng.reshape(4, V, 3, 3), full_psi, dims, samp)
+    # the FP64 rebuild's rounding, amplified by kappa of each long link, per sampled site
+    u = lng_h / (c * ph)[:, None, None]
+    kap = 1.0 / np.minimum(np.abs(u[:, 0, 1]) ** 2 + np.abs(u[:, 0, 2]) ** 2, np.abs(u[:, 2, 0]) ** 2)
+    allow = np.zeros(samp.size)
+    for li, nb in long_hops:
+        m = np.maximum(np.abs(full_psi[nb].real), np.abs(full_psi[nb].imag)).max(axis=1)
+        allow += kap[np.searchsorted(lidx, li)] * m
+    allow *= 3 * 1000 * 2.0 ** -52 * abs(c)
+    q = oracle.spinor_quantum(ref, sname)[:, None]
+    bound = 0.5 * q * (1 + 1e-3) + 2e-13 * np.abs(ref).max() + allow[:, None]
+    d = y - ref
+    worst = float((np.maximum(np.abs(d.real), np.abs(d.imag)) / bound).max())
+    assert worst <= 1.0, f"{name}: max err/bound {worst:.3f}"

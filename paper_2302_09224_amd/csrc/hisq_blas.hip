@@ -416,7 +416,8 @@ __global__ void k_norm2_f64(const char *v, size_t n, double *partial) {
 // ---------------------------------------------------------------------------
 
 template <int SF, class R>
-__global__ void k_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, double *partial, Guard gd) {
+__global__ void k_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, double *partial, Guard gd,
+                          char *r_copy) {
     __shared__ double lds[32];
     if (!gd.pass()) return;
     const R a = (R)(*alpha);
@@ -431,6 +432,7 @@ __global__ void k_cg_axpy(char *r, const char *ap, const double *alpha, size_t n
             rn.im[c] = fma(-a, av.im[c], ro.im[c]);
         }
         CVec<R> o = SpinorIO<SF, R>::store(r, n, s, rn);
+        if (r_copy) (void)SpinorIO<SF, R>::store(r_copy, n, s, rn);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             acc[0] += (double)o.re[c] * (double)o.re[c] + (double)o.im[c] * (double)o.im[c];
@@ -556,107 +558,76 @@ __global__ void k_ru_convert(char *rs, const char *r64, const char *p, const cha
     }
 }
 
-// x += sum_{q <= last} ai_buf[q][i] * slot q of shift i's gradient ring
-template <int SF, class R>
-__device__ __forceinline__ void flush_shift(char *x64, const char *ring, size_t slot_bytes, const SolverCtrl *ctrl,
-                                            int i, int last, const CVec<R> *cur, size_t n, size_t s) {
-    constexpr int LOAD_GROUP = load_group<SF>();
-    CVec<double> xv = SpinorIO<SF_F64, double>::load(x64, n, s);
-    // slot `last` may already be in registers (*cur); slots are loaded up to lim
-    const int lim = cur ? (last > 0 ? last - 1 : 0) : last;
-    for (int q0 = 0; q0 <= last; q0 += LOAD_GROUP) {
-        CVec<R> pq[LOAD_GROUP];
-        double a[LOAD_GROUP];
-#pragma unroll
-        for (int k = 0; k < LOAD_GROUP; k++) {
-            const int q = q0 + k;
-            const CVec<R> v = SpinorIO<SF, R>::load(ring + (size_t)min(q, lim) * slot_bytes, n, s);
-            const bool use_cur = cur && q == last;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                pq[k].re[c] = use_cur ? cur->re[c] : v.re[c];
-                pq[k].im[c] = use_cur ? cur->im[c] : v.im[c];
-            }
-            const double aq = ctrl->ai_buf[min(q, last)][i];
-            a[k] = q <= last ? aq : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < LOAD_GROUP; k++) {
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                xv.re[c] = fma(a[k], (double)pq[k].re[c], xv.re[c]);
-                xv.im[c] = fma(a[k], (double)pq[k].im[c], xv.im[c]);
-            }
-        }
-    }
-    SpinorIO<SF_F64, double>::store(x64, n, s, xv);
-}
-
-// One launch for every shifted system still being updated (Sec. 3.2).  The
-// shifted solutions are FP64 and, like the base solution, are updated from a
-// ring of buffered gradient vectors once every N_b iterations (Sec. 3.1 item 1)
-// and when the shift stops.
-template <int SF, class R>
-__global__ void k_shift_update(SpinorList x64, SpinorList p, const char *r, const SolverCtrl *ctrl, int nshift, size_t n,
-                               size_t slot_bytes, int jb, int jn, int flush_all, Guard gd) {
+// The shifted systems of the multi-shift CG (Sec. 3.2) over a block of
+// `count` iterations, every shift in one launch.  The shifted gradient
+// vectors obey p_i <- zeta_i r + beta_i p_i with the base residual r of the
+// same iteration, and the shifted solutions x_i += alpha_i p_i; the solutions
+// are updated once per block (buffered, Sec. 3.1 item 1).  So a shift's
+// gradient vector is stored only at the block's start: the block's base
+// residuals r_{k+1} are kept in a ring (rr.p[q], q < count), the finalize
+// kernel records the shifts' scalars of every iteration (slot q), and this
+// kernel replays the block's updates in registers, loading each residual once
+// per group of G shifts.  A shift that stops in slot q takes its x update of
+// that slot and no more; the shifts still active store their gradient vector
+// again for the next block.
+template <int SF, class R, int G>
+__global__ void __launch_bounds__(BLAS_BLOCK) k_shift_replay(SpinorList x64, SpinorList p, SpinorList rr,
+                                                             const SolverCtrl *ctrl, int nshift, size_t n, int count,
+                                                             Guard gd) {
     if (!gd.pass()) return;
-    const unsigned sel = (unsigned)ctrl->e_mask & ~1u & (nshift >= 32 ? ~0u : (1u << nshift) - 1u);
-    const int rm = ctrl->rm_mask;
-    constexpr int LOAD_GROUP = load_group<SF>();
+    const unsigned all = nshift >= 32 ? ~0u : (1u << nshift) - 1u;
+    const unsigned upd = (unsigned)ctrl->eb_buf[0] & ~1u & all;   // shifts can only leave during a block
+    const unsigned keep = (unsigned)ctrl->eb_buf[count - 1] & ~(unsigned)ctrl->rmb_buf[count - 1];
     for (size_t s = gtid(); s < n; s += gstride()) {
-        CVec<R> rv = SpinorIO<SF, R>::load(r, n, s);
-        // the shifts being updated, a group at a time: their current gradient
-        // vectors are loaded together, then each is updated
-        for (unsigned m = sel; m;) {
-            int ids[LOAD_GROUP];
+        for (unsigned m = upd; m;) {
+            int ids[G];
 #pragma unroll
-            for (int k = 0; k < LOAD_GROUP; k++) {
+            for (int k = 0; k < G; k++) {
                 ids[k] = m ? __builtin_ctz(m) : -1;
                 m &= m - 1u;
             }
-            CVec<R> pv[LOAD_GROUP];
+            CVec<R> pv[G];
+            CVec<double> xv[G];
 #pragma unroll
-            for (int k = 0; k < LOAD_GROUP; k++)
-                pv[k] = SpinorIO<SF, R>::load(p.p[ids[k] >= 0 ? ids[k] : ids[0]] + jb * slot_bytes, n, s);
+            for (int k = 0; k < G; k++) {
+                const int i = ids[k] >= 0 ? ids[k] : ids[0];   // a short group repeats its first shift, unused
+                pv[k] = SpinorIO<SF, R>::load(p.p[i], n, s);
+                xv[k] = SpinorIO<SF_F64, double>::load(x64.p[i], n, s);
+            }
+            for (int q = 0; q < count; q++) {
+                const CVec<R> rv = SpinorIO<SF, R>::load(rr.p[q], n, s);
+                const unsigned eq = (unsigned)ctrl->eb_buf[q], sq = (unsigned)ctrl->rmb_buf[q];
 #pragma unroll
-            for (int k = 0; k < LOAD_GROUP; k++) {
-                const int i = ids[k];
-                if (i < 0) break;
-                const char *ring = p.p[i];
-                const int stopped = (rm >> i) & 1;
-                if (flush_all || stopped) flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, &pv[k], n, s);
-                if (!stopped) {
-                    const R bi = (R)ctrl->beta_i[i], zi = (R)ctrl->zeta[i];
-                    CVec<R> pn;
+                for (int k = 0; k < G; k++) {
+                    const int i = ids[k];
+                    if (i < 0 || !((eq >> i) & 1u)) continue;
+                    const double a = ctrl->ai_buf[q][i];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        pn.re[c] = fma(zi, rv.re[c], bi * pv[k].re[c]);
-                        pn.im[c] = fma(zi, rv.im[c], bi * pv[k].im[c]);
+                        xv[k].re[c] = fma(a, (double)pv[k].re[c], xv[k].re[c]);
+                        xv[k].im[c] = fma(a, (double)pv[k].im[c], xv[k].im[c]);
                     }
-                    SpinorIO<SF, R>::store(p.p[i] + jn * slot_bytes, n, s, pn);
+                    if ((sq >> i) & 1u) continue;
+                    const R zi = (R)ctrl->zb_buf[q][i], bi = (R)ctrl->bb_buf[q][i];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        pv[k].re[c] = fma(zi, rv.re[c], bi * pv[k].re[c]);
+                        pv[k].im[c] = fma(zi, rv.im[c], bi * pv[k].im[c]);
+                    }
                 }
+            }
+#pragma unroll
+            for (int k = 0; k < G; k++) {
+                const int i = ids[k];
+                if (i < 0) continue;
+                SpinorIO<SF_F64, double>::store(x64.p[i], n, s, xv[k]);
+                if ((keep >> i) & 1u) (void)SpinorIO<SF, R>::store(p.p[i], n, s, pv[k]);
             }
         }
     }
 }
-
-// after a block of iterations ended at slot jb < N_b-1: flush the buffered
-// slots of the shifts still being updated and move their newest gradient
-// vector (slot jb+1) to slot 0, where the next block starts
-template <int SF, class R>
-__global__ void k_shift_realign(SpinorList x64, SpinorList p, const SolverCtrl *ctrl, int nshift, size_t n,
-                                size_t slot_bytes, int jb) {
-    const int mask = ctrl->active_mask;
-    for (size_t s = gtid(); s < n; s += gstride()) {
-        for (int i = 1; i < nshift; i++) {
-            if (!((mask >> i) & 1)) continue;
-            char *ring = p.p[i];
-            flush_shift<SF, R>(x64.p[i], ring, slot_bytes, ctrl, i, jb, nullptr, n, s);
-            const CVec<R> pn = SpinorIO<SF, R>::load(ring + (jb + 1) * slot_bytes, n, s);
-            SpinorIO<SF, R>::store(ring, n, s, pn);
-        }
-    }
-}
+// shifts per group: the gradient vectors and FP64 solutions of four shifts in registers
+constexpr int REPLAY_GROUP = 4;
 
 // ---------------------------------------------------------------------------
 // batched (nrhs independent systems) vector updates
@@ -925,8 +896,8 @@ hipError_t launch_norm2_f64(const char *v, size_t n, double *partial, int *nbloc
 }
 
 hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, int sf, int compute, double *partial,
-                          Guard gd, hipStream_t st) {
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_axpy<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r, ap, alpha, n, partial, gd));
+                          Guard gd, hipStream_t st, char *r_copy) {
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_cg_axpy<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, r, ap, alpha, n, partial, gd, r_copy));
     return hipGetLastError();
 }
 
@@ -974,8 +945,8 @@ int resident_grid(const void *fn, size_t n) {
     }
     return std::min(nb, it->second);
 }
-hipError_t shift_update_kernel(int sf, int compute, const void **fn) {
-    HISQ_DISPATCH_SC(sf, compute, *fn = reinterpret_cast<const void *>(&k_shift_update<SFc, Rc>));
+hipError_t shift_replay_kernel(int sf, int compute, const void **fn) {
+    HISQ_DISPATCH_SC(sf, compute, *fn = reinterpret_cast<const void *>(&k_shift_replay<SFc, Rc, REPLAY_GROUP>));
     return hipSuccess;
 }
 hipError_t flush_x_kernel(int sf, int compute, const void **fn) {
@@ -984,9 +955,9 @@ hipError_t flush_x_kernel(int sf, int compute, const void **fn) {
 }
 }  // namespace
 
-int shift_update_grid(size_t n, int sf, int compute) {
+int shift_replay_grid(size_t n, int sf, int compute) {
     const void *fn = nullptr;
-    return resident_grid(shift_update_kernel(sf, compute, &fn) == hipSuccess ? fn : nullptr, n);
+    return resident_grid(shift_replay_kernel(sf, compute, &fn) == hipSuccess ? fn : nullptr, n);
 }
 
 int flush_x_grid(size_t n, int sf, int compute) {
@@ -994,17 +965,11 @@ int flush_x_grid(size_t n, int sf, int compute) {
     return resident_grid(flush_x_kernel(sf, compute, &fn) == hipSuccess ? fn : nullptr, n);
 }
 
-hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
-                               int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
-                               int compute, Guard gd, hipStream_t st) {
-    const int nb = shift_update_grid(n, sf, compute);
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_update<SFc, Rc>), dim3(nb), dim3(BLAS_BLOCK), 0, st, x64, p, r, ctrl, nshift, n, slot_bytes, jb, jn, flush_all, gd));
-    return hipGetLastError();
-}
-
-hipError_t launch_shift_realign(const SpinorList &x64, const SpinorList &p, const SolverCtrl *ctrl, int nshift,
-                                size_t n, size_t slot_bytes, int jb, int sf, int compute, hipStream_t st) {
-    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_realign<SFc, Rc>), dim3(blas_blocks(n)), dim3(BLAS_BLOCK), 0, st, x64, p, ctrl, nshift, n, slot_bytes, jb));
+hipError_t launch_shift_replay(const SpinorList &x64, const SpinorList &p, const SpinorList &rr, const SolverCtrl *ctrl,
+                               int nshift, size_t n, int count, int sf, int compute, Guard gd, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int nb = shift_replay_grid(n, sf, compute);
+    HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_replay<SFc, Rc, REPLAY_GROUP>), dim3(nb), dim3(BLAS_BLOCK), 0, st, x64, p, rr, ctrl, nshift, n, count, gd));
     return hipGetLastError();
 }
 

@@ -220,8 +220,12 @@ struct SolverCtrl {
     double tol2_i[HISQ_MAX_SHIFTS];
     double zeta[HISQ_MAX_SHIFTS], zeta_prev[HISQ_MAX_SHIFTS];
     double alpha_i[HISQ_MAX_SHIFTS], beta_i[HISQ_MAX_SHIFTS];
-    double ai_buf[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];  // alpha_i of each buffered gradient slot
-    int rm_mask;     // multi-shift: shifts that stopped in this iteration (flush their buffers)
+    double ai_buf[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];  // alpha_i of each iteration (slot) of the block
+    double zb_buf[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];  // zeta_i after each iteration of the block
+    double bb_buf[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];  // beta_i of each iteration of the block
+    int eb_buf[HISQ_MAX_GRAD_BUFFER];   // shifts updated in each iteration of the block
+    int rmb_buf[HISQ_MAX_GRAD_BUFFER];  // shifts that stopped in each iteration of the block
+    int rm_mask;     // multi-shift: shifts that stopped in this iteration
     int shift_stop_k[HISQ_MAX_SHIFTS];
     // batched CG: per right-hand side scalars
     double brho[16], brho_prev[16], brho_new[16], bgamma[16], bpi[16], balpha[16], bbeta[16];
@@ -243,9 +247,10 @@ struct SpinorList {
     char *p[HISQ_MAX_SHIFTS];
 };
 
-// r = r - alpha*ap; partial (|r'|^2, Re<r', r>)
+// r = r - alpha*ap; partial (|r'|^2, Re<r', r>); r_copy (optional): the new r
+// stored a second time there (the multi-shift ring of base residuals)
 hipError_t launch_cg_axpy(char *r, const char *ap, const double *alpha, size_t n, int sf, int compute,
-                          double *partial, Guard gd, hipStream_t st);
+                          double *partial, Guard gd, hipStream_t st, char *r_copy = nullptr);
 // p_dst = pa*r + pb*p_src, (pa, pb) from the control block
 // (ppart: optional per-block |p_dst|^2 of the stored values)
 hipError_t launch_cg_pupdate(char *p_dst, const char *r, const char *p_src, const SolverCtrl *ctrl, double *ppart,
@@ -256,22 +261,21 @@ hipError_t launch_flush_x(char *x64, const SpinorList &p, int count, const doubl
 // r_s = pack(r64); partial (|r_s|^2, Re<r_s,p>, Im<r_s,p>, Re<r_s, r_old + alpha ap>)
 hipError_t launch_ru_convert(char *r_s, const char *r64, const char *p, const char *ap, const double *alpha,
                              size_t n, int sf, int compute, double *partial, Guard gd, hipStream_t st);
-// multi-shift, one launch for every shift of ctrl->e_mask: p_i[jn] = zeta_i r + beta_i p_i[jb]
-// (ring of gradient slots `slot_bytes` apart starting at p.p[i]); x_i += sum_{q<=jb} ai_buf[q][i] p_i[q]
-// when flush_all or when shift i stopped in this iteration (buffered FP64 solution update)
-hipError_t launch_shift_update(const SpinorList &x64, const SpinorList &p, const char *r, const SolverCtrl *ctrl,
-                               int nshift, size_t n, size_t slot_bytes, int jb, int jn, int flush_all, int sf,
-                               int compute, Guard gd, hipStream_t st);
-// grids of launch_shift_update and launch_flush_x: blas_blocks(n) capped at
+// multi-shift, the shifted systems over a block of `count` iterations, all
+// shifts in one launch: shift i's gradient vector p.p[i] holds p_i at the
+// block's start; with the base residuals r_{k+1} of the block's iterations in
+// rr.p[0..count) and the scalars recorded per iteration (ai_buf, zb_buf,
+// bb_buf, eb_buf, rmb_buf), x_i += alpha_i p_i and p_i = zeta_i r + beta_i p_i
+// are replayed in registers; p_i is stored again for the shifts still active
+hipError_t launch_shift_replay(const SpinorList &x64, const SpinorList &p, const SpinorList &rr, const SolverCtrl *ctrl,
+                               int nshift, size_t n, int count, int sf, int compute, Guard gd, hipStream_t st);
+// grids of launch_shift_replay and launch_flush_x: blas_blocks(n) capped at
 // the blocks of that kernel the device holds at once (a larger grid leaves
 // blocks that start only after the first ones finish, on a device that is then
 // mostly idle).  The occupancy is queried once per device and triplet; the
 // solvers call these before they capture a graph.
-int shift_update_grid(size_t n, int sf, int compute);
+int shift_replay_grid(size_t n, int sf, int compute);
 int flush_x_grid(size_t n, int sf, int compute);
-// multi-shift, shifts of ctrl->active_mask: flush slots 0..jb into x_i and move slot jb+1 to slot 0
-hipError_t launch_shift_realign(const SpinorList &x64, const SpinorList &p, const SolverCtrl *ctrl, int nshift,
-                                size_t n, size_t slot_bytes, int jb, int sf, int compute, hipStream_t st);
 
 // batched versions (nrhs consecutive fields of `stride` bytes)
 hipError_t launch_bcg_axpy(char *r, const char *ap, const SolverCtrl *ctrl, size_t n, size_t stride, int nrhs,

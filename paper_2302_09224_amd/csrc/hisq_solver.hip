@@ -136,6 +136,8 @@ __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd
             c->alpha_i[i] = a * ratio;
             c->ai_buf[jb][i] = a * ratio;
             c->beta_i[i] = beta * ratio * ratio;
+            c->zb_buf[jb][i] = zn;
+            c->bb_buf[jb][i] = beta * ratio * ratio;
             c->zeta_prev[i] = z;
             c->zeta[i] = zn;
             emask |= 1 << i;
@@ -147,6 +149,8 @@ __global__ void k_fin_beta(SolverCtrl *c, const double *partial, int n, Guard gd
         }
         c->e_mask = emask;
         c->rm_mask = rm;
+        c->eb_buf[jb] = emask;
+        c->rmb_buf[jb] = rm;
         c->active_mask = amask;
         c->alpha_prev = a;
         c->beta_prev = beta;
@@ -303,7 +307,8 @@ struct CgBuffers {
     char *p[HISQ_MAX_GRAD_BUFFER];
     char *pconv;                       // multi-shift: base gradient vector in the refinement format
     char *xs[HISQ_MAX_SHIFTS];         // multi-shift: FP64 shifted solutions (index >= 1)
-    char *ps[HISQ_MAX_SHIFTS];         // multi-shift: shifted gradient vectors (index >= 1)
+    char *ps[HISQ_MAX_SHIFTS];         // multi-shift: shifted gradient vectors at the block's start (index >= 1)
+    char *rr[HISQ_MAX_GRAD_BUFFER];    // multi-shift: the base residuals of the block's iterations
 };
 
 // sloppy_bytes: bytes/site of the largest sloppy format used; ms_bytes: of the
@@ -328,12 +333,15 @@ size_t carve_cg(CgBuffers *b, char *base, const Geom &g, int sloppy_bytes, int n
     for (int i = 0; i < HISQ_MAX_GRAD_BUFFER; i++) B.p[i] = i < nb ? cv.take(sloppy_bytes * vh) : nullptr;
     B.pconv = nullptr;
     for (int i = 0; i < HISQ_MAX_SHIFTS; i++) B.xs[i] = B.ps[i] = nullptr;
+    for (int i = 0; i < HISQ_MAX_GRAD_BUFFER; i++) B.rr[i] = nullptr;
     if (ms_bytes > 0) {
         B.pconv = cv.take(ref_bytes * vh);
         for (int i = 1; i < nshift; i++) {
             B.xs[i] = cv.take(48 * vh);
-            B.ps[i] = cv.take((size_t)nb * ms_bytes * vh);  // ring of nb gradient slots
+            B.ps[i] = cv.take((size_t)ms_bytes * vh);
         }
+        if (nshift > 1)
+            for (int q = 0; q < nb; q++) B.rr[q] = cv.take((size_t)ms_bytes * vh);
     }
     return cv.off;
 }
@@ -386,7 +394,7 @@ struct Run {
         nb_64 = dslash_tile_blocks(g, plan_64.tile[0]);
         // occupancy queries of the capped-grid kernels, before any capture
         (void)flush_x_grid(vh, fmt.spinor, fmt.compute);
-        if (multishift) (void)shift_update_grid(vh, fmt.spinor, fmt.compute);
+        if (multishift) (void)shift_replay_grid(vh, fmt.spinor, fmt.compute);
     }
 
     DslashArgs dargs(const hisq_gauge *gg, char *out, const char *in, int parity) const {
@@ -423,19 +431,12 @@ struct Run {
         hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial,
                            nb_s, jb, gns);
         HISQ_TRY_HIP(hipGetLastError());
-        HISQ_TRY_HIP(launch_cg_axpy(B->rs, B->aps, &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, gns, st));
+        HISQ_TRY_HIP(launch_cg_axpy(B->rs, B->aps, &c->alpha, vh, fmt.spinor, fmt.compute, B->partial, gns, st,
+                                    multishift ? B->rr[jb] : nullptr));
         hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(FIN_THREADS), 0, st, c, B->partial, blas_blocks(vh), gns,
                            multishift ? 1 : 0, jb, B->ppart, blas_blocks(vh));
         HISQ_TRY_HIP(hipGetLastError());
-        if (multishift) {
-            SpinorList xl, pl;
-            for (int i = 0; i < HISQ_MAX_SHIFTS; i++) {
-                xl.p[i] = B->xs[i];
-                pl.p[i] = B->ps[i];
-            }
-            HISQ_TRY_HIP(launch_shift_update(xl, pl, B->rs, c, nshift, vh, slot_bytes(), jb, jn, jb == nb - 1,
-                                             fmt.spinor, fmt.compute, gns, st));
-        }
+        if (multishift && jb == nb - 1) HISQ_TRY(enq_shift_replay(nb, gns));
         if (jb == nb - 1) {
             SpinorList pl;
             for (int i = 0; i < HISQ_MAX_SHIFTS; i++) pl.p[i] = i < nb ? B->p[i] : nullptr;
@@ -447,19 +448,24 @@ struct Run {
     double c_ = 0.0;
 
     // bytes between the gradient slots of one shift's ring
-    size_t slot_bytes() const { return (size_t)spinor_site_bytes(fmt.spinor) * vh; }
-
-    // a block ended at gradient slot jb: shifts still being updated flush their
-    // buffered slots and restart their ring at slot 0 like the base
-    hisq_status realign_shifts(int jb) {
-        if (!multishift || jb == nb - 1) return HISQ_OK;
-        SpinorList xl, pl;
+    // the shifted systems' updates of the block's first `count` iterations
+    hisq_status enq_shift_replay(int count, Guard gd) {
+        SpinorList xl, pl, rl;
         for (int i = 0; i < HISQ_MAX_SHIFTS; i++) {
             xl.p[i] = B->xs[i];
             pl.p[i] = B->ps[i];
+            rl.p[i] = i < HISQ_MAX_GRAD_BUFFER ? B->rr[i] : nullptr;
         }
-        HISQ_TRY_HIP(launch_shift_realign(xl, pl, B->ctrl, nshift, vh, slot_bytes(), jb, fmt.spinor, fmt.compute, st));
+        HISQ_TRY_HIP(launch_shift_replay(xl, pl, rl, B->ctrl, nshift, vh, count, fmt.spinor, fmt.compute, gd, st));
         return HISQ_OK;
+    }
+
+    // a block ended early at slot jb (reliable update, end of the phase): the
+    // shifted systems take the block's iterations so far, and like the base
+    // restart at slot 0
+    hisq_status realign_shifts(int jb) {
+        if (!multishift || jb == nb - 1) return HISQ_OK;
+        return enq_shift_replay(jb + 1, Guard{nullptr, 0, 0});
     }
 
     // r64 = b - (c x64 - D_eo D_oe x64), |r64|^2 -> done flag (FP64 operator)
@@ -560,11 +566,12 @@ struct Run {
             dslash_sloppy += 2 * dk;
             alg_bytes += dk * iter_bytes();
             if (multishift) {
-                // r once; per updated shift: its slot read and the next one written, plus
-                // the ring flush (N_b-1 more slots and an FP64 read-modify-write) every N_b
+                // the base residual written to the ring and read back once per block; per
+                // updated shift, once per block of N_b iterations: its gradient vector read
+                // and written and its FP64 solution read and written
                 const double bs = spinor_site_bytes(fmt.spinor);
                 const int ne = __builtin_popcount((unsigned)h->e_mask);
-                alg_bytes += dk * (double)vh * (bs + ne * (2.0 * bs + ((nb - 1) * bs + 96.0) / nb));
+                alg_bytes += dk * (double)vh * (2.0 * bs + ne * (2.0 * bs + 96.0) / nb);
             }
             if (h->stop == STOP_NEVER) continue;
             if (h->breakdown)

@@ -328,8 +328,9 @@ size_t hisq_multishift_workspace_bytes(const int dims[4], int nshift, hisq_fmt m
 /* Mixed-precision multi-shift CG with post-solve refinement (Sec. 3.2):
  * x_i = (4m^2 + shift_i - D_eo D_oe)^-1 b for i = 0..nshift-1.  One Krylov
  * space of the base system (shift_0, the smallest) built in the ms_fmt
- * triplet with reliable updates on the base only; all shifted solutions
- * (FP64) and gradient vectors are updated in one fused launch per iteration;
+ * triplet with reliable updates on the base only; the shifted solutions
+ * (FP64) and gradient vectors are updated once per block of grad_buffer
+ * iterations, all shifts in one launch, from the block's base residuals;
  * shift i stops updating when its iterated residual reaches
  * max(tol_i, shift_floor); the phase ends when every shift i >= 1 has
  * stopped.  Then CG refinement in the refine_fmt triplet: the base keeping

@@ -141,6 +141,65 @@ def test_multishift(ms, ref, batch):
         assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
 
 
+@pytest.mark.parametrize("ms,ref", [("double", "double"), ("single", "half")])
+def test_multishift_block_size_invariance(ms, ref):
+    """The shifted systems are updated once per block of grad_buffer
+    iterations, replaying the block's recurrences from its base residuals; with
+    IEEE storage of the multi-shift vectors (nothing is quantised between
+    iterations) the arithmetic and its order do not depend on where the blocks
+    end.  So the solutions, iterations and reliable updates are bit-identical
+    for every block size, chunk length (where the host looks) and with or
+    without graph replay, also when shifts stop and reliable updates fall
+    inside a block."""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.02
+    shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
+    tol = [1e-10, 1e-9, 1e-10, 1e-8, 1e-10, 1e-11]
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", ms, ref])
+    runs = []
+    for opts in (dict(grad_buffer=8), dict(grad_buffer=1), dict(grad_buffer=3, poll_every=7),
+                 dict(grad_buffer=16), dict(grad_buffer=5, use_graph=0)):
+        xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[hisq.fmt(ms).gauge],
+                                          pg[hisq.fmt(ref).gauge], mass, ms_fmt=ms, ref_fmt=ref, **opts)
+        assert st["status"] == "HISQ_OK", (opts, st)
+        runs.append((opts, [x.cpu().numpy() for x in xs], st))
+    opts0, x0, st0 = runs[0]
+    assert st0["reliable_updates"] > 1 and len(set(st0["shift_iters"][1:len(shifts)])) > 1, st0
+    for opts, xs, st in runs[1:]:
+        assert st["iters"] == st0["iters"] and st["refine_iters"] == st0["refine_iters"], (opts, st, st0)
+        assert st["reliable_updates"] == st0["reliable_updates"], (opts, st, st0)
+        for i in range(len(shifts)):
+            assert np.array_equal(xs[i].view(np.uint64), x0[i].view(np.uint64)), (opts, i)
+    for i, s in enumerate(shifts):
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x0[i]), full(dims, ev, b), dims, mass, s)
+        assert res <= tol[i] * (1 + 1e-6), (i, res)
+
+
+@pytest.mark.parametrize("nb", [1, 3, 16])
+def test_multishift_quantised_block_sizes(nb):
+    """30-bit multi-shift vectors (the benchmark's format) with blocks of 1, 3
+    (shifts stop and reliable updates fall inside blocks) and 16 iterations:
+    every shift still reaches its true residual and the oracle's solution"""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
+    tol = [1e-10] * len(shifts)
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "int30", "int20"])
+    xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[hisq.fmt("int30").gauge],
+                                      pg[hisq.fmt("int20").gauge], mass, ms_fmt="int30", ref_fmt="int20",
+                                      grad_buffer=nb, poll_every=7)
+    assert st["status"] == "HISQ_OK", st
+    out = oracle.multishift_cg(fat.numpy(), lng.numpy(), full(dims, ev, b), dims, mass, shifts, 1e-12)
+    for i, s in enumerate(shifts):
+        x = xs[i].cpu().numpy()
+        res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass, s)
+        assert res <= tol[i] * (1 + 1e-6), (nb, i, res, st)
+        xo = out["x"][i][ev]
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8, (nb, i)
+
+
 def test_multishift_per_shift_tolerances():
     """RHMC-like: every shift has its own target (Sec. 6.2 footnote)"""
     hisq = need_gpu()

@@ -570,14 +570,31 @@ __global__ void k_ru_convert(char *rs, const char *r64, const char *p, const cha
 // per group of G shifts.  A shift that stops in slot q takes its x update of
 // that slot and no more; the shifts still active store their gradient vector
 // again for the next block.
+constexpr int RING_LOADS = 4;
 template <int SF, class R, int G>
 __global__ void __launch_bounds__(BLAS_BLOCK) k_shift_replay(SpinorList x64, SpinorList p, SpinorList rr,
                                                              const SolverCtrl *ctrl, int nshift, size_t n, int count,
                                                              Guard gd) {
+    // the block's scalars staged in LDS: their reads then wait on the LDS
+    // counter, not behind the residual loads in flight
+    __shared__ double s_a[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS], s_z[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS],
+        s_b[HISQ_MAX_GRAD_BUFFER][HISQ_MAX_SHIFTS];
+    __shared__ unsigned s_e[HISQ_MAX_GRAD_BUFFER], s_r[HISQ_MAX_GRAD_BUFFER];
     if (!gd.pass()) return;
+    for (int t = threadIdx.x; t < count * HISQ_MAX_SHIFTS; t += blockDim.x) {
+        const int q = t / HISQ_MAX_SHIFTS, i = t % HISQ_MAX_SHIFTS;
+        s_a[q][i] = ctrl->ai_buf[q][i];
+        s_z[q][i] = ctrl->zb_buf[q][i];
+        s_b[q][i] = ctrl->bb_buf[q][i];
+    }
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+        s_e[t] = (unsigned)ctrl->eb_buf[t];
+        s_r[t] = (unsigned)ctrl->rmb_buf[t];
+    }
+    __syncthreads();
     const unsigned all = nshift >= 32 ? ~0u : (1u << nshift) - 1u;
-    const unsigned upd = (unsigned)ctrl->eb_buf[0] & ~1u & all;   // shifts can only leave during a block
-    const unsigned keep = (unsigned)ctrl->eb_buf[count - 1] & ~(unsigned)ctrl->rmb_buf[count - 1];
+    const unsigned upd = s_e[0] & ~1u & all;   // shifts can only leave during a block
+    const unsigned keep = s_e[count - 1] & ~s_r[count - 1];
     for (size_t s = gtid(); s < n; s += gstride()) {
         for (unsigned m = upd; m;) {
             int ids[G];
@@ -594,28 +611,39 @@ __global__ void __launch_bounds__(BLAS_BLOCK) k_shift_replay(SpinorList x64, Spi
                 pv[k] = SpinorIO<SF, R>::load(p.p[i], n, s);
                 xv[k] = SpinorIO<SF_F64, double>::load(x64.p[i], n, s);
             }
-            for (int q = 0; q < count; q++) {
-                const CVec<R> rv = SpinorIO<SF, R>::load(rr.p[q], n, s);
-                const unsigned eq = (unsigned)ctrl->eb_buf[q], sq = (unsigned)ctrl->rmb_buf[q];
+            // iteration q of the block, in order
+            auto step = [&](int q, const CVec<R> &rv) {
+                const unsigned eq = s_e[q], sq = s_r[q];
 #pragma unroll
                 for (int k = 0; k < G; k++) {
                     const int i = ids[k];
                     if (i < 0 || !((eq >> i) & 1u)) continue;
-                    const double a = ctrl->ai_buf[q][i];
+                    const double a = s_a[q][i];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
                         xv[k].re[c] = fma(a, (double)pv[k].re[c], xv[k].re[c]);
                         xv[k].im[c] = fma(a, (double)pv[k].im[c], xv[k].im[c]);
                     }
                     if ((sq >> i) & 1u) continue;
-                    const R zi = (R)ctrl->zb_buf[q][i], bi = (R)ctrl->bb_buf[q][i];
+                    const R zi = (R)s_z[q][i], bi = (R)s_b[q][i];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
                         pv[k].re[c] = fma(zi, rv.re[c], bi * pv[k].re[c]);
                         pv[k].im[c] = fma(zi, rv.im[c], bi * pv[k].im[c]);
                     }
                 }
+            };
+            // the residuals are loaded RING_LOADS slots at a time, all in flight
+            // before the first of them is used; the updates keep slot order
+            int q = 0;
+            for (; q + RING_LOADS <= count; q += RING_LOADS) {
+                CVec<R> rv[RING_LOADS];
+#pragma unroll
+                for (int u = 0; u < RING_LOADS; u++) rv[u] = SpinorIO<SF, R>::load(rr.p[q + u], n, s);
+#pragma unroll
+                for (int u = 0; u < RING_LOADS; u++) step(q + u, rv[u]);
             }
+            for (; q < count; q++) step(q, SpinorIO<SF, R>::load(rr.p[q], n, s));
 #pragma unroll
             for (int k = 0; k < G; k++) {
                 const int i = ids[k];
@@ -968,6 +996,7 @@ int flush_x_grid(size_t n, int sf, int compute) {
 hipError_t launch_shift_replay(const SpinorList &x64, const SpinorList &p, const SpinorList &rr, const SolverCtrl *ctrl,
                                int nshift, size_t n, int count, int sf, int compute, Guard gd, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (count > HISQ_MAX_GRAD_BUFFER || nshift > HISQ_MAX_SHIFTS) return hipErrorInvalidValue;
     const int nb = shift_replay_grid(n, sf, compute);
     HISQ_DISPATCH_SC(sf, compute, hipLaunchKernelGGL((k_shift_replay<SFc, Rc, REPLAY_GROUP>), dim3(nb), dim3(BLAS_BLOCK), 0, st, x64, p, rr, ctrl, nshift, n, count, gd));
     return hipGetLastError();

@@ -535,6 +535,9 @@ def main():
     ap.add_argument("--batch-refine", type=int, default=3, choices=(0, 1, 2, 3),
                     help="refine the shifted systems together (1), together while the base is refined "
                          "concurrently (2), together with the base in the same block (3), or one after another (0)")
+    ap.add_argument("--shift-floor", type=float, default=0.0,
+                    help="multi-shift: relative residual below which a shifted system stops (0: none with FP64 "
+                         "arithmetic, the spinor format's epsilon with FP32 arithmetic)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the 16^4 CG-stability table (not part of the timed step)")
@@ -695,7 +698,8 @@ def main():
         return hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=ms, ref_fmt=ref, **kw)
 
     def step():
-        return solve_once(args.ms, args.ref, ms_long=ms_recon, batch_refine=args.batch_refine)
+        return solve_once(args.ms, args.ref, ms_long=ms_recon, batch_refine=args.batch_refine,
+                          shift_floor=args.shift_floor)
 
     def timed_once(ms, ref, **kw):
         """one warm-up solve (launch shapes of new keys are tuned there), then one timed"""
@@ -737,7 +741,8 @@ def main():
                  dslash_sloppy=st_["dslash_sloppy"], dslash_f64=st_["dslash_f64"]) for st_ in stats],
             config={"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "ms_triplet": repr(fms),
                     "refine_triplet": repr(fref), "ms_long_recon": ms_recon, "long_recon": args.recon,
-                    "batch_refine": args.batch_refine, "graphs": not args.no_graph})))
+                    "batch_refine": args.batch_refine, "graphs": not args.no_graph,
+                    "shift_floor": args.shift_floor or "auto"})))
         return
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
@@ -831,7 +836,7 @@ def main():
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
                    "ms_long_recon": rms,
                    "batch_refine": args.batch_refine, "graphs": not args.no_graph,
-                   "parallelism": "single GPU"},
+                   "shift_floor": args.shift_floor or "auto", "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "phase_seconds": [round(v, 3) for v in last["phase_seconds"]],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],

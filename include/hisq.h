@@ -263,8 +263,9 @@ typedef struct {
                             multiple of grad_buffer); 0 = default */
     int use_graph;       /* 1: replay each block of iterations as a captured hipGraph */
     double shift_floor;  /* multi-shift: a shifted system stops updating once its iterated residual is below
-                            max(tol_i, shift_floor) (Sec. 3.2: "reach the limit of the sloppy precision");
-                            <= 0 selects the sloppy format's epsilon */
+                            max(tol_i, shift_floor) (Sec. 3.2: the shifts stop at the sloppy precision's
+                            limit); <= 0 selects that limit: none (tol_i alone) for triplets with FP64
+                            arithmetic, the spinor format's epsilon for FP32 arithmetic */
     int batch_refine;    /* multi-shift: refine the shifted systems together, one Dslash per iteration shared
                             by up to 16 of them (1), or one after another (0), the base refined first.
                             2: as 1, but the batch runs on a second library stream while a host thread refines

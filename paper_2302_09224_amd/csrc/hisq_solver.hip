@@ -893,7 +893,13 @@ extern "C" hisq_status hisq_multishift_cg_solve(double *const *x, const double *
         R.ds = E.ds;
         init_ctrl(h, q, tol[0], 0.0, ms_fmt.spinor);
         h->nshift = nshift;
-        const double fl = q.shift_floor > 0 ? q.shift_floor : std::ldexp(1.0, -sloppy_floor_bits(ms_fmt.spinor));
+        // where a shifted system's iterated residual stops tracking its true
+        // residual: with FP32 arithmetic near the storage format's epsilon;
+        // with FP64 arithmetic (INT30 or SX24/INT30 storage included) below
+        // any tolerance the FP64 reliable updates certify, so only tol_i stops it
+        const double fl = q.shift_floor > 0     ? q.shift_floor
+                          : ms_fmt.compute == 64 ? 0.0
+                                                 : std::ldexp(1.0, -sloppy_floor_bits(ms_fmt.spinor));
         h->floor2 = fl * fl;
         h->active_mask = 0;
         for (int i = 0; i < nshift; i++) {

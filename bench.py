@@ -538,6 +538,8 @@ def main():
     ap.add_argument("--shift-floor", type=float, default=0.0,
                     help="multi-shift: relative residual below which a shifted system stops (0: none with FP64 "
                          "arithmetic, the spinor format's epsilon with FP32 arithmetic)")
+    ap.add_argument("--grad-buffer", type=int, default=16,
+                    help="multi-shift solves: iterations per block of buffered updates (0: the library default, 8)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the 16^4 CG-stability table (not part of the timed step)")
@@ -695,6 +697,8 @@ def main():
             fat, lng, dims, f_ref.gauge, long_recon=args.recon)
         if args.no_graph:
             kw["use_graph"] = 0
+        if args.grad_buffer:
+            kw["grad_buffer"] = args.grad_buffer
         return hisq.multishift_cg_solve(b, shifts, tols, g64, gms, gref, args.mass, ms_fmt=ms, ref_fmt=ref, **kw)
 
     def step():
@@ -742,7 +746,7 @@ def main():
             config={"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "ms_triplet": repr(fms),
                     "refine_triplet": repr(fref), "ms_long_recon": ms_recon, "long_recon": args.recon,
                     "batch_refine": args.batch_refine, "graphs": not args.no_graph,
-                    "shift_floor": args.shift_floor or "auto"})))
+                    "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8})))
         return
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
@@ -836,7 +840,7 @@ def main():
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
                    "ms_long_recon": rms,
                    "batch_refine": args.batch_refine, "graphs": not args.no_graph,
-                   "shift_floor": args.shift_floor or "auto", "parallelism": "single GPU"},
+                   "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8, "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "phase_seconds": [round(v, 3) for v in last["phase_seconds"]],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],

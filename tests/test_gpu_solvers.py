@@ -200,6 +200,38 @@ def test_multishift_quantised_block_sizes(nb):
         assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8, (nb, i)
 
 
+def test_multishift_explicit_floor():
+    """An explicit stopping floor above the tolerance (the INT30 epsilon) ends
+    the multi-shift phase sooner and leaves more to the refinement; every
+    shift still reaches its tolerance and the oracle's solution. Without a
+    floor (FP64 arithmetic) the shifts stop at their tolerance in the
+    multi-shift phase itself."""
+    hisq = need_gpu()
+    dims, mass = (8, 8, 8, 8), 0.05
+    shifts = [1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0]
+    tol = [1e-10] * len(shifts)
+    fat, lng, ev, b = setup(dims, "near_unit")
+    pg = packed(hisq, fat, lng, dims, ["double", "int30", "int20"])
+    runs = {}
+    for floor in (0.0, 2.0 ** -29):
+        xs, st = hisq.multishift_cg_solve(torch.from_numpy(b).cuda(), shifts, tol, pg[0], pg[hisq.fmt("int30").gauge],
+                                          pg[hisq.fmt("int20").gauge], mass, ms_fmt="int30", ref_fmt="int20",
+                                          shift_floor=floor)
+        assert st["status"] == "HISQ_OK", (floor, st)
+        runs[floor] = (xs, st)
+    out = oracle.multishift_cg(fat.numpy(), lng.numpy(), full(dims, ev, b), dims, mass, shifts, 1e-12)
+    for floor, (xs, st) in runs.items():
+        for i, s in enumerate(shifts):
+            x = xs[i].cpu().numpy()
+            res = oracle.true_residual(fat.numpy(), lng.numpy(), full(dims, ev, x), full(dims, ev, b), dims, mass, s)
+            assert res <= tol[i] * (1 + 1e-6), (floor, i, res, st)
+            xo = out["x"][i][ev]
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8, (floor, i)
+    st0, st1 = runs[0.0][1], runs[2.0 ** -29][1]
+    assert st1["iters"] < st0["iters"], (st0["iters"], st1["iters"])
+    assert sum(st1["refine_iters"]) > sum(st0["refine_iters"]), (st0["refine_iters"], st1["refine_iters"])
+
+
 def test_multishift_per_shift_tolerances():
     """RHMC-like: every shift has its own target (Sec. 6.2 footnote)"""
     hisq = need_gpu()

@@ -540,6 +540,8 @@ def main():
                          "arithmetic, the spinor format's epsilon with FP32 arithmetic)")
     ap.add_argument("--grad-buffer", type=int, default=16,
                     help="multi-shift solves: iterations per block of buffered updates (0: the library default, 8)")
+    ap.add_argument("--ms-shape", type=str, default=None, metavar="STAGE,BLOCK,GRID,ORDER",
+                    help="pin the launch shape of the multi-shift operator instead of autotuning it")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stability", action="store_true",
                     help="skip the 16^4 CG-stability table (not part of the timed step)")
@@ -683,6 +685,10 @@ def main():
 
     # ---------------- the timed step ----------------
     ms_recon = args.ms_recon if hisq.fmt(args.ms).compute == 64 else args.recon   # eight parameters: FP64 only
+    if args.ms_shape:
+        stage, block, grid, order = (int(v) for v in args.ms_shape.split(","))
+        hisq.hisq_tune_set(args.ms, dims, 1, 1, 1, stage, block, grid, sweep=order, long_recon=ms_recon)
+        log(f"[bench] multi-shift operator pinned: stage {stage} block {block} grid {grid} order {order}")
 
     def solve_once(ms, ref, ms_long=None, **kw):
         """pack the links the solve needs (FP64 + its two triplets) and run it;
@@ -746,7 +752,8 @@ def main():
             config={"workload": f"multishift_cg_{'x'.join(map(str, dims))}", "ms_triplet": repr(fms),
                     "refine_triplet": repr(fref), "ms_long_recon": ms_recon, "long_recon": args.recon,
                     "batch_refine": args.batch_refine, "graphs": not args.no_graph,
-                    "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8})))
+                    "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8,
+                    "ms_shape": args.ms_shape or "tuned"})))
         return
     # packing: every packed field reads its FP64 source once and writes its storage
     def pack_field_bytes(gf, recon):
@@ -840,7 +847,8 @@ def main():
                    "ms_triplet": repr(fms), "refine_triplet": repr(fref), "long_recon": args.recon,
                    "ms_long_recon": rms,
                    "batch_refine": args.batch_refine, "graphs": not args.no_graph,
-                   "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8, "parallelism": "single GPU"},
+                   "shift_floor": args.shift_floor or "auto", "grad_buffer": args.grad_buffer or 8,
+                   "ms_shape": args.ms_shape or "tuned", "parallelism": "single GPU"},
         "multishift": {"mixed_seconds": round(ms_per_step / 1e3, 3), "ms_iters": last["iters"],
                        "phase_seconds": [round(v, 3) for v in last["phase_seconds"]],
                        "refine_iters": last["refine_iters"], "reliable_updates": last["reliable_updates"],

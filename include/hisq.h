@@ -503,7 +503,8 @@ void hisq_tune_clear(void);
  * otherwise); HISQ_EIO for a file that cannot be read or written, a
  * malformed line or a shape the kernels do not have (then nothing is loaded).
  * With the environment variable HISQ_TUNE_CACHE=<path>, the file is loaded at
- * the first shape lookup of the process (if it exists) and every shape the
+ * the first shape lookup of the process (if it exists; keys already fixed by
+ * hisq_tune_set or hisq_tune_load keep their shapes) and every shape the
  * autotuner chooses afterwards is appended to it, so later processes on the
  * same device and runtime do not tune again. */
 hisq_status hisq_tune_save(const char *path);

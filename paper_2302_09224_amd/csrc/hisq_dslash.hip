@@ -106,8 +106,10 @@ std::string tune_line(const std::string &tag, const TuneKey &k, const DslashTile
 }
 
 // Parse `path` into entries for device `tag` (g_tune_mu held by the caller when
-// `apply`).  Returns HISQ_EIO for an unreadable file or a malformed line.
-hisq_status read_tune_file(const char *path, const std::string &tag, bool apply, int *nloaded) {
+// `apply`); `replace`: a line replaces the table's entry of the same key, else
+// only keys without an entry are filled.  Returns HISQ_EIO for an unreadable
+// file or a malformed line.
+hisq_status read_tune_file(const char *path, const std::string &tag, bool apply, bool replace, int *nloaded) {
     FILE *fp = fopen(path, "r");
     if (!fp) return set_error(HISQ_EIO, "tune cache %s: cannot open", path);
     std::vector<std::pair<TuneKey, DslashTile>> got;
@@ -143,7 +145,12 @@ hisq_status read_tune_file(const char *path, const std::string &tag, bool apply,
     fclose(fp);
     if (st != HISQ_OK) return st;
     if (apply)
-        for (const auto &e : got) g_tuned[e.first] = std::make_pair(e.second, -1.f);
+        for (const auto &e : got) {
+            if (replace)
+                g_tuned[e.first] = std::make_pair(e.second, -1.f);
+            else
+                g_tuned.emplace(e.first, std::make_pair(e.second, -1.f));
+        }
     if (nloaded) *nloaded = (int)got.size();
     return HISQ_OK;
 }
@@ -165,7 +172,8 @@ void cache_read_once() {
     FILE *probe = fopen(path, "r");
     if (!probe) return;   // no file yet: it is created by the first append
     fclose(probe);
-    if (!tag.empty()) (void)read_tune_file(path, tag, true, nullptr);
+    // shapes fixed before the first lookup (hisq_tune_set, hisq_tune_load) stay
+    if (!tag.empty()) (void)read_tune_file(path, tag, true, false, nullptr);
 }
 
 void cache_append(const TuneKey &k, const DslashTile &t, float ms) {
@@ -474,7 +482,7 @@ extern "C" hisq_status hisq_tune_load(const char *path, int *nloaded) {
     const std::string tag = hisq::device_tag();
     if (tag.empty()) return hisq::set_error(HISQ_EHIP, "hisq_tune_load: no current HIP device");
     std::lock_guard<std::mutex> lk(hisq::g_tune_mu);
-    return hisq::read_tune_file(path, tag, true, nloaded);
+    return hisq::read_tune_file(path, tag, true, true, nloaded);
 }
 
 extern "C" size_t hisq_tune_report(char *buf, size_t len) {

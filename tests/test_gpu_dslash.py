@@ -192,6 +192,54 @@ def test_tune_cache_file_round_trip(tmp_path):
     hisq.hisq_tune_clear()
 
 
+_PIN_CHILD = """
+import sys, torch
+sys.path.insert(0, {root!r})
+from paper_2302_09224_amd import hisq, inputs
+dims = (8, 8, 8, 8)
+f = hisq.fmt("int20")
+if {pin}:
+    hisq.hisq_tune_set(f, dims, 1, 1, 1, 2, 256, 0, sweep=1)
+fat, lng = inputs.make_links(dims, "near_unit", inputs.GAUGE_SEED, device="cuda")
+pg = hisq.pack_gauge(fat, lng, dims, f.gauge)
+pin = hisq.pack_spinor(inputs.gaussian_spinor(2048, 5, device="cuda"), f.spinor)
+hisq.dslash(pin, pg, 0, f)
+torch.cuda.synchronize()
+print("REPORT " + hisq.hisq_tune_report().strip().replace(chr(10), " | "), flush=True)
+"""
+
+
+def test_tune_cache_keeps_pinned_shapes(tmp_path):
+    """HISQ_TUNE_CACHE is read at the first shape lookup of a process: it fills
+    the keys without a shape, and a shape fixed before (hisq_tune_set) stays.
+    Each case runs in a fresh process, since the file is read once per process."""
+    import os
+    import subprocess
+    import sys
+    hisq = need_gpu()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    dims = (8, 8, 8, 8)
+    f = hisq.fmt("int20")
+    cache = tmp_path / "tune.txt"
+    hisq.hisq_tune_clear()
+    try:
+        hisq.hisq_tune_set(f, dims, 1, 1, 1, 1, 128, 0, sweep=0)     # the file's shape: stage 1, block 128
+        hisq.hisq_tune_save(cache)
+    finally:
+        hisq.hisq_tune_clear()
+    env = dict(os.environ, HISQ_TUNE_CACHE=str(cache))
+    shapes = {}
+    for pin in (False, True):
+        print(f"child process, pinned {pin}", flush=True)
+        r = subprocess.run([sys.executable, "-c", _PIN_CHILD.format(root=root, pin=pin)], env=env,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        rep = [ln for ln in r.stdout.splitlines() if ln.startswith("REPORT ")][0]
+        shapes[pin] = rep
+    assert "stage 1 block 128 grid 0 sweep 0" in shapes[False], shapes[False]
+    assert "stage 2 block 256 grid 0 sweep 1" in shapes[True], shapes[True]
+
+
 @pytest.mark.parametrize("name", ["double", "single", "int30", "int20", "half", "int24", "sx24", "sx24_int30"])
 def test_normal_op(name):
     """(4m^2+s) p - D_eo D_oe p; the intermediate D_oe p is stored in the
